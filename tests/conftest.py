@@ -1,0 +1,44 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+    config.addinivalue_line("markers", "slow: longer CPU test")
+
+
+@pytest.fixture(scope="session")
+def oracle_lib():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+@pytest.fixture(scope="session")
+def geom_full(oracle_lib):
+    from paper_2103_14737_amd import workloads as W
+    return oracle_lib.Geometry(W.make_geometry())
+
+
+@pytest.fixture(scope="session")
+def geom_tiny(oracle_lib):
+    from paper_2103_14737_amd import workloads as W
+    return oracle_lib.Geometry(W.make_tiny_geometry())
+
+
+@pytest.fixture(scope="session")
+def param_full(oracle_lib):
+    from paper_2103_14737_amd import workloads as W
+    return oracle_lib.Param(W.make_param())
+
+
+@pytest.fixture(scope="session")
+def param_tiny(oracle_lib):
+    from paper_2103_14737_amd import workloads as W
+    return oracle_lib.Param(W.make_param(n_layers=3))
