@@ -1,0 +1,276 @@
+// Device arithmetic of the hit simulation: counter-based random numbers,
+// FP64 elementary functions for the per-(particle, layer) setup, the
+// samplers, and the FP32 per-hit placement and cell lookup.
+//
+// Every quantity that decides a hit count or a cell index is evaluated with
+// IEEE +, -, *, /, sqrt and floor only, in a fixed operation order and with
+// floating-point contraction disabled, so that the result is reproducible
+// bit for bit (the paper's Validation section traces its two CPU/GPU cell
+// mismatches in 62M hits to rounding differences).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fcsk {
+
+// ---------------------------------------------------------------- Philox ---
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two
+// 32x32->64 multiplies with a Weyl key schedule.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo_a = 0xD2511F53u * c0;
+        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t lo_b = 0xCD9E8D57u * c2;
+        const uint32_t y0 = hi_b ^ c1 ^ k0;
+        const uint32_t y2 = hi_a ^ c3 ^ k1;
+        c0 = y0;
+        c1 = lo_b;
+        c2 = y2;
+        c3 = lo_a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// Counter words: (draw index, layer | stream tag << 8, particle in event,
+// global event index).  Stream tags: 1 layer-energy Gamma, 2 hit-count
+// Poisson, 3 per-hit draws.
+enum : uint32_t { kTagGamma = 1u, kTagPoisson = 2u, kTagHit = 3u };
+
+// (0,1) uniform of a 32-bit word for the FP64 setup draws
+__device__ __forceinline__ double unit_open(uint32_t v) { return ((double)v + 0.5) * 0x1p-32; }
+// [0, 1 - 2^-24] uniform with an exact 24-bit conversion, per-hit draws
+__device__ __forceinline__ float unit24(uint32_t v) { return (float)(v >> 8) * 0x1p-24f; }
+
+// ------------------------------------------------- FP64 own functions ---
+constexpr double kLn2Hi = 6.93147180369123816490e-01;  // 32 trailing zero bits
+constexpr double kLn2Lo = 1.90821492927058770002e-10;
+constexpr double kInvLn2 = 1.44269504088896338700e+00;
+
+// log for finite normal x > 0: x = m 2^e with m in [sqrt(1/2), sqrt(2)),
+// log m = 2 atanh(s) with s = (m-1)/(m+1), odd series to s^21
+__device__ __noinline__ double dlog(double x)
+{
+    const long long bits = __double_as_longlong(x);
+    int e = (int)((bits >> 52) & 0x7ff) - 1022;
+    double m = __longlong_as_double((bits & 0x000fffffffffffffLL) | 0x3fe0000000000000LL);
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double q = 1.0 / 21.0;
+    q = q * z + 1.0 / 19.0;
+    q = q * z + 1.0 / 17.0;
+    q = q * z + 1.0 / 15.0;
+    q = q * z + 1.0 / 13.0;
+    q = q * z + 1.0 / 11.0;
+    q = q * z + 1.0 / 9.0;
+    q = q * z + 1.0 / 7.0;
+    q = q * z + 1.0 / 5.0;
+    q = q * z + 1.0 / 3.0;
+    q = q * z + 1.0;
+    const double ed = (double)e;
+    return ed * kLn2Hi + (ed * kLn2Lo + (2.0 * s) * q);
+}
+
+// exp: x = k ln2 + r, Taylor series of e^r to r^13, times 2^k
+__device__ __noinline__ double dexp(double x)
+{
+    if (x < -708.0) return 0.0;
+    if (x > 709.0) return __longlong_as_double(0x7ff0000000000000LL);
+    const double k = floor(x * kInvLn2 + 0.5);
+    const double r = (x - k * kLn2Hi) - k * kLn2Lo;
+    double q = 1.0 / 6227020800.0;
+    q = q * r + 1.0 / 479001600.0;
+    q = q * r + 1.0 / 39916800.0;
+    q = q * r + 1.0 / 3628800.0;
+    q = q * r + 1.0 / 362880.0;
+    q = q * r + 1.0 / 40320.0;
+    q = q * r + 1.0 / 5040.0;
+    q = q * r + 1.0 / 720.0;
+    q = q * r + 1.0 / 120.0;
+    q = q * r + 1.0 / 24.0;
+    q = q * r + 1.0 / 6.0;
+    q = q * r + 0.5;
+    q = q * r + 1.0;
+    q = q * r + 1.0;
+    const int ki = (int)k;
+    if (ki < -1000) {
+        const double sc = __longlong_as_double((long long)(ki + 1000 + 1023) << 52);
+        return (q * sc) * 0x1p-1000;
+    }
+    return q * __longlong_as_double((long long)(ki + 1023) << 52);
+}
+
+// cos(2 pi u), u in (0,1): exact quarter-turn reduction, then a Taylor
+// series of cos (to t^16) or sin (to t^17) on |t| <= pi/4
+__device__ __noinline__ double dcos_turns(double u)
+{
+    const double qt = floor(4.0 * u + 0.5);
+    const double f = u - 0.25 * qt;
+    const double t = f * 6.28318530717958647692;
+    const double z = t * t;
+    const int quad = ((int)qt) & 3;
+    if ((quad & 1) == 0) {
+        double c = 1.0 / 20922789888000.0;
+        c = c * z - 1.0 / 87178291200.0;
+        c = c * z + 1.0 / 479001600.0;
+        c = c * z - 1.0 / 3628800.0;
+        c = c * z + 1.0 / 40320.0;
+        c = c * z - 1.0 / 720.0;
+        c = c * z + 1.0 / 24.0;
+        c = c * z - 0.5;
+        c = c * z + 1.0;
+        return quad == 0 ? c : -c;
+    }
+    double s = 1.0 / 355687428096000.0;
+    s = s * z - 1.0 / 1307674368000.0;
+    s = s * z + 1.0 / 6227020800.0;
+    s = s * z - 1.0 / 39916800.0;
+    s = s * z + 1.0 / 362880.0;
+    s = s * z - 1.0 / 5040.0;
+    s = s * z + 1.0 / 120.0;
+    s = s * z - 1.0 / 6.0;
+    s = s * z + 1.0;
+    s = t * s;
+    return quad == 1 ? -s : s;
+}
+
+// log(k!): exact factorial below 10, Stirling series (to 1/(1260 x^5))
+__device__ __noinline__ double dlnfact(long long k)
+{
+    if (k < 10) {
+        double f = 1.0;
+        for (long long j = 2; j <= k; ++j) f = f * (double)j;
+        return dlog(f);
+    }
+    const double x = (double)k + 1.0;
+    const double ix = 1.0 / x;
+    const double ix2 = ix * ix;
+    const double corr = ix * (1.0 / 12.0 - ix2 * (1.0 / 360.0 - ix2 * (1.0 / 1260.0)));
+    return (((x - 0.5) * dlog(x)) - x) + 0.91893853320467274178 + corr;
+}
+
+// ------------------------------------------------------------ samplers ---
+// Gamma(alpha, 1): Marsaglia-Tsang squeeze on a Box-Muller normal; for
+// alpha < 1 the draw for alpha + 1 is scaled by u^(1/alpha).
+// Attempt j uses counter (j, layer | 1 << 8, particle, event).
+__device__ __noinline__ double gamma_draw(double alpha, uint32_t k0, uint32_t k1, uint32_t layer,
+                                          uint32_t part, uint32_t ev)
+{
+    const double a = alpha < 1.0 ? alpha + 1.0 : alpha;
+    const double d = a - 1.0 / 3.0;
+    const double c = 1.0 / sqrt(9.0 * d);
+    for (uint32_t j = 0; j < 64; ++j) {
+        const U4 x = philox4x32_10(j, layer | (kTagGamma << 8), part, ev, k0, k1);
+        const double z = sqrt(-2.0 * dlog(unit_open(x.x))) * dcos_turns(unit_open(x.y));
+        const double t = 1.0 + c * z;
+        if (!(t > 0.0)) continue;
+        const double v = (t * t) * t;
+        const double lhs = dlog(unit_open(x.z));
+        const double rhs = ((((0.5 * z) * z) + d) - d * v) + d * dlog(v);
+        if (lhs < rhs) {
+            double g = d * v;
+            if (alpha < 1.0) g = g * dexp(dlog(unit_open(x.w)) / alpha);
+            return g;
+        }
+    }
+    return d;
+}
+
+// Poisson(mu): sequential inversion below mu = 10, transformed rejection
+// (PTRS, Hoermann 1993) above with two attempts per Philox call.
+// Call j uses counter (j, layer | 2 << 8, particle, event).
+__device__ __noinline__ long long poisson_draw(double mu, uint32_t k0, uint32_t k1, uint32_t layer,
+                                               uint32_t part, uint32_t ev)
+{
+    if (mu < 10.0) {
+        const U4 x = philox4x32_10(0u, layer | (kTagPoisson << 8), part, ev, k0, k1);
+        const double u = unit_open(x.x);
+        double pk = dexp(-mu);
+        double cdf = pk;
+        long long k = 0;
+        while (u > cdf && k < 200) {
+            k = k + 1;
+            pk = (pk * mu) / (double)k;
+            cdf = cdf + pk;
+        }
+        return k;
+    }
+    const double slam = sqrt(mu);
+    const double loglam = dlog(mu);
+    const double b = 0.931 + 2.53 * slam;
+    const double a = -0.059 + 0.02483 * b;
+    const double invalpha = 1.1239 + 1.1328 / (b - 3.4);
+    const double vr = 0.9277 - 3.6224 / (b - 2.0);
+    for (uint32_t j = 0; j < 32; ++j) {
+        const U4 x = philox4x32_10(j, layer | (kTagPoisson << 8), part, ev, k0, k1);
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t wu = h == 0 ? x.x : x.z;
+            const uint32_t wv = h == 0 ? x.y : x.w;
+            const double U = unit_open(wu) - 0.5;
+            const double V = unit_open(wv);
+            const double us = 0.5 - fabs(U);
+            const double kd = floor((((2.0 * a) / us + b) * U + mu) + 0.43);
+            if (us >= 0.07 && V <= vr) return (long long)kd;
+            if (kd < 0.0 || (us < 0.013 && V > us)) continue;
+            const double lhs = (dlog(V) + dlog(invalpha)) - dlog(a / (us * us) + b);
+            const double rhs = (-mu + kd * loglam) - dlnfact((long long)kd);
+            if (lhs <= rhs) return (long long)kd;
+        }
+    }
+    return (long long)floor(mu);
+}
+
+// ------------------------------------------------ per-hit FP32 placement ---
+// (cos, sin) of alpha = (ia + u) pi/4: even bins rotate forward from a
+// multiple of pi/2 by d = u pi/4, odd bins back from the next multiple by
+// d = (1-u) pi/4; the short polynomials below cover d in [0, pi/4].
+__device__ __forceinline__ void sincos_bin(int ia, float u, float& cs, float& sn)
+{
+    const float quarter_pi = (float)(0.78539816339744830962);
+    const bool even = (ia & 1) == 0;
+    const float d = even ? u * quarter_pi : (1.0f - u) * quarter_pi;
+    const int m = even ? (ia >> 1) : ((ia + 1) >> 1);
+    const float d2 = d * d;
+    float sp = (float)(1.0 / 362880.0);
+    sp = sp * d2 + (float)(-1.0 / 5040.0);
+    sp = sp * d2 + (float)(1.0 / 120.0);
+    sp = sp * d2 + (float)(-1.0 / 6.0);
+    sp = sp * d2 + 1.0f;
+    const float s0 = d * sp;
+    float cp = (float)(-1.0 / 3628800.0);
+    cp = cp * d2 + (float)(1.0 / 40320.0);
+    cp = cp * d2 + (float)(-1.0 / 720.0);
+    cp = cp * d2 + (float)(1.0 / 24.0);
+    cp = cp * d2 + (float)(-0.5);
+    cp = cp * d2 + 1.0f;
+    const float c0 = cp;
+    // quadrant table: even bins  m=0:(c,s) 1:(-s,c) 2:(-c,-s) 3:(s,-c)
+    //                 odd bins   m=1:(s,c) 2:(-c,s) 3:(-s,-c) 4:(c,-s)
+    const int q = m & 3;
+    float c, s;
+    if (even) {
+        c = (q == 0) ? c0 : (q == 1) ? -s0 : (q == 2) ? -c0 : s0;
+        s = (q == 0) ? s0 : (q == 1) ? c0 : (q == 2) ? -s0 : -c0;
+    } else {
+        c = (q == 1) ? s0 : (q == 2) ? -c0 : (q == 3) ? -s0 : c0;
+        s = (q == 1) ? c0 : (q == 2) ? s0 : (q == 3) ? -c0 : -s0;
+    }
+    cs = c;
+    sn = s;
+}
+
+}  // namespace fcsk

@@ -1,0 +1,1056 @@
+// Host runtime of the C ABI declared in include/fcs.h: context, validated
+// uploads of the flattened geometry and parametrization, workspace, the
+// launch sequence of one batch (optionally captured in a hipGraph), the
+// per-event launch loop, and the adjoint.
+//
+// One translation unit holds the whole library (no relocatable device code).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "fcs.h"
+#include "fcs_kernels.hpp"
+
+using fcsk::Counters;
+using fcsk::Params;
+
+namespace {
+
+std::string g_create_error = "no error";
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct GraphKey {
+    long long n_particles, n_events;
+    int dense, validate, grid;
+    bool operator<(const GraphKey& o) const
+    {
+        return std::tie(n_particles, n_events, dense, validate, grid) <
+               std::tie(o.n_particles, o.n_events, o.dense, o.validate, o.grid);
+    }
+};
+
+}  // namespace
+
+struct fcs_ctx {
+    int device = 0;
+    bool dry = false;  // FCS_DEVICE_NONE: argument checks only
+    int n_cu = 0;
+    char name[64] = {0};
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_in = nullptr;
+    std::string err = "no error";
+    long long held = 0;
+
+    // geometry
+    bool has_geom = false;
+    long long n_cells = 0;
+    int n_layers = 0, n_regions = 0;
+    DevBuf g_eta_lo, g_eta_hi, g_inv_deta, g_inv_dphi, g_phi_lo, g_neta, g_nphi, g_offset,
+        g_inv_r, g_cell_id;
+
+    // parametrization
+    bool has_param = false;
+    int n_types = 0, n_ebins = 0, n_etabins = 0;
+    float r_max = 0.f;
+    long long n_hist = 0;
+    DevBuf p_e_edges, p_eta_edges, p_alpha, p_weights, p_cum, p_guide;
+
+    // workspace
+    DevBuf w_particles, w_evoff, w_override, w_task_n, w_task_ehit, w_part_ev, w_part_p,
+        w_part_set, w_blk_sums, w_blk_offs, w_task_hoff, w_chunks, w_small_key, w_small_off,
+        w_tile_first, w_cells, w_flags, w_seg_cnt, w_seg_off, w_seg_blk, w_ctr, w_params,
+        w_acc_el, w_acc_bins;
+    long long cells_events = 0;  // events the accumulator holds (kept zero)
+    long long flag_events = 0;
+    long long chunk_cap = 0;
+    // staging of host outputs
+    DevBuf o_cells, o_ids, o_e, o_evoff, o_heta, o_hphi, o_he, o_hcell, o_thoff, o_counts,
+        o_elayer;
+
+    Params* h_params = nullptr;  // pinned
+    Counters* h_ctr = nullptr;   // pinned
+    std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+int fail(fcs_ctx* c, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else g_create_error = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, FCS_E_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                 \
+    } while (0)
+
+void release(fcs_ctx* c, DevBuf& b)
+{
+    if (b.p) {
+        (void)hipFree(b.p);
+        c->held -= (long long)b.bytes;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+// grow-only device buffer; contents are not preserved
+int ensure(fcs_ctx* c, DevBuf& b, size_t bytes, bool* grown = nullptr)
+{
+    if (grown) *grown = false;
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return FCS_OK;
+    release(c, b);
+    size_t want = bytes + bytes / 8;
+    want = (want + 255) & ~(size_t)255;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(c, FCS_E_NOMEM, "device allocation of %zu bytes failed", want);
+    }
+    b.bytes = want;
+    c->held += (long long)want;
+    if (grown) *grown = true;
+    return FCS_OK;
+}
+
+template <typename T>
+int upload(fcs_ctx* c, DevBuf& b, const T* src, size_t n)
+{
+    int rc = ensure(c, b, n * sizeof(T));
+    if (rc) return rc;
+    if (n) HIPCHK(c, hipMemcpy(b.p, src, n * sizeof(T), hipMemcpyHostToDevice));
+    return FCS_OK;
+}
+
+unsigned grid_for(long long n, int block) { return (unsigned)((n + block - 1) / block); }
+
+void drop_graphs(fcs_ctx* c)
+{
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
+
+}  // namespace
+
+// ========================================================================
+extern "C" {
+
+void fcs_default_options(fcs_sim_options* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->mode = FCS_MODE_BATCHED;
+    o->outputs = FCS_OUT_COMPACT;
+    o->hit_energy_scale_mev = 100.0f;
+    o->nhit_cap = 20000;
+    o->min_layer_energy_mev = 1e-6;
+    o->use_graph = 1;
+}
+
+const char* fcs_last_error(const fcs_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int fcs_create(fcs_ctx** out, int device)
+{
+    if (!out) return fail(nullptr, FCS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (device == FCS_DEVICE_NONE) {
+        fcs_ctx* c = new fcs_ctx();
+        c->dry = true;
+        c->device = FCS_DEVICE_NONE;
+        std::snprintf(c->name, sizeof c->name, "none");
+        *out = c;
+        return FCS_OK;
+    }
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return fail(nullptr, FCS_E_NO_DEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= n)
+        return fail(nullptr, FCS_E_NO_DEVICE, "device %d out of range [0, %d)", device, n);
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, FCS_E_HIP, "hipSetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return fail(nullptr, FCS_E_HIP, "hipGetDeviceProperties failed");
+    if (prop.warpSize != 64)
+        return fail(nullptr, FCS_E_NO_DEVICE, "device %d is not a wave64 device", device);
+    fcs_ctx* c = new fcs_ctx();
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount;
+    std::snprintf(c->name, sizeof c->name, "%s", prop.gcnArchName);
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_params, sizeof(Params)) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_ctr, sizeof(Counters)) != hipSuccess) {
+        fcs_destroy(c);
+        return fail(nullptr, FCS_E_HIP, "stream/event/pinned allocation failed");
+    }
+    if (ensure(c, c->w_params, sizeof(Params)) || ensure(c, c->w_ctr, sizeof(Counters))) {
+        fcs_destroy(c);
+        return fail(nullptr, FCS_E_NOMEM, "device allocation failed");
+    }
+    *out = c;
+    return FCS_OK;
+}
+
+void fcs_destroy(fcs_ctx* c)
+{
+    if (!c) return;
+    if (c->dry) {
+        delete c;
+        return;
+    }
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    DevBuf* bufs[] = {&c->g_eta_lo, &c->g_eta_hi, &c->g_inv_deta, &c->g_inv_dphi, &c->g_phi_lo,
+                      &c->g_neta, &c->g_nphi, &c->g_offset, &c->g_inv_r, &c->g_cell_id,
+                      &c->p_e_edges, &c->p_eta_edges, &c->p_alpha, &c->p_weights, &c->p_cum,
+                      &c->p_guide, &c->w_particles, &c->w_evoff, &c->w_override, &c->w_task_n,
+                      &c->w_task_ehit, &c->w_part_ev, &c->w_part_p, &c->w_part_set,
+                      &c->w_blk_sums, &c->w_blk_offs, &c->w_task_hoff, &c->w_chunks,
+                      &c->w_small_key, &c->w_small_off, &c->w_tile_first, &c->w_cells,
+                      &c->w_flags, &c->w_seg_cnt, &c->w_seg_off, &c->w_seg_blk, &c->w_ctr,
+                      &c->w_params, &c->w_acc_el, &c->w_acc_bins, &c->o_cells, &c->o_ids,
+                      &c->o_e, &c->o_evoff, &c->o_heta, &c->o_hphi, &c->o_he, &c->o_hcell,
+                      &c->o_thoff, &c->o_counts, &c->o_elayer};
+    for (DevBuf* b : bufs) release(c, *b);
+    if (c->h_params) (void)hipHostFree(c->h_params);
+    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+    if (c->ev_start) (void)hipEventDestroy(c->ev_start);
+    if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int fcs_get_info(const fcs_ctx* c, fcs_info* info)
+{
+    if (!c || !info) return FCS_E_INVALID_ARG;
+    std::memset(info, 0, sizeof *info);
+    std::snprintf(info->device_name, sizeof info->device_name, "%s", c->name);
+    info->compute_units = c->n_cu;
+    info->device = c->device;
+    info->n_cells = c->has_geom ? c->n_cells : 0;
+    info->n_layers = c->has_geom ? c->n_layers : 0;
+    info->n_regions = c->has_geom ? c->n_regions : 0;
+    info->n_histograms = c->has_param ? c->n_hist : 0;
+    info->device_bytes = c->held;
+    return FCS_OK;
+}
+
+// ------------------------------------------------------------ geometry ---
+int fcs_load_geometry(fcs_ctx* c, const fcs_geometry* g)
+{
+    if (!c) return FCS_E_INVALID_ARG;
+    if (!g) return fail(c, FCS_E_INVALID_ARG, "geometry is NULL");
+    if (g->n_layers < 1 || g->n_layers > 64)
+        return fail(c, FCS_E_INVALID_ARG, "n_layers = %d outside [1, 64]", g->n_layers);
+    if (g->n_regions < 1 || g->n_regions > 8)
+        return fail(c, FCS_E_INVALID_ARG, "n_regions = %d outside [1, 8]", g->n_regions);
+    if (g->n_cells < 1 || g->n_cells > (1LL << 30))
+        return fail(c, FCS_E_INVALID_ARG, "n_cells = %lld outside [1, 2^30]", (long long)g->n_cells);
+    const void* ptrs[] = {g->cell_id, g->reg_eta_lo, g->reg_eta_hi, g->reg_inv_deta,
+                          g->reg_inv_dphi, g->reg_phi_lo, g->reg_neta, g->reg_nphi,
+                          g->reg_offset, g->layer_inv_r};
+    const char* names[] = {"cell_id", "reg_eta_lo", "reg_eta_hi", "reg_inv_deta", "reg_inv_dphi",
+                           "reg_phi_lo", "reg_neta", "reg_nphi", "reg_offset", "layer_inv_r"};
+    for (int i = 0; i < 10; ++i)
+        if (!ptrs[i]) return fail(c, FCS_E_INVALID_ARG, "geometry field %s is NULL", names[i]);
+    const int L = g->n_layers, R = g->n_regions;
+    long long run = 0;
+    for (int l = 0; l < L; ++l) {
+        if (!finite_pos(g->layer_inv_r[l]))
+            return fail(c, FCS_E_INVALID_ARG, "layer_inv_r[%d] not finite and positive", l);
+        for (int k = 0; k < R; ++k) {
+            const int r = l * R + k;
+            if (!std::isfinite(g->reg_eta_lo[r]) || !std::isfinite(g->reg_eta_hi[r]) ||
+                !(g->reg_eta_lo[r] < g->reg_eta_hi[r]))
+                return fail(c, FCS_E_INVALID_ARG, "reg_eta_lo/hi[%d] not an increasing range", r);
+            if (k > 0 && g->reg_eta_lo[r] != g->reg_eta_hi[r - 1])
+                return fail(c, FCS_E_INVALID_ARG, "region %d does not start where region %d ends",
+                            r, r - 1);
+            if (!finite_pos(g->reg_inv_deta[r]) || !finite_pos(g->reg_inv_dphi[r]) ||
+                !std::isfinite(g->reg_phi_lo[r]))
+                return fail(c, FCS_E_INVALID_ARG, "reg_inv_deta/inv_dphi/phi_lo[%d] invalid", r);
+            if (g->reg_neta[r] < 1 || g->reg_nphi[r] < 1 || g->reg_neta[r] > 65535 ||
+                g->reg_nphi[r] > 65535)
+                return fail(c, FCS_E_INVALID_ARG, "reg_neta/nphi[%d] outside [1, 65535]", r);
+            if (g->reg_offset[r] != run)
+                return fail(c, FCS_E_INVALID_ARG, "reg_offset[%d] = %d, expected %lld", r,
+                            g->reg_offset[r], run);
+            run += (long long)g->reg_neta[r] * g->reg_nphi[r];
+        }
+    }
+    if (run != g->n_cells)
+        return fail(c, FCS_E_INVALID_ARG, "n_cells = %lld but regions hold %lld cells",
+                    (long long)g->n_cells, run);
+    if (c->dry) {
+        c->n_cells = g->n_cells;
+        c->n_layers = L;
+        c->n_regions = R;
+        c->has_geom = true;
+        return FCS_OK;
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const size_t nr = (size_t)L * R;
+    int rc = 0;
+    if ((rc = upload(c, c->g_eta_lo, g->reg_eta_lo, nr)) || (rc = upload(c, c->g_eta_hi, g->reg_eta_hi, nr)) ||
+        (rc = upload(c, c->g_inv_deta, g->reg_inv_deta, nr)) ||
+        (rc = upload(c, c->g_inv_dphi, g->reg_inv_dphi, nr)) ||
+        (rc = upload(c, c->g_phi_lo, g->reg_phi_lo, nr)) || (rc = upload(c, c->g_neta, g->reg_neta, nr)) ||
+        (rc = upload(c, c->g_nphi, g->reg_nphi, nr)) || (rc = upload(c, c->g_offset, g->reg_offset, nr)) ||
+        (rc = upload(c, c->g_inv_r, g->layer_inv_r, (size_t)L)) ||
+        (rc = upload(c, c->g_cell_id, g->cell_id, (size_t)g->n_cells)))
+        return rc;
+    const bool changed = !c->has_geom || c->n_cells != g->n_cells;
+    c->n_cells = g->n_cells;
+    c->n_layers = L;
+    c->n_regions = R;
+    c->has_geom = true;
+    if (changed) {
+        // accumulator layout depends on the cell count: start it over
+        release(c, c->w_cells);
+        release(c, c->w_flags);
+        c->cells_events = 0;
+        c->flag_events = 0;
+        drop_graphs(c);
+    }
+    if (c->has_param && c->n_layers != L) c->has_param = false;
+    return FCS_OK;
+}
+
+// ------------------------------------------------------ parametrization ---
+int fcs_load_parametrization(fcs_ctx* c, const fcs_param* p)
+{
+    if (!c) return FCS_E_INVALID_ARG;
+    if (!p) return fail(c, FCS_E_INVALID_ARG, "param is NULL");
+    if (!c->has_geom) return fail(c, FCS_E_NOT_LOADED, "load the geometry first");
+    if (p->n_types != 3) return fail(c, FCS_E_INVALID_ARG, "n_types = %d, must be 3", p->n_types);
+    if (p->n_ebins < 1 || p->n_ebins > 64 || p->n_etabins < 1 || p->n_etabins > 64)
+        return fail(c, FCS_E_INVALID_ARG, "n_ebins / n_etabins outside [1, 64]");
+    if (p->n_layers != c->n_layers)
+        return fail(c, FCS_E_INVALID_ARG, "n_layers = %d but the geometry has %d", p->n_layers,
+                    c->n_layers);
+    if (p->n_rbins != 32 || p->n_abins != 8)
+        return fail(c, FCS_E_INVALID_ARG, "histograms must be 32 (r) x 8 (alpha) bins");
+    if (!finite_pos(p->r_max_mm)) return fail(c, FCS_E_INVALID_ARG, "r_max_mm not finite and positive");
+    if (!p->e_edges || !p->eta_edges || !p->dirichlet_alpha || !p->weights)
+        return fail(c, FCS_E_INVALID_ARG, "e_edges, eta_edges, dirichlet_alpha and weights are required");
+    for (int k = 0; k <= p->n_ebins; ++k)
+        if (!std::isfinite(p->e_edges[k]) || (k > 0 && !(p->e_edges[k] > p->e_edges[k - 1])))
+            return fail(c, FCS_E_INVALID_ARG, "e_edges not finite and increasing at %d", k);
+    for (int k = 0; k <= p->n_etabins; ++k)
+        if (!std::isfinite(p->eta_edges[k]) || (k > 0 && !(p->eta_edges[k] > p->eta_edges[k - 1])))
+            return fail(c, FCS_E_INVALID_ARG, "eta_edges not finite and increasing at %d", k);
+    const int L = p->n_layers;
+    for (int i = 0; i < 3 * L; ++i)
+        if (!finite_pos(p->dirichlet_alpha[i]))
+            return fail(c, FCS_E_INVALID_ARG, "dirichlet_alpha[%d] not finite and positive", i);
+    const long long n_sets = 3LL * p->n_ebins * p->n_etabins;
+    const long long n_hist = n_sets * L;
+    for (long long h = 0; h < n_hist; ++h) {
+        double tot = 0.0;
+        for (int b = 0; b < 256; ++b) {
+            const float w = p->weights[h * 256 + b];
+            if (!(w >= 0.f) || !std::isfinite(w))
+                return fail(c, FCS_E_INVALID_ARG, "weights[%lld] negative or not finite", h * 256 + b);
+            tot += w;
+        }
+        if (!(tot > 0.0)) return fail(c, FCS_E_INVALID_ARG, "histogram %lld has no weight", h);
+    }
+    if (c->dry) {
+        c->n_types = p->n_types;
+        c->n_ebins = p->n_ebins;
+        c->n_etabins = p->n_etabins;
+        c->r_max = p->r_max_mm;
+        c->n_hist = n_hist;
+        c->has_param = true;
+        return FCS_OK;
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int rc = 0;
+    if ((rc = upload(c, c->p_e_edges, p->e_edges, (size_t)p->n_ebins + 1)) ||
+        (rc = upload(c, c->p_eta_edges, p->eta_edges, (size_t)p->n_etabins + 1)) ||
+        (rc = upload(c, c->p_alpha, p->dirichlet_alpha, (size_t)3 * L)) ||
+        (rc = upload(c, c->p_weights, p->weights, (size_t)n_hist * 256)) ||
+        (rc = ensure(c, c->p_cum, (size_t)n_hist * 256 * sizeof(float))) ||
+        (rc = ensure(c, c->p_guide, (size_t)n_hist * 256)))
+        return rc;
+    hipLaunchKernelGGL(fcsk::k_build_cum, dim3(grid_for(n_hist, 64)), dim3(64), 0, c->stream,
+                       (const float*)c->p_weights.p, (float*)c->p_cum.p, n_hist);
+    hipLaunchKernelGGL(fcsk::k_build_guide, dim3(grid_for(n_hist * 256, 256)), dim3(256), 0,
+                       c->stream, (const float*)c->p_cum.p, (uint8_t*)c->p_guide.p, n_hist);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->n_types = p->n_types;
+    c->n_ebins = p->n_ebins;
+    c->n_etabins = p->n_etabins;
+    c->r_max = p->r_max_mm;
+    c->n_hist = n_hist;
+    c->has_param = true;
+    return FCS_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ batch ===
+namespace {
+
+struct Shape {
+    long long n_particles, part_base, n_events, ev0;
+    long long hit_base, out_base;
+};
+
+struct Tuning {
+    int chunk, big, tile, wg_per_cu;
+};
+
+int check_tuning(fcs_ctx* c, const fcs_sim_options* o, Tuning* t)
+{
+    t->chunk = o->chunk_hits ? o->chunk_hits : 2048;
+    t->big = o->big_task_hits ? o->big_task_hits : 128;
+    t->tile = o->tile_hits ? o->tile_hits : 2048;
+    t->wg_per_cu = o->wg_per_cu ? o->wg_per_cu : 4;
+    if (t->chunk < 1 || t->chunk > (1 << 20))
+        return fail(c, FCS_E_INVALID_ARG, "chunk_hits = %d outside [1, 2^20]", t->chunk);
+    if (t->tile < fcsk::kBlock || t->tile > fcsk::kTileMax || t->tile % fcsk::kBlock)
+        return fail(c, FCS_E_INVALID_ARG, "tile_hits = %d must be a multiple of 256 in [256, %d]",
+                    t->tile, fcsk::kTileMax);
+    if (t->big < 1 || t->big > t->tile)
+        return fail(c, FCS_E_INVALID_ARG, "big_task_hits = %d outside [1, tile_hits]", t->big);
+    if (t->wg_per_cu < 1 || t->wg_per_cu > 32)
+        return fail(c, FCS_E_INVALID_ARG, "wg_per_cu = %d outside [1, 32]", t->wg_per_cu);
+    return FCS_OK;
+}
+
+// Fill the Params block for one launch sequence over a range of events.
+// `dense_out` (device) is the caller's dense cell buffer or NULL.
+int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
+            const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
+            float* dense_out, const fcs_sim_output* dout, bool want_hits, Params* P)
+{
+    const int L = c->n_layers;
+    const long long N = sh.n_particles;
+    const long long nt = N * L;
+    const long long E = sh.n_events;
+    const int n_blk = (int)((c->n_cells + 63) / 64);
+    const int n_seg = (n_blk + 63) / 64;
+    const long long nsb = (nt + fcsk::kScanBlock - 1) / fcsk::kScanBlock;
+    const long long nseg = E * n_seg;
+    const long long nsegb = (nseg + fcsk::kScanBlock - 1) / fcsk::kScanBlock;
+    if (c->chunk_cap < nt + 1024) c->chunk_cap = nt + 1024;
+    int rc = 0;
+    if ((rc = ensure(c, c->w_task_n, nt * 4)) || (rc = ensure(c, c->w_task_ehit, nt * 4)) ||
+        (rc = ensure(c, c->w_part_ev, N * 4)) || (rc = ensure(c, c->w_part_p, N * 4)) ||
+        (rc = ensure(c, c->w_part_set, N * 4)) || (rc = ensure(c, c->w_blk_sums, nsb * 16)) ||
+        (rc = ensure(c, c->w_blk_offs, nsb * 16)) ||
+        (rc = ensure(c, c->w_task_hoff, want_hits ? nt * 4 : 4)) ||
+        (rc = ensure(c, c->w_chunks, (size_t)c->chunk_cap * 16)) ||
+        (rc = ensure(c, c->w_small_key, nt * 4)) || (rc = ensure(c, c->w_small_off, nt * 4)) ||
+        (rc = ensure(c, c->w_tile_first, (nt + 1) * 4)) ||
+        (rc = ensure(c, c->w_seg_cnt, nseg * 4)) || (rc = ensure(c, c->w_seg_off, nseg * 4)) ||
+        (rc = ensure(c, c->w_seg_blk, nsegb * 4)))
+        return rc;
+    // flags and the private accumulator are kept zero between calls
+    if (c->flag_events < E) {
+        bool grown = false;
+        if ((rc = ensure(c, c->w_flags, (size_t)E * n_blk, &grown))) return rc;
+        hipLaunchKernelGGL(fcsk::k_fill_u8, dim3(1024), dim3(256), 0, c->stream,
+                           (uint8_t*)c->w_flags.p, (long long)(c->w_flags.bytes));
+        c->flag_events = (long long)(c->w_flags.bytes / (size_t)n_blk);
+    }
+    if (!dense_out && c->cells_events < E) {
+        if ((rc = ensure(c, c->w_cells, (size_t)E * c->n_cells * 4))) return rc;
+        hipLaunchKernelGGL(fcsk::k_fill_u32, dim3(4096), dim3(256), 0, c->stream,
+                           (uint32_t*)c->w_cells.p, (long long)(c->w_cells.bytes / 4), 0u);
+        c->cells_events = (long long)(c->w_cells.bytes / 4 / (size_t)c->n_cells);
+    }
+    HIPCHK(c, hipGetLastError());
+
+    std::memset(P, 0, sizeof *P);
+    P->n_cells = c->n_cells;
+    P->n_layers = L;
+    P->n_regions = c->n_regions;
+    P->n_blk = n_blk;
+    P->n_seg = n_seg;
+    P->reg_eta_lo = (const float*)c->g_eta_lo.p;
+    P->reg_eta_hi = (const float*)c->g_eta_hi.p;
+    P->reg_inv_deta = (const float*)c->g_inv_deta.p;
+    P->reg_inv_dphi = (const float*)c->g_inv_dphi.p;
+    P->reg_phi_lo = (const float*)c->g_phi_lo.p;
+    P->reg_neta = (const int32_t*)c->g_neta.p;
+    P->reg_nphi = (const int32_t*)c->g_nphi.p;
+    P->reg_offset = (const int32_t*)c->g_offset.p;
+    P->layer_inv_r = (const float*)c->g_inv_r.p;
+    P->cell_id = (const long long*)c->g_cell_id.p;
+    P->n_types = c->n_types;
+    P->n_ebins = c->n_ebins;
+    P->n_etabins = c->n_etabins;
+    P->r_max = c->r_max;
+    P->e_edges = (const float*)c->p_e_edges.p;
+    P->eta_edges = (const float*)c->p_eta_edges.p;
+    P->alpha = (const float*)c->p_alpha.p;
+    P->cum = (const float*)c->p_cum.p;
+    P->guide = (const uint8_t*)c->p_guide.p;
+    P->weights = (const float*)c->p_weights.p;
+    P->n_hist = c->n_hist;
+    P->key0 = (uint32_t)(o->seed & 0xffffffffu);
+    P->key1 = (uint32_t)(o->seed >> 32);
+    P->ev_base = o->event_index_base + (unsigned long long)sh.ev0;
+    P->n_particles = N;
+    P->part_base = sh.part_base;
+    P->n_events = E;
+    P->n_tasks = nt;
+    P->particles = d_particles;
+    P->ev_off = d_evoff;
+    P->elayer_override = d_override;
+    P->scale = o->hit_energy_scale_mev;
+    P->cap = o->nhit_cap;
+    P->min_e = o->min_layer_energy_mev;
+    P->chunk_hits = tu.chunk;
+    P->big_thr = tu.big;
+    P->tile_hits = tu.tile;
+    P->want_hits = want_hits ? 1 : 0;
+    P->clean_cells = dense_out ? 0 : 1;
+    P->chunk_cap = (int)std::min<long long>(c->chunk_cap, 2147483647LL);
+    P->n_scan_blocks = (int)nsb;
+    P->n_seg_blocks = (int)nsegb;
+    P->task_n = (int32_t*)c->w_task_n.p;
+    P->task_ehit = (float*)c->w_task_ehit.p;
+    P->part_ev = (int32_t*)c->w_part_ev.p;
+    P->part_p = (uint32_t*)c->w_part_p.p;
+    P->part_set = (int32_t*)c->w_part_set.p;
+    P->blk_sums = (int32_t*)c->w_blk_sums.p;
+    P->blk_offs = (int32_t*)c->w_blk_offs.p;
+    P->task_hoff = (int32_t*)c->w_task_hoff.p;
+    P->chunks = (int4*)c->w_chunks.p;
+    P->small_key = (int32_t*)c->w_small_key.p;
+    P->small_off = (int32_t*)c->w_small_off.p;
+    P->tile_first = (int32_t*)c->w_tile_first.p;
+    P->cells = dense_out ? dense_out : (float*)c->w_cells.p;
+    P->flags = (uint8_t*)c->w_flags.p;
+    P->seg_cnt = (int32_t*)c->w_seg_cnt.p;
+    P->seg_off = (int32_t*)c->w_seg_off.p;
+    P->seg_blk = (int32_t*)c->w_seg_blk.p;
+    P->ctr = (Counters*)c->w_ctr.p;
+    if (dout) {
+        P->out_elayer = dout->elayer;
+        P->out_counts = dout->counts;
+        P->out_ids = (long long*)dout->cell_ids;
+        P->out_e = dout->cell_e;
+        P->out_cap = dout->cell_ids ? dout->cell_capacity : 0;
+        P->out_ev_off = (long long*)dout->event_cell_offsets;
+        P->hit_eta = dout->hit_eta;
+        P->hit_phi = dout->hit_phi;
+        P->hit_e = dout->hit_e;
+        P->hit_cell = dout->hit_cell;
+        P->hit_cap = want_hits ? dout->hit_capacity : 0;
+        P->out_task_hoff = (long long*)dout->task_hit_offsets;
+    }
+    P->hit_base = sh.hit_base;
+    P->out_base = sh.out_base;
+    return FCS_OK;
+}
+
+// Enqueue the launch sequence of one batch on c->stream (all kernels read
+// the device Params block, so the sequence can be captured and replayed).
+void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, bool compact, int grid)
+{
+    const Params* dP = (const Params*)c->w_params.p;
+    hipStream_t s = c->stream;
+    hipLaunchKernelGGL(fcsk::k_reset_counters, dim3(1), dim3(64), 0, s, dP);
+    if (validate)
+        hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(P.n_particles, P.n_events), 256)),
+                           dim3(256), 0, s, dP);
+    if (dense) hipLaunchKernelGGL(fcsk::k_fill_dense, dim3(2048), dim3(256), 0, s, dP);
+    const int ppb = fcsk::kBlock / P.n_layers;
+    hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(P.n_particles, ppb)), dim3(fcsk::kBlock), 0, s, dP);
+    hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
+    hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, s, dP);
+    hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
+    hipLaunchKernelGGL(fcsk::k_hits, dim3(grid), dim3(fcsk::kBlock), 0, s, dP);
+    (void)compact;
+    const unsigned nw = grid_for(P.n_events * P.n_seg, fcsk::kBlock / fcsk::kWave);
+    hipLaunchKernelGGL(fcsk::k_seg_count, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
+    hipLaunchKernelGGL(fcsk::k_seg_reduce, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
+    hipLaunchKernelGGL(fcsk::k_seg_top, dim3(1), dim3(1024), 0, s, dP);
+    hipLaunchKernelGGL(fcsk::k_seg_apply, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
+    hipLaunchKernelGGL(fcsk::k_seg_write, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
+}
+
+int counters_error(fcs_ctx* c, const Counters& k)
+{
+    if (k.error & fcsk::kErrPdg) return fail(c, FCS_E_INVALID_ARG, "unknown particle pdg (use 11, 22, 211)");
+    if (k.error & fcsk::kErrParticle)
+        return fail(c, FCS_E_INVALID_ARG, "particle energy must be finite and > 0, eta/phi finite");
+    if (k.error & fcsk::kErrOffsets) return fail(c, FCS_E_INVALID_ARG, "malformed event_offsets");
+    if (k.error & fcsk::kErrTooManyHits)
+        return fail(c, FCS_E_CAPACITY, "more than 2^31-1 hits in one batch: split the batch");
+    return FCS_OK;
+}
+
+// Run one launch sequence over a range of events and wait for it.
+int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
+              const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
+              float* dense_out, const fcs_sim_output* dout, bool want_hits, bool validate,
+              bool use_graph, Counters* res)
+{
+    const int grid = c->n_cu * tu.wg_per_cu;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        Params* P = c->h_params;
+        int rc = prepare(c, o, tu, sh, d_particles, d_evoff, d_override, dense_out, dout, want_hits, P);
+        if (rc) return rc;
+        HIPCHK(c, hipMemcpyAsync(c->w_params.p, P, sizeof(Params), hipMemcpyHostToDevice, c->stream));
+        const bool dense = dense_out != nullptr;
+        if (use_graph) {
+            GraphKey key{sh.n_particles, sh.n_events, dense ? 1 : 0, validate ? 1 : 0, grid};
+            auto it = c->graphs.find(key);
+            if (it == c->graphs.end()) {
+                hipGraph_t g = nullptr;
+                hipGraphExec_t ge = nullptr;
+                HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                enqueue_batch(c, *P, dense, validate, true, grid);
+                HIPCHK(c, hipStreamEndCapture(c->stream, &g));
+                HIPCHK(c, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+                (void)hipGraphDestroy(g);
+                it = c->graphs.emplace(key, ge).first;
+            }
+            HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+        } else {
+            enqueue_batch(c, *P, dense, validate, true, grid);
+            HIPCHK(c, hipGetLastError());
+        }
+        HIPCHK(c, hipMemcpyAsync(c->h_ctr, c->w_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *res = *c->h_ctr;
+        if ((res->error & fcsk::kErrChunkCap) && attempt == 0) {
+            c->chunk_cap = (long long)res->need_chunks + 1024;
+            continue;
+        }
+        return counters_error(c, *res);
+    }
+    return fail(c, FCS_E_HIP, "work queue sizing did not converge");
+}
+
+// host-side checks of host inputs
+int check_host_inputs(fcs_ctx* c, const fcs_particle* parts, const int64_t* off, int64_t n_events)
+{
+    if (off[0] != 0) return fail(c, FCS_E_INVALID_ARG, "event_offsets[0] = %lld, must be 0", (long long)off[0]);
+    for (int64_t e = 0; e < n_events; ++e)
+        if (off[e + 1] < off[e])
+            return fail(c, FCS_E_INVALID_ARG, "event_offsets decreases at event %lld", (long long)e);
+    const int64_t N = off[n_events];
+    for (int64_t i = 0; i < N; ++i) {
+        const fcs_particle& p = parts[i];
+        const int a = p.pdg < 0 ? -p.pdg : p.pdg;
+        if (a != 11 && a != 22 && a != 211)
+            return fail(c, FCS_E_INVALID_ARG, "particle %lld: unknown pdg %d (use 11, 22, 211)",
+                        (long long)i, p.pdg);
+        if (!finite_pos(p.e_mev))
+            return fail(c, FCS_E_INVALID_ARG, "particle %lld: energy must be finite and > 0", (long long)i);
+        if (!std::isfinite(p.eta) || !std::isfinite(p.phi) || std::fabs(p.phi) > 3.2f)
+            return fail(c, FCS_E_INVALID_ARG, "particle %lld: eta/phi not finite or |phi| > 3.2",
+                        (long long)i);
+    }
+    return FCS_OK;
+}
+
+// Common front half of simulate / query / backward: validate, bring inputs
+// to the device, read the event offsets the host needs.
+struct Inputs {
+    const fcsk::Particle* d_particles = nullptr;
+    const long long* d_evoff = nullptr;
+    const float* d_override = nullptr;
+    std::vector<int64_t> h_off;  // host copy of event_offsets
+    long long N = 0;
+    bool validate_on_device = false;
+};
+
+int stage_inputs(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
+                 int64_t n_events, const fcs_sim_options* o, bool need_host_offsets, Inputs* in)
+{
+    if (!c->has_geom || !c->has_param)
+        return fail(c, FCS_E_NOT_LOADED, "load the geometry and the parametrization first");
+    if (!o) return fail(c, FCS_E_INVALID_ARG, "options are NULL");
+    if (n_events < 1) return fail(c, FCS_E_INVALID_ARG, "n_events = %lld, must be >= 1", (long long)n_events);
+    if (!event_offsets) return fail(c, FCS_E_INVALID_ARG, "event_offsets is NULL");
+    if (!(o->hit_energy_scale_mev > 0.f) || !std::isfinite(o->hit_energy_scale_mev))
+        return fail(c, FCS_E_INVALID_ARG, "hit_energy_scale_mev must be finite and > 0");
+    if (o->nhit_cap < 1) return fail(c, FCS_E_INVALID_ARG, "nhit_cap must be >= 1");
+    if (!(o->min_layer_energy_mev > 0.0) || !std::isfinite(o->min_layer_energy_mev))
+        return fail(c, FCS_E_INVALID_ARG, "min_layer_energy_mev must be finite and > 0");
+    if (o->mode != FCS_MODE_BATCHED && o->mode != FCS_MODE_PER_EVENT)
+        return fail(c, FCS_E_INVALID_ARG, "unknown mode %d", o->mode);
+    if (c->dry) {
+        if (!o->inputs_on_device) {
+            const long long N = event_offsets[n_events];
+            if (N > 0 && !particles) return fail(c, FCS_E_INVALID_ARG, "particles is NULL");
+            int rc = check_host_inputs(c, particles, event_offsets, n_events);
+            if (rc) return rc;
+        }
+        return fail(c, FCS_E_NO_DEVICE, "context has no device (arguments are valid)");
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    if (o->stream) {
+        HIPCHK(c, hipEventRecord(c->ev_in, (hipStream_t)o->stream));
+        HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
+    }
+    const int L = c->n_layers;
+    if (!o->inputs_on_device) {
+        in->N = event_offsets[n_events];
+        if (in->N > 0 && !particles) return fail(c, FCS_E_INVALID_ARG, "particles is NULL");
+        int rc = check_host_inputs(c, particles, event_offsets, n_events);
+        if (rc) return rc;
+        if (in->N >= (1LL << 25))
+            return fail(c, FCS_E_INVALID_ARG, "%lld particles in one call, at most 2^25 - 1", in->N);
+        if ((rc = upload(c, c->w_particles, (const fcsk::Particle*)particles, (size_t)in->N)) ||
+            (rc = upload(c, c->w_evoff, (const long long*)event_offsets, (size_t)n_events + 1)))
+            return rc;
+        if (o->elayer_override) {
+            for (long long i = 0; i < in->N * L; ++i)
+                if (!std::isfinite(o->elayer_override[i]) || o->elayer_override[i] < 0.f)
+                    return fail(c, FCS_E_INVALID_ARG, "elayer_override[%lld] negative or not finite", i);
+            if ((rc = upload(c, c->w_override, o->elayer_override, (size_t)(in->N * L)))) return rc;
+            in->d_override = (const float*)c->w_override.p;
+        }
+        in->d_particles = (const fcsk::Particle*)c->w_particles.p;
+        in->d_evoff = (const long long*)c->w_evoff.p;
+        if (need_host_offsets) in->h_off.assign(event_offsets, event_offsets + n_events + 1);
+    } else {
+        in->d_particles = (const fcsk::Particle*)particles;
+        in->d_evoff = (const long long*)event_offsets;
+        in->d_override = o->elayer_override;
+        if (need_host_offsets) {
+            in->h_off.resize((size_t)n_events + 1);
+            HIPCHK(c, hipMemcpyAsync(in->h_off.data(), event_offsets, (n_events + 1) * sizeof(int64_t),
+                                     hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            in->N = in->h_off[n_events];
+        } else {
+            int64_t last = 0;
+            HIPCHK(c, hipMemcpyAsync(&last, event_offsets + n_events, sizeof(int64_t),
+                                     hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            in->N = last;
+        }
+        if (in->N < 0 || in->N >= (1LL << 25))
+            return fail(c, FCS_E_INVALID_ARG, "event_offsets[n_events] = %lld outside [0, 2^25)", in->N);
+        if (in->N > 0 && !particles) return fail(c, FCS_E_INVALID_ARG, "particles is NULL");
+        in->validate_on_device = true;
+    }
+    return FCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
+                        int64_t n_events, const fcs_sim_options* o, fcs_sim_output* out)
+{
+    if (!c) return FCS_E_INVALID_ARG;
+    if (!out) return fail(c, FCS_E_INVALID_ARG, "output struct is NULL");
+    Tuning tu;
+    int rc = o ? check_tuning(c, o, &tu) : fail(c, FCS_E_INVALID_ARG, "options are NULL");
+    if (rc) return rc;
+    const uint32_t f = o->outputs;
+    if ((f & FCS_OUT_DENSE) && !out->cells) return fail(c, FCS_E_INVALID_ARG, "FCS_OUT_DENSE needs out->cells");
+    if ((f & FCS_OUT_COMPACT) && (!out->cell_ids || !out->cell_e || !out->event_cell_offsets))
+        return fail(c, FCS_E_INVALID_ARG, "FCS_OUT_COMPACT needs cell_ids, cell_e, event_cell_offsets");
+    if ((f & FCS_OUT_COMPACT) && out->cell_capacity < 0)
+        return fail(c, FCS_E_INVALID_ARG, "cell_capacity < 0");
+    if ((f & FCS_OUT_HITS) && (!out->hit_eta || !out->hit_phi || !out->hit_e || !out->hit_cell ||
+                               !out->task_hit_offsets || out->hit_capacity < 0))
+        return fail(c, FCS_E_INVALID_ARG, "FCS_OUT_HITS needs hit_eta/phi/e/cell, task_hit_offsets, hit_capacity");
+    if ((f & FCS_OUT_COUNTS) && !out->counts) return fail(c, FCS_E_INVALID_ARG, "FCS_OUT_COUNTS needs out->counts");
+    if ((f & FCS_OUT_ELAYER) && !out->elayer) return fail(c, FCS_E_INVALID_ARG, "FCS_OUT_ELAYER needs out->elayer");
+    const bool per_event = o->mode == FCS_MODE_PER_EVENT;
+    Inputs in;
+    if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, per_event, &in))) return rc;
+    const int L = c->n_layers;
+    const long long N = in.N;
+    const long long C = c->n_cells;
+
+    // device-side output views (the caller's, or staging for host outputs)
+    fcs_sim_output d = *out;
+    const bool host_out = !o->outputs_on_device;
+    if (host_out) {
+        if ((f & FCS_OUT_DENSE) && (rc = ensure(c, c->o_cells, (size_t)n_events * C * 4))) return rc;
+        if (f & FCS_OUT_COMPACT) {
+            if ((rc = ensure(c, c->o_ids, (size_t)std::max<int64_t>(out->cell_capacity, 1) * 8)) ||
+                (rc = ensure(c, c->o_e, (size_t)std::max<int64_t>(out->cell_capacity, 1) * 4)) ||
+                (rc = ensure(c, c->o_evoff, (size_t)(n_events + 1) * 8)))
+                return rc;
+            d.cell_ids = (int64_t*)c->o_ids.p;
+            d.cell_e = (float*)c->o_e.p;
+            d.event_cell_offsets = (int64_t*)c->o_evoff.p;
+        }
+        if (f & FCS_OUT_HITS) {
+            const size_t hc = (size_t)std::max<int64_t>(out->hit_capacity, 1);
+            if ((rc = ensure(c, c->o_heta, hc * 4)) || (rc = ensure(c, c->o_hphi, hc * 4)) ||
+                (rc = ensure(c, c->o_he, hc * 4)) || (rc = ensure(c, c->o_hcell, hc * 4)) ||
+                (rc = ensure(c, c->o_thoff, (size_t)(N * L + 1) * 8)))
+                return rc;
+            d.hit_eta = (float*)c->o_heta.p;
+            d.hit_phi = (float*)c->o_hphi.p;
+            d.hit_e = (float*)c->o_he.p;
+            d.hit_cell = (int32_t*)c->o_hcell.p;
+            d.task_hit_offsets = (int64_t*)c->o_thoff.p;
+        }
+        if ((f & FCS_OUT_COUNTS) && (rc = ensure(c, c->o_counts, (size_t)std::max<long long>(N * L, 1) * 4))) return rc;
+        if ((f & FCS_OUT_ELAYER) && (rc = ensure(c, c->o_elayer, (size_t)std::max<long long>(N * L, 1) * 4))) return rc;
+        d.cells = (f & FCS_OUT_DENSE) ? (float*)c->o_cells.p : nullptr;
+        d.counts = (f & FCS_OUT_COUNTS) ? (int32_t*)c->o_counts.p : nullptr;
+        d.elayer = (f & FCS_OUT_ELAYER) ? (float*)c->o_elayer.p : nullptr;
+    }
+    if (!(f & FCS_OUT_DENSE)) d.cells = nullptr;
+    if (!(f & FCS_OUT_COMPACT)) {
+        d.cell_ids = nullptr;
+        d.cell_e = nullptr;
+        d.event_cell_offsets = nullptr;
+        d.cell_capacity = 0;
+    }
+    if (!(f & FCS_OUT_HITS)) {
+        d.hit_eta = d.hit_phi = d.hit_e = nullptr;
+        d.hit_cell = nullptr;
+        d.task_hit_offsets = nullptr;
+        d.hit_capacity = 0;
+    }
+    if (!(f & FCS_OUT_COUNTS)) d.counts = nullptr;
+    if (!(f & FCS_OUT_ELAYER)) d.elayer = nullptr;
+    const bool want_hits = (f & FCS_OUT_HITS) != 0;
+
+    HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
+    long long hits = 0, hits_out = 0, nnz = 0, items = 0;
+    if (N == 0) {
+        // no particles: zero outputs only
+        if (d.cells) HIPCHK(c, hipMemsetAsync(d.cells, 0, (size_t)n_events * C * 4, c->stream));
+        if (d.event_cell_offsets)
+            HIPCHK(c, hipMemsetAsync(d.event_cell_offsets, 0, (size_t)(n_events + 1) * 8, c->stream));
+        if (d.task_hit_offsets) HIPCHK(c, hipMemsetAsync(d.task_hit_offsets, 0, 8, c->stream));
+    } else if (!per_event) {
+        Shape sh{N, 0, n_events, 0, 0, 0};
+        Counters k;
+        rc = run_range(c, o, tu, sh, in.d_particles, in.d_evoff, in.d_override, d.cells, &d,
+                       want_hits, in.validate_on_device, o->use_graph != 0, &k);
+        if (rc) return rc;
+        hits = k.hits_total;
+        hits_out = k.hits_out;
+        nnz = k.nnz_total;
+        items = (long long)k.n_chunks + k.n_tiles;
+    } else {
+        for (int64_t e = 0; e < n_events; ++e) {
+            const long long p0 = in.h_off[e], p1 = in.h_off[e + 1];
+            fcs_sim_output de = d;
+            if (d.cells) de.cells = d.cells + e * C;
+            if (d.counts) de.counts = d.counts + p0 * L;
+            if (d.elayer) de.elayer = d.elayer + p0 * L;
+            if (d.task_hit_offsets) de.task_hit_offsets = d.task_hit_offsets + p0 * L;
+            if (d.event_cell_offsets) de.event_cell_offsets = d.event_cell_offsets + e;
+            if (p1 == p0) {
+                if (de.cells) HIPCHK(c, hipMemsetAsync(de.cells, 0, (size_t)C * 4, c->stream));
+                if (de.event_cell_offsets) {
+                    // an empty event: its offset is the running count
+                    HIPCHK(c, hipMemcpyAsync(de.event_cell_offsets, &nnz, 8, hipMemcpyHostToDevice, c->stream));
+                    HIPCHK(c, hipStreamSynchronize(c->stream));
+                }
+                continue;
+            }
+            Shape sh{p1 - p0, p0, 1, e, hits, nnz};
+            const fcsk::Particle* dp = in.d_particles + p0;
+            const float* dov = in.d_override ? in.d_override + p0 * L : nullptr;
+            Counters k;
+            rc = run_range(c, o, tu, sh, dp, in.d_evoff + e, dov, de.cells, &de, want_hits,
+                           in.validate_on_device, false, &k);
+            if (rc) return rc;
+            hits += k.hits_total;
+            hits_out += k.hits_out;
+            nnz += k.nnz_total;
+            items += (long long)k.n_chunks + k.n_tiles;
+        }
+        if (d.event_cell_offsets)
+            HIPCHK(c, hipMemcpyAsync(d.event_cell_offsets + n_events, &nnz, 8, hipMemcpyHostToDevice, c->stream));
+        if (d.task_hit_offsets)
+            HIPCHK(c, hipMemcpyAsync(d.task_hit_offsets + N * L, &hits, 8, hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(c, hipEventRecord(c->ev_stop, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev_start, c->ev_stop);
+
+    out->n_hits = hits;
+    out->n_hits_out_of_acceptance = hits_out;
+    out->n_tasks = N * L;
+    out->n_cells_nonzero = nnz;
+    out->required_cell_capacity = nnz;
+    out->required_hit_capacity = hits;
+    out->n_work_items = items;
+    out->device_ms = ms;
+
+    if (host_out) {
+        if (f & FCS_OUT_DENSE)
+            HIPCHK(c, hipMemcpy(out->cells, d.cells, (size_t)n_events * C * 4, hipMemcpyDeviceToHost));
+        if (f & FCS_OUT_COMPACT) {
+            const size_t m = (size_t)std::min<long long>(nnz, out->cell_capacity);
+            if (m) {
+                HIPCHK(c, hipMemcpy(out->cell_ids, d.cell_ids, m * 8, hipMemcpyDeviceToHost));
+                HIPCHK(c, hipMemcpy(out->cell_e, d.cell_e, m * 4, hipMemcpyDeviceToHost));
+            }
+            HIPCHK(c, hipMemcpy(out->event_cell_offsets, d.event_cell_offsets, (n_events + 1) * 8,
+                                hipMemcpyDeviceToHost));
+        }
+        if (f & FCS_OUT_HITS) {
+            const size_t m = (size_t)std::min<long long>(hits, out->hit_capacity);
+            if (m) {
+                HIPCHK(c, hipMemcpy(out->hit_eta, d.hit_eta, m * 4, hipMemcpyDeviceToHost));
+                HIPCHK(c, hipMemcpy(out->hit_phi, d.hit_phi, m * 4, hipMemcpyDeviceToHost));
+                HIPCHK(c, hipMemcpy(out->hit_e, d.hit_e, m * 4, hipMemcpyDeviceToHost));
+                HIPCHK(c, hipMemcpy(out->hit_cell, d.hit_cell, m * 4, hipMemcpyDeviceToHost));
+            }
+            HIPCHK(c, hipMemcpy(out->task_hit_offsets, d.task_hit_offsets, (size_t)(N * L + 1) * 8,
+                                hipMemcpyDeviceToHost));
+        }
+        if ((f & FCS_OUT_COUNTS) && N)
+            HIPCHK(c, hipMemcpy(out->counts, d.counts, (size_t)(N * L) * 4, hipMemcpyDeviceToHost));
+        if ((f & FCS_OUT_ELAYER) && N)
+            HIPCHK(c, hipMemcpy(out->elayer, d.elayer, (size_t)(N * L) * 4, hipMemcpyDeviceToHost));
+    }
+    if ((f & FCS_OUT_COMPACT) && nnz > out->cell_capacity)
+        return fail(c, FCS_E_CAPACITY, "cell_capacity %lld < %lld compacted cells",
+                    (long long)out->cell_capacity, nnz);
+    if ((f & FCS_OUT_HITS) && hits > out->hit_capacity)
+        return fail(c, FCS_E_CAPACITY, "hit_capacity %lld < %lld hits", (long long)out->hit_capacity, hits);
+    return FCS_OK;
+}
+
+int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
+                    int64_t n_events, const fcs_sim_options* o, fcs_sizes* s)
+{
+    if (!c) return FCS_E_INVALID_ARG;
+    if (!s) return fail(c, FCS_E_INVALID_ARG, "sizes struct is NULL");
+    Tuning tu;
+    int rc = o ? check_tuning(c, o, &tu) : fail(c, FCS_E_INVALID_ARG, "options are NULL");
+    if (rc) return rc;
+    Inputs in;
+    if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, false, &in))) return rc;
+    std::memset(s, 0, sizeof *s);
+    if (in.N == 0) return FCS_OK;
+    Params* P = c->h_params;
+    Shape sh{in.N, 0, n_events, 0, 0, 0};
+    if ((rc = prepare(c, o, tu, sh, in.d_particles, in.d_evoff, nullptr, nullptr, nullptr, false, P)))
+        return rc;
+    const Params* dP = (const Params*)c->w_params.p;
+    HIPCHK(c, hipMemcpyAsync(c->w_params.p, P, sizeof(Params), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(fcsk::k_reset_counters, dim3(1), dim3(64), 0, c->stream, dP);
+    if (in.validate_on_device)
+        hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(in.N, (long long)n_events), 256)),
+                           dim3(256), 0, c->stream, dP);
+    hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(in.N, fcsk::kBlock / c->n_layers)), dim3(fcsk::kBlock),
+                       0, c->stream, dP);
+    hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, c->stream, dP);
+    hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, c->stream, dP);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->h_ctr, c->w_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const Counters k = *c->h_ctr;
+    if ((rc = counters_error(c, k))) return rc;
+    s->n_hits = k.hits_total;
+    s->n_tasks = in.N * c->n_layers;
+    s->max_cells = std::min<long long>(k.hits_total, (long long)n_events * c->n_cells);
+    return FCS_OK;
+}
+
+int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
+                 int64_t n_events, const fcs_sim_options* o, const float* grad_cells,
+                 float* grad_elayer, float* grad_weights)
+{
+    if (!c) return FCS_E_INVALID_ARG;
+    if (!grad_cells) return fail(c, FCS_E_INVALID_ARG, "grad_cells is NULL");
+    Tuning tu;
+    int rc = o ? check_tuning(c, o, &tu) : fail(c, FCS_E_INVALID_ARG, "options are NULL");
+    if (rc) return rc;
+    Inputs in;
+    if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, false, &in))) return rc;
+    const long long nt = in.N * c->n_layers;
+    if (in.N == 0) {
+        if (grad_weights) HIPCHK(c, hipMemsetAsync(grad_weights, 0, (size_t)c->n_hist * 256 * 4, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return FCS_OK;
+    }
+    if ((rc = ensure(c, c->w_acc_el, (size_t)nt * 8)) ||
+        (rc = ensure(c, c->w_acc_bins, (size_t)c->n_hist * 256 * 8)))
+        return rc;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        Params* P = c->h_params;
+        Shape sh{in.N, 0, n_events, 0, 0, 0};
+        if ((rc = prepare(c, o, tu, sh, in.d_particles, in.d_evoff, in.d_override, nullptr, nullptr,
+                          false, P)))
+            return rc;
+        P->grad_cells = grad_cells;
+        P->acc_elayer = (double*)c->w_acc_el.p;
+        P->acc_bins = (double*)c->w_acc_bins.p;
+        P->grad_elayer = grad_elayer;
+        P->grad_weights = grad_weights;
+        const Params* dP = (const Params*)c->w_params.p;
+        hipStream_t s = c->stream;
+        HIPCHK(c, hipMemcpyAsync(c->w_params.p, P, sizeof(Params), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(fcsk::k_reset_counters, dim3(1), dim3(64), 0, s, dP);
+        if (in.validate_on_device)
+            hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(in.N, (long long)n_events), 256)),
+                               dim3(256), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_fill_u32, dim3(1024), dim3(256), 0, s, (uint32_t*)c->w_acc_el.p, nt * 2, 0u);
+        hipLaunchKernelGGL(fcsk::k_fill_u32, dim3(2048), dim3(256), 0, s, (uint32_t*)c->w_acc_bins.p,
+                           c->n_hist * 512, 0u);
+        hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(in.N, fcsk::kBlock / c->n_layers)),
+                           dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_adjoint, dim3(c->n_cu * tu.wg_per_cu), dim3(fcsk::kBlock), 0, s, dP);
+        if (grad_elayer)
+            hipLaunchKernelGGL(fcsk::k_adj_elayer, dim3(grid_for(nt, 256)), dim3(256), 0, s, dP);
+        if (grad_weights)
+            hipLaunchKernelGGL(fcsk::k_adj_weights, dim3((unsigned)c->n_hist), dim3(fcsk::kBlock), 0, s, dP);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(c->h_ctr, c->w_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        const Counters k = *c->h_ctr;
+        if ((k.error & fcsk::kErrChunkCap) && attempt == 0) {
+            c->chunk_cap = (long long)k.need_chunks + 1024;
+            continue;
+        }
+        return counters_error(c, k);
+    }
+    return fail(c, FCS_E_HIP, "work queue sizing did not converge");
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol the
+header declares, and checks arguments (device-less context) before any
+device work."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2103_14737_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2103_14737_amd import fcs
+    return fcs
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "fcs.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fcs_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(F):
+    L = F.lib()
+    declared = _declared()
+    assert set(declared) == set(F.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_create_without_gpu(F):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host has a GPU")
+    with pytest.raises(F.FcsError) as e:
+        F.Simulator(0)
+    assert e.value.code == F.FCS_E_NO_DEVICE
+
+
+@pytest.fixture()
+def dry(F):
+    s = F.Simulator(F.FCS_DEVICE_NONE)
+    yield s
+    s.close()
+
+
+def test_dry_context_loads_valid_inputs(F, dry):
+    dry.load_geometry(W.make_geometry())
+    dry.load_parametrization(W.make_param())
+    info = dry.info()
+    assert info["n_cells"] == 191338 and info["n_histograms"] == 11520 and info["device"] == -1
+
+
+def _bad_geometry(field, value):
+    g = W.make_tiny_geometry()
+    g = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in g.items()}
+    if callable(value):
+        value(g)
+    else:
+        g[field] = value
+    return g
+
+
+@pytest.mark.parametrize("case,needle", [
+    ("offset", "reg_offset"),
+    ("gap", "does not start"),
+    ("ncells", "n_cells"),
+    ("layers", "n_layers"),
+    ("inv_r", "layer_inv_r"),
+    ("neta", "reg_neta"),
+])
+def test_geometry_validation(F, dry, case, needle):
+    if case == "offset":
+        g = _bad_geometry(None, lambda g: g["reg_offset"].__setitem__(2, g["reg_offset"][2] + 1))
+    elif case == "gap":
+        g = _bad_geometry(None, lambda g: g["reg_eta_lo"].__setitem__(1, np.float32(-1.3)))
+    elif case == "ncells":
+        g = _bad_geometry("n_cells", 5)
+    elif case == "layers":
+        g = _bad_geometry("n_layers", 0)
+    elif case == "inv_r":
+        g = _bad_geometry(None, lambda g: g["layer_inv_r"].__setitem__(1, np.float32(np.nan)))
+    else:
+        g = _bad_geometry(None, lambda g: g["reg_neta"].__setitem__(0, 0))
+    with pytest.raises(F.FcsError) as e:
+        dry.load_geometry(g)
+    assert e.value.code == F.FCS_E_INVALID_ARG
+    assert needle in str(e.value)
+
+
+def test_param_validation(F, dry):
+    with pytest.raises(F.FcsError) as e:
+        dry.load_parametrization(W.make_param())
+    assert e.value.code == F.FCS_E_NOT_LOADED
+    dry.load_geometry(W.make_geometry())
+    p = W.make_param()
+    p["weights"] = p["weights"].copy()
+    p["weights"][5] = -1.0
+    with pytest.raises(F.FcsError) as e:
+        dry.load_parametrization(p)
+    assert "weights[5]" in str(e.value)
+    p = W.make_param()
+    p["weights"] = p["weights"].copy()
+    p["weights"][256:512] = 0.0
+    with pytest.raises(F.FcsError) as e:
+        dry.load_parametrization(p)
+    assert "histogram 1 " in str(e.value)
+    p = W.make_param(n_layers=3)
+    with pytest.raises(F.FcsError) as e:
+        dry.load_parametrization(p)
+    assert "n_layers" in str(e.value)
+    p = W.make_param()
+    p["n_rbins"] = 16
+    with pytest.raises(F.FcsError):
+        dry.load_parametrization(p)
+
+
+def test_simulate_argument_checks(F, dry):
+    dry.load_geometry(W.make_geometry())
+    dry.load_parametrization(W.make_param())
+    w = W.single_particle_sweep(n_events=5)
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10)
+    assert e.value.code == F.FCS_E_NO_DEVICE          # valid arguments reach the device step
+    bad = w.particles.copy()
+    bad["pdg"][3] = 13
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(bad, w.event_offsets, 1, cell_capacity=10)
+    assert e.value.code == F.FCS_E_INVALID_ARG and "particle 3" in str(e.value)
+    bad = w.particles.copy()
+    bad["e"][1] = -5
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(bad, w.event_offsets, 1, cell_capacity=10)
+    assert "energy" in str(e.value)
+    off = w.event_offsets.copy()
+    off[2], off[3] = off[3], off[2]
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, off, 1, cell_capacity=10)
+    assert "decreases" in str(e.value)
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10, tile_hits=300)
+    assert "tile_hits" in str(e.value)
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10,
+                            hit_energy_scale=0.0)
+    assert "hit_energy_scale" in str(e.value)
+
+
+def test_simulate_needs_loads(F, dry):
+    w = W.single_electron()
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10)
+    assert e.value.code == F.FCS_E_NOT_LOADED

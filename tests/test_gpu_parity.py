@@ -1,0 +1,313 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: hit counts, hit positions (bit patterns), hit cells and the set and
+order of compacted cells are identical; cell energies (FP32 accumulation)
+agree with the FP64 oracle within relative 1e-5 or absolute 1e-3 MeV."""
+import numpy as np
+import pytest
+
+from paper_2103_14737_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL, ABS = 1e-5, 1e-3
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a host without a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def geo():
+    return W.make_geometry()
+
+
+@pytest.fixture(scope="module")
+def par():
+    return W.make_param()
+
+
+@pytest.fixture(scope="module")
+def sim(torch_cuda, geo, par):
+    from paper_2103_14737_amd.fcs import Simulator
+    s = Simulator(0)
+    s.load_geometry(geo)
+    s.load_parametrization(par)
+    yield s
+    s.close()
+
+
+def _np(x):
+    return x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x)
+
+
+def _dev(w, torch):
+    from paper_2103_14737_amd.fcs import particles_to_device
+    return particles_to_device(w.particles), torch.from_numpy(w.event_offsets).cuda()
+
+
+def check_parity(r, ref, geo, hits=True, counts=True, label=""):
+    print(f"[parity] {label}: {ref['n_hits_total']} hits, {ref['n_cells_nonzero']} cells",
+          flush=True)
+    st = r["stats"]
+    assert st["n_hits"] == ref["n_hits_total"], label
+    assert st["n_hits_out_of_acceptance"] == ref["n_out_of_acc"], label
+    if counts:
+        assert np.array_equal(_np(r["counts"]), ref["n"]), label
+    if hits:
+        h = ref["hits"]
+        assert np.array_equal(_np(r["hit_cell"]), h["cell"]), label
+        assert np.array_equal(_np(r["hit_eta"]).view(np.uint32), h["eta"].view(np.uint32)), label
+        assert np.array_equal(_np(r["hit_phi"]).view(np.uint32), h["phi"].view(np.uint32)), label
+        assert np.array_equal(_np(r["hit_e"]).view(np.uint32), h["e"].view(np.uint32)), label
+        off = _np(r["task_hit_offsets"])
+        assert off[0] == 0 and np.array_equal(np.diff(off), ref["n"]), label
+    assert np.array_equal(_np(r["event_cell_offsets"]), ref["ev_cell_off"]), label
+    assert np.array_equal(_np(r["cell_ids"]), geo["cell_id"][ref["cell_idx"]]), label
+    e = _np(r["cell_e"]).astype(np.float64)
+    err = np.abs(e - ref["cell_e"])
+    tol = np.maximum(REL * np.abs(ref["cell_e"]), ABS)
+    bad = err > tol
+    assert not bad.any(), (label, int(bad.sum()), float((err / np.maximum(np.abs(ref["cell_e"]), 1e-30)).max()))
+
+
+def run_both(sim, oracle_lib, geom_o, param_o, geo, w, torch, mode="batched", hits=True,
+             device_inputs=True, base=0, **kw):
+    outputs = ("compact", "counts", "hits") if hits else ("compact", "counts")
+    if device_inputs:
+        dp, doff = _dev(w, torch)
+        r = sim.simulate_events(dp, doff, w.seed, event_index_base=base, mode=mode,
+                                outputs=outputs, hit_energy_scale=w.hit_energy_scale, **kw)
+        torch.cuda.synchronize()
+    else:
+        r = sim.simulate_events(w.particles, w.event_offsets, w.seed, event_index_base=base,
+                                mode=mode, outputs=outputs, hit_energy_scale=w.hit_energy_scale,
+                                **kw)
+    ref = oracle_lib.simulate(geom_o, param_o, w.particles, w.event_offsets, w.seed,
+                              event_index_base=base, hit_energy_scale=w.hit_energy_scale,
+                              hit_list=hits)
+    return r, ref
+
+
+# ------------------------------------------------------------- workloads ---
+@pytest.mark.parametrize("mode", ["batched", "per_event"])
+@pytest.mark.parametrize("device_inputs", [True, False])
+def test_single_electron(sim, oracle_lib, geom_full, param_full, geo, torch_cuda, mode,
+                         device_inputs):
+    w = W.single_electron()
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode,
+                      device_inputs=device_inputs)
+    check_parity(r, ref, geo, label=f"single electron {mode}")
+
+
+@pytest.mark.parametrize("mode", ["batched", "per_event"])
+def test_single_particle_sweep_slice(sim, oracle_lib, geom_full, param_full, geo, torch_cuda,
+                                     mode):
+    w = W.subset_events(W.single_particle_sweep(), 1000, 300)
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode,
+                      base=1000)
+    check_parity(r, ref, geo, label=f"sweep[1000:1300] {mode}")
+
+
+@pytest.mark.parametrize("mode", ["batched", "per_event"])
+def test_hard_scatter_slice(sim, oracle_lib, geom_full, param_full, geo, torch_cuda, mode):
+    w = W.subset_events(W.hard_scatter(), 10, 3)
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode,
+                      base=10)
+    check_parity(r, ref, geo, label=f"hard scatter[10:13] {mode}")
+
+
+def test_pileup_one_event(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+    w = W.subset_events(W.pileup(), 5, 1)
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, base=5)
+    check_parity(r, ref, geo, label="pileup[5]")
+
+
+def test_single_pion_diff_config(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+    w = W.single_pion_diff()
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda)
+    check_parity(r, ref, geo, label="single pions")
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(chunk_hits=256, big_task_hits=1, tile_hits=256, wg_per_cu=1),
+    dict(chunk_hits=4096, big_task_hits=4096, tile_hits=4096, wg_per_cu=8),
+    dict(chunk_hits=1000, big_task_hits=37, tile_hits=512, wg_per_cu=2, use_graph=False),
+])
+def test_tuning_does_not_change_results(sim, oracle_lib, geom_full, param_full, geo, torch_cuda,
+                                        tuning):
+    w = W.subset_events(W.hard_scatter(), 0, 2)
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, **tuning)
+    check_parity(r, ref, geo, label=f"tuning {tuning}")
+
+
+def test_dense_output_matches_compact(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+    w = W.subset_events(W.single_particle_sweep(), 0, 20)
+    dp, doff = _dev(w, torch_cuda)
+    r = sim.simulate_events(dp, doff, w.seed, outputs=("dense", "compact"))
+    ref = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed)
+    check_parity(r, ref, geo, hits=False, counts=False, label="dense+compact")
+    dense = _np(r["cells"])
+    C = geo["n_cells"]
+    want = np.zeros((w.n_events, C))
+    for e in range(w.n_events):
+        s, t = ref["ev_cell_off"][e], ref["ev_cell_off"][e + 1]
+        want[e, ref["cell_idx"][s:t]] = ref["cell_e"][s:t]
+    assert np.all(np.abs(dense - want) <= np.maximum(REL * np.abs(want), ABS))
+    assert np.count_nonzero(dense) == ref["n_cells_nonzero"]
+
+
+# ------------------------------------------------------------ edge cases ---
+def _particles(rows):
+    p = np.zeros(len(rows), W.PARTICLE_DTYPE)
+    for i, r in enumerate(rows):
+        p[i] = r
+    return p
+
+
+def test_edge_cases(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+    pi_f = np.float32(np.pi)
+    rows = [(11, 65000.0, 3.6, 0.0),             # all hits out of acceptance
+            (11, 65000.0, 3.2, 1.0),             # acceptance edge
+            (22, 50000.0, -3.1999998, -pi_f),    # phi = -pi_f
+            (211, 40000.0, 1.4, np.nextafter(pi_f, np.float32(0))),  # region edge, phi ~ pi
+            (11, 4.0e6, 0.0, 0.5),               # 4 TeV: hit cap
+            (-211, 1000.0, -1.4, 2.0),           # soft pion at a region edge
+            (22, 2.0e5, 2.49, -3.0)]
+    parts = _particles(rows)
+    # events: [0,2), empty, [2,5), [5,7)
+    w = W.Workload("edges", 77, parts, np.array([0, 2, 2, 5, 7], np.int64))
+    for mode in ("batched", "per_event"):
+        r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode)
+        check_parity(r, ref, geo, label=f"edges {mode}")
+        assert ref["n"].max() == 20000
+        assert ref["ev_cell_off"][1] == ref["ev_cell_off"][2]
+
+
+def test_tiny_geometry(torch_cuda, oracle_lib):
+    from paper_2103_14737_amd.fcs import Simulator
+    g, p = W.make_tiny_geometry(), W.make_param(n_layers=3)
+    s = Simulator(0)
+    s.load_geometry(g)
+    s.load_parametrization(p)
+    rng = np.random.default_rng(3)
+    n = 200
+    parts = _particles([(int(rng.choice([11, 22, 211])), float(np.exp(rng.uniform(8, 13))),
+                         float(rng.uniform(-3.4, 3.4)), float(rng.uniform(-np.pi, np.pi)))
+                        for _ in range(n)])
+    off = np.array([0, 50, 120, 200], np.int64)
+    w = W.Workload("tiny", 5, parts, off)
+    go, po = oracle_lib.Geometry(g), oracle_lib.Param(p)
+    r, ref = run_both(s, oracle_lib, go, po, g, w, torch_cuda)
+    check_parity(r, ref, g, label="tiny geometry")
+    s.close()
+
+
+def test_capacity_and_errors(sim, geo, torch_cuda):
+    from paper_2103_14737_amd.fcs import FCS_E_CAPACITY, FCS_E_INVALID_ARG, FcsError
+    w = W.subset_events(W.single_particle_sweep(), 0, 10)
+    dp, doff = _dev(w, torch_cuda)
+    with pytest.raises(FcsError) as e:
+        sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=5)
+    assert e.value.code == FCS_E_CAPACITY and "cell_capacity" in str(e.value)
+    with pytest.raises(FcsError) as e:
+        sim.simulate_events(dp, doff, w.seed, outputs=("hits",), hit_capacity=10)
+    assert e.value.code == FCS_E_CAPACITY
+    bad = w.particles.copy()
+    bad["pdg"][4] = 2212
+    from paper_2103_14737_amd.fcs import particles_to_device
+    with pytest.raises(FcsError) as e:
+        sim.simulate_events(particles_to_device(bad), doff, w.seed, cell_capacity=10 ** 6)
+    assert e.value.code == FCS_E_INVALID_ARG and "pdg" in str(e.value)
+    # the context stays usable after errors, and the accumulator stays clean
+    r1 = sim.simulate_events(dp, doff, w.seed)
+    r2 = sim.simulate_events(dp, doff, w.seed)
+    assert np.array_equal(_np(r1["cell_ids"]), _np(r2["cell_ids"]))
+    assert np.array_equal(_np(r1["cell_e"]), _np(r2["cell_e"])) or np.allclose(
+        _np(r1["cell_e"]), _np(r2["cell_e"]), rtol=REL, atol=ABS)
+
+
+def test_modes_and_graph_replay_agree(sim, geo, torch_cuda):
+    w = W.subset_events(W.hard_scatter(), 20, 4)
+    dp, doff = _dev(w, torch_cuda)
+    outs = []
+    for kw in (dict(mode="batched"), dict(mode="batched"), dict(mode="batched", use_graph=False),
+               dict(mode="per_event")):
+        r = sim.simulate_events(dp, doff, w.seed, event_index_base=20,
+                                outputs=("compact", "counts", "hits"), **kw)
+        torch_cuda.cuda.synchronize()
+        outs.append({k: _np(v) for k, v in r.items() if k != "stats"})
+    for o in outs[1:]:
+        for k in ("cell_ids", "event_cell_offsets", "counts", "hit_cell", "task_hit_offsets"):
+            assert np.array_equal(o[k], outs[0][k]), k
+        assert np.allclose(o["cell_e"], outs[0]["cell_e"], rtol=REL, atol=ABS)
+
+
+# ------------------------------------------- full-size launch configurations ---
+def test_full_single_particle_sweep(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+    w = W.single_particle_sweep()
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, hits=False)
+    check_parity(r, ref, geo, hits=False, label="sweep 10k events (full)")
+
+
+def test_full_hard_scatter(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+    w = W.hard_scatter()
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, hits=False)
+    check_parity(r, ref, geo, hits=False, label="hard scatter 100 events (full)")
+
+
+def test_full_pileup_sampled_events(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+    full = W.pileup()
+    dp, doff = _dev(full, torch_cuda)
+    r = sim.simulate_events(dp, doff, full.seed, outputs=("compact", "counts"),
+                            hit_energy_scale=full.hit_energy_scale)
+    torch_cuda.cuda.synchronize()
+    print(f"[parity] pileup full: {r['stats']['n_hits']} hits", flush=True)
+    ids, es, off = _np(r["cell_ids"]), _np(r["cell_e"]), _np(r["event_cell_offsets"])
+    counts = _np(r["counts"])
+    L = 24
+    for e in (0, 13, 19):
+        sub = W.subset_events(full, e, 1)
+        ref = oracle_lib.simulate(geom_full, param_full, sub.particles, sub.event_offsets,
+                                  full.seed, event_index_base=e,
+                                  hit_energy_scale=full.hit_energy_scale)
+        a, b = full.event_offsets[e], full.event_offsets[e + 1]
+        assert np.array_equal(counts[a * L:b * L], ref["n"])
+        s, t = off[e], off[e + 1]
+        assert np.array_equal(ids[s:t], geo["cell_id"][ref["cell_idx"]])
+        err = np.abs(es[s:t].astype(np.float64) - ref["cell_e"])
+        assert np.all(err <= np.maximum(REL * ref["cell_e"], ABS))
+
+
+# --------------------------------------------------------------- adjoint ---
+def test_backward_matches_oracle_gradient(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+    torch = torch_cuda
+    w = W.single_pion_diff()
+    C = geo["n_cells"]
+    ep = oracle_lib.perturbed_elayer(param_full, w.particles, w.event_offsets, w.seed)
+    T = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
+                            elayer_override=ep)
+    E = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed)
+
+    def dense(res):
+        d = np.zeros(w.n_events * C)
+        o = res["ev_cell_off"]
+        for e in range(w.n_events):
+            d[e * C + res["cell_idx"][o[e]:o[e + 1]]] = res["cell_e"][o[e]:o[e + 1]]
+        return d
+
+    g = (2.0 * (dense(E) - dense(T))).astype(np.float32)
+    dE_ref, dW_ref = oracle_lib.gradient(geom_full, param_full, w.particles, w.event_offsets,
+                                         w.seed, g)
+    dp, doff = _dev(w, torch)
+    dE, dW = sim.backward(dp, doff, w.seed, torch.from_numpy(g).cuda())
+    torch.cuda.synchronize()
+    dE, dW = _np(dE).astype(np.float64), _np(dW).astype(np.float64)
+    sE = np.abs(dE_ref).max()
+    assert np.all(np.abs(dE - dE_ref) <= 1e-5 * np.abs(dE_ref) + 1e-6 * sE)
+    sW = np.abs(dW_ref).max()
+    assert np.all(np.abs(dW - dW_ref) <= 1e-5 * np.abs(dW_ref) + 1e-6 * sW)
+    assert np.count_nonzero(dW_ref) > 0
