@@ -1,0 +1,248 @@
+"""Benchmark of the batched hit simulation on one MI355X.
+
+One step = one fcs_simulate_events call over the whole batch in batched mode
+(per-(particle, layer) setup, work-queue build, persistent hit kernel,
+ordered compaction and accumulator reset), inputs and outputs resident in
+device memory.  The headline workload is the single-particle sweep: 10,000
+events of one e/gamma/pi+- each, E log-uniform 1 GeV - 4 TeV, |eta| < 2.5.
+
+Also reported on the same JSON line: the per-event launch form of the same
+workload (one launch sequence and one host synchronization per event), the
+forward+backward throughput of the differentiable workload (64 single pions),
+the batched throughput of the multi-particle workloads, the roofline of the
+hit kernel and the CPU oracle timed on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "hits/s & events/s, batched vs per-event launch; fwd+bwd hits/s (1 GPU)"
+
+# peak figures of the chip (MI355X): 256 CUs, 4 SIMD x 16 lanes per CU, 2.4 GHz
+N_CU, CLOCK_HZ = 256, 2.4e9
+VALU_LANE_OPS_PEAK = N_CU * 64 * CLOCK_HZ       # 32-bit VALU lane-ops per second
+HBM_PEAK = 8.0e12
+
+# Algorithmic 32-bit operations per hit (lane-ops): Philox4x32-10 = 10 rounds
+# x (2 32x32->64 multiplies + 4 xor) + 9 x 2 key adds = 78; three 24-bit
+# uniforms = 9; guide-table bin search ~ 4; placement (radius, octant sine /
+# cosine polynomials, quadrant, deta / dphi, add, wrap) = 37; region-grid
+# lookup = 19.  One deposit per hit.
+OPS_PER_HIT = 78 + 9 + 4 + 37 + 19
+
+
+def _sync(torch):
+    torch.cuda.synchronize()
+
+
+def _time_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    _sync(torch)
+    t0 = time.perf_counter()
+    res = [fn() for _ in range(steps)]
+    _sync(torch)
+    return (time.perf_counter() - t0) / steps, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time only the headline batched workload (for profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "events shard across GPUs with no communication, see the design notes.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2103_14737_amd import workloads as W
+    from paper_2103_14737_amd.fcs import Simulator, particles_to_device
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    geo, par = W.make_geometry(), W.make_param()
+    sim = Simulator(0)
+    t0 = time.perf_counter()
+    sim.load_geometry(geo)
+    sim.load_parametrization(par)
+    load_ms = (time.perf_counter() - t0) * 1e3
+
+    def prepare(w, outputs=("compact",)):
+        dp = particles_to_device(w.particles, dev)
+        doff = torch.from_numpy(w.event_offsets).to(dev)
+        q = sim.query_sizes(dp, doff, w.seed, hit_energy_scale=w.hit_energy_scale)
+        out = {}
+        cap = q["max_cells"]
+        if "compact" in outputs:
+            out["cell_ids"] = torch.empty(cap, dtype=torch.int64, device=dev)
+            out["cell_e"] = torch.empty(cap, dtype=torch.float32, device=dev)
+            out["event_cell_offsets"] = torch.empty(w.n_events + 1, dtype=torch.int64, device=dev)
+        if "dense" in outputs:
+            out["cells"] = torch.empty((w.n_events, geo["n_cells"]), dtype=torch.float32,
+                                       device=dev)
+        return dp, doff, out, cap, q
+
+    # ------------------------------------------------ headline: batched sweep
+    w = W.single_particle_sweep()
+    dp, doff, out, cap, q = prepare(w)
+    hits_per_step = q["n_hits"]
+    print(f"bench: {w.name}: {w.n_events} events, {hits_per_step} hits per step", flush=True)
+    stats = []
+
+    def step_batched(profile=True):
+        r = sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap,
+                                out=out, profile=profile)
+        stats.append(r["stats"])
+        return r["stats"]["n_hits"]
+
+    t_step, _ = _time_steps(torch, step_batched, args.steps, args.warmup)
+    timed = stats[-args.steps:]
+    assert all(s["n_hits"] == hits_per_step for s in timed)
+    kernel_ms = float(np.mean([s["kernel_ms"] for s in timed]))
+    call_ms = float(np.mean([s["device_ms"] for s in timed]))
+    value = hits_per_step / t_step
+    print(f"bench: batched {t_step * 1e3:.3f} ms/step, {value:.4g} hits/s, "
+          f"hit kernel {kernel_ms:.3f} ms", flush=True)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "hits/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_step * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "single_particle_sweep", "n_events": w.n_events,
+                   "particles_per_event": 1, "mix_e_gamma_pi": [0.4, 0.2, 0.4],
+                   "energy_MeV": "log-uniform 1e3-4e6", "abs_eta_max": 2.5, "seed": w.seed,
+                   "hit_energy_scale_MeV": w.hit_energy_scale, "n_cells": geo["n_cells"],
+                   "mode": "batched", "outputs": "compact (cell_id, E) per event",
+                   "hits_per_step": hits_per_step},
+        "events_per_s": w.n_events / t_step,
+        "device_ms_per_call": call_ms,
+        "geometry_param_load_ms": load_ms,
+    }
+    # roofline of the dominant kernel (the persistent hit kernel)
+    ops = OPS_PER_HIT * hits_per_step
+    achieved = ops / (kernel_ms * 1e-3)
+    line["roofline"] = {"kernel": "k_hits", "bound": "alu", "achieved": achieved / 1e12,
+                        "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tops/s",
+                        "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None,
+                        "ops_per_hit": OPS_PER_HIT, "hits_per_launch": hits_per_step,
+                        "kernel_ms": kernel_ms}
+
+    if not args.only_headline:
+        # -------------------------------------------- per-event launch form
+        pe_steps = max(1, min(2, args.steps))
+        stats.clear()
+
+        def step_per_event():
+            r = sim.simulate_events(dp, doff, w.seed, mode="per_event", outputs=("compact",),
+                                    cell_capacity=cap, out=out)
+            return r["stats"]["n_hits"]
+
+        t_pe, res = _time_steps(torch, step_per_event, pe_steps, 1)
+        assert all(h == hits_per_step for h in res)
+        line["per_event_launch"] = {"ms_per_step": t_pe * 1e3,
+                                    "hits_per_s": hits_per_step / t_pe,
+                                    "events_per_s": w.n_events / t_pe, "steps": pe_steps}
+        line["batched_over_per_event"] = t_pe / t_step
+        print(f"bench: per-event {t_pe * 1e3:.1f} ms/step -> batched is "
+              f"{t_pe / t_step:.1f}x faster", flush=True)
+
+        # ---------------------------------------- forward + backward (64 pions)
+        wd = W.single_pion_diff()
+        dpd = particles_to_device(wd.particles, dev)
+        doffd = torch.from_numpy(wd.event_offsets).to(dev)
+        C = geo["n_cells"]
+        base = sim.simulate_events(dpd, doffd, wd.seed, outputs=("dense", "elayer"))
+        el = base["elayer"]
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(wd.seed)
+        pert = (el * (1 + 0.2 * torch.randn(el.shape, generator=gen, device=dev))).clamp_min(0)
+        target = sim.simulate_events(dpd, doffd, wd.seed, outputs=("dense",),
+                                     elayer_override=pert)["cells"]
+        dense_out = {"cells": torch.empty((wd.n_events, C), dtype=torch.float32, device=dev)}
+        times = {"fwd": 0.0, "bwd": 0.0}
+        nh = [0]
+
+        def step_fb():
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            r = sim.simulate_events(dpd, doffd, wd.seed, outputs=("dense",), elayer_override=el,
+                                    out=dense_out)
+            g = 2.0 * (r["cells"] - target)
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            ge, gw = sim.backward(dpd, doffd, wd.seed, g, elayer_override=el)
+            torch.cuda.synchronize()
+            times["fwd"] += b - a
+            times["bwd"] += time.perf_counter() - b
+            nh[0] = r["stats"]["n_hits"]
+            return nh[0]
+
+        for _ in range(args.warmup):
+            step_fb()
+        times["fwd"] = times["bwd"] = 0.0
+        t_fb, _ = _time_steps(torch, step_fb, args.steps, 0)
+        line["fwd_bwd"] = {"workload": "single_pion_diff", "n_events": wd.n_events,
+                           "hits_per_step": nh[0], "hits_per_s": nh[0] / t_fb,
+                           "t_fwd_ms": times["fwd"] / args.steps * 1e3,
+                           "t_bwd_ms": times["bwd"] / args.steps * 1e3}
+        print(f"bench: fwd+bwd {nh[0] / t_fb:.4g} hits/s", flush=True)
+
+        # ---------------------------------------- multi-particle workloads
+        others = {}
+        for wo in (W.hard_scatter(), W.pileup()):
+            dpo, doffo, outo, capo, qo = prepare(wo)
+
+            def step_o():
+                r = sim.simulate_events(dpo, doffo, wo.seed, outputs=("compact",),
+                                        cell_capacity=capo, out=outo,
+                                        hit_energy_scale=wo.hit_energy_scale)
+                return r["stats"]["n_hits"]
+
+            n_o = max(2, args.steps // 2)
+            t_o, _ = _time_steps(torch, step_o, n_o, 1)
+            others[wo.name] = {"hits_per_step": qo["n_hits"], "ms_per_step": t_o * 1e3,
+                               "hits_per_s": qo["n_hits"] / t_o,
+                               "events_per_s": wo.n_events / t_o,
+                               "hit_energy_scale_MeV": wo.hit_energy_scale}
+            print(f"bench: {wo.name} {qo['n_hits'] / t_o:.4g} hits/s", flush=True)
+            del dpo, doffo, outo
+        line["other_workloads"] = others
+
+    # ------------------------------------------------- CPU oracle baseline
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        go, po = oracle.Geometry(geo), oracle.Param(par)
+        t0 = time.perf_counter()
+        ref = oracle.simulate(go, po, w.particles, w.event_offsets, w.seed)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": ref["n_hits_total"] / dt, "unit": "hits/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"the whole {w.name} workload ({w.n_events} events, "
+                                          f"{ref['n_hits_total']} hits), one thread, {dt:.1f} s"}
+        print(f"bench: oracle {ref['n_hits_total'] / dt:.4g} hits/s on 1 core", flush=True)
+
+    sim.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

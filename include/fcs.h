@@ -194,7 +194,8 @@ typedef struct {
                                    device pointers (else host)              */
     int32_t outputs_on_device;  /* every output pointer is a device pointer
                                    (else host; copied back before return)   */
-    int32_t reserved;
+    int32_t profile;            /* 1: time the hit kernel with HIP events on
+                                   the stream it runs on (out->kernel_ms)    */
     const float *elayer_override; /* [N * n_layers] or NULL: energies used for
                                    Ehit; hit counts still come from the
                                    particle's own layer energies            */
@@ -241,6 +242,8 @@ typedef struct {
     int64_t required_hit_capacity;
     int64_t n_work_items;           /* chunks + tiles of the last launch     */
     double device_ms;               /* GPU time of the call (hipEvents)      */
+    double kernel_ms;               /* with opt->profile: summed duration of
+                                       the hit kernel launches              */
 } fcs_sim_output;
 
 /* Simulate n_events events.  particles[N] are grouped by event:

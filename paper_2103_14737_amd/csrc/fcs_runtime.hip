@@ -33,11 +33,11 @@ struct DevBuf {
 
 struct GraphKey {
     long long n_particles, n_events;
-    int dense, validate, grid;
+    int dense, validate, grid, profile;
     bool operator<(const GraphKey& o) const
     {
-        return std::tie(n_particles, n_events, dense, validate, grid) <
-               std::tie(o.n_particles, o.n_events, o.dense, o.validate, o.grid);
+        return std::tie(n_particles, n_events, dense, validate, grid, profile) <
+               std::tie(o.n_particles, o.n_events, o.dense, o.validate, o.grid, o.profile);
     }
 };
 
@@ -50,6 +50,7 @@ struct fcs_ctx {
     char name[64] = {0};
     hipStream_t stream = nullptr;
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_in = nullptr;
+    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the hit kernel
     std::string err = "no error";
     long long held = 0;
 
@@ -206,6 +207,7 @@ int fcs_create(fcs_ctx** out, int device)
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
         hipHostMalloc((void**)&c->h_params, sizeof(Params)) != hipSuccess ||
         hipHostMalloc((void**)&c->h_ctr, sizeof(Counters)) != hipSuccess) {
         fcs_destroy(c);
@@ -246,6 +248,8 @@ void fcs_destroy(fcs_ctx* c)
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_k0) (void)hipEventDestroy(c->ev_k0);
+    if (c->ev_k1) (void)hipEventDestroy(c->ev_k1);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -583,7 +587,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
 
 // Enqueue the launch sequence of one batch on c->stream (all kernels read
 // the device Params block, so the sequence can be captured and replayed).
-void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, bool compact, int grid)
+void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, bool profile, int grid)
 {
     const Params* dP = (const Params*)c->w_params.p;
     hipStream_t s = c->stream;
@@ -597,8 +601,9 @@ void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, bool 
     hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
     hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, s, dP);
     hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
+    if (profile) (void)hipEventRecord(c->ev_k0, s);
     hipLaunchKernelGGL(fcsk::k_hits, dim3(grid), dim3(fcsk::kBlock), 0, s, dP);
-    (void)compact;
+    if (profile) (void)hipEventRecord(c->ev_k1, s);
     const unsigned nw = grid_for(P.n_events * P.n_seg, fcsk::kBlock / fcsk::kWave);
     hipLaunchKernelGGL(fcsk::k_seg_count, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
     hipLaunchKernelGGL(fcsk::k_seg_reduce, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
@@ -622,7 +627,7 @@ int counters_error(fcs_ctx* c, const Counters& k)
 int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
               const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
               float* dense_out, const fcs_sim_output* dout, bool want_hits, bool validate,
-              bool use_graph, Counters* res)
+              bool use_graph, bool profile, Counters* res, double* kernel_ms)
 {
     const int grid = c->n_cu * tu.wg_per_cu;
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -632,13 +637,14 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, P, sizeof(Params), hipMemcpyHostToDevice, c->stream));
         const bool dense = dense_out != nullptr;
         if (use_graph) {
-            GraphKey key{sh.n_particles, sh.n_events, dense ? 1 : 0, validate ? 1 : 0, grid};
+            GraphKey key{sh.n_particles, sh.n_events, dense ? 1 : 0, validate ? 1 : 0, grid,
+                         profile ? 1 : 0};
             auto it = c->graphs.find(key);
             if (it == c->graphs.end()) {
                 hipGraph_t g = nullptr;
                 hipGraphExec_t ge = nullptr;
                 HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                enqueue_batch(c, *P, dense, validate, true, grid);
+                enqueue_batch(c, *P, dense, validate, profile, grid);
                 HIPCHK(c, hipStreamEndCapture(c->stream, &g));
                 HIPCHK(c, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
                 (void)hipGraphDestroy(g);
@@ -646,7 +652,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             }
             HIPCHK(c, hipGraphLaunch(it->second, c->stream));
         } else {
-            enqueue_batch(c, *P, dense, validate, true, grid);
+            enqueue_batch(c, *P, dense, validate, profile, grid);
             HIPCHK(c, hipGetLastError());
         }
         HIPCHK(c, hipMemcpyAsync(c->h_ctr, c->w_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
@@ -655,6 +661,11 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         if ((res->error & fcsk::kErrChunkCap) && attempt == 0) {
             c->chunk_cap = (long long)res->need_chunks + 1024;
             continue;
+        }
+        if (profile && kernel_ms) {
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev_k0, c->ev_k1));
+            *kernel_ms += ms;
         }
         return counters_error(c, *res);
     }
@@ -851,6 +862,8 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
 
     HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
     long long hits = 0, hits_out = 0, nnz = 0, items = 0;
+    double kms = 0.0;
+    const bool profile = o->profile != 0;
     if (N == 0) {
         // no particles: zero outputs only
         if (d.cells) HIPCHK(c, hipMemsetAsync(d.cells, 0, (size_t)n_events * C * 4, c->stream));
@@ -861,7 +874,7 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
         Shape sh{N, 0, n_events, 0, 0, 0};
         Counters k;
         rc = run_range(c, o, tu, sh, in.d_particles, in.d_evoff, in.d_override, d.cells, &d,
-                       want_hits, in.validate_on_device, o->use_graph != 0, &k);
+                       want_hits, in.validate_on_device, o->use_graph != 0, profile, &k, &kms);
         if (rc) return rc;
         hits = k.hits_total;
         hits_out = k.hits_out;
@@ -890,7 +903,7 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
             const float* dov = in.d_override ? in.d_override + p0 * L : nullptr;
             Counters k;
             rc = run_range(c, o, tu, sh, dp, in.d_evoff + e, dov, de.cells, &de, want_hits,
-                           in.validate_on_device, false, &k);
+                           in.validate_on_device, false, profile, &k, &kms);
             if (rc) return rc;
             hits += k.hits_total;
             hits_out += k.hits_out;
@@ -915,6 +928,7 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
     out->required_hit_capacity = hits;
     out->n_work_items = items;
     out->device_ms = ms;
+    out->kernel_ms = kms;
 
     if (host_out) {
         if (f & FCS_OUT_DENSE)

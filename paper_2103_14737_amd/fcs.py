@@ -74,7 +74,7 @@ class FcsSimOptions(C.Structure):
                 ("chunk_hits", C.c_int32), ("big_task_hits", C.c_int32),
                 ("tile_hits", C.c_int32), ("wg_per_cu", C.c_int32), ("use_graph", C.c_int32),
                 ("inputs_on_device", C.c_int32), ("outputs_on_device", C.c_int32),
-                ("reserved", C.c_int32), ("elayer_override", _vp), ("stream", _vp)]
+                ("profile", C.c_int32), ("elayer_override", _vp), ("stream", _vp)]
 
 
 class FcsSimOutput(C.Structure):
@@ -85,7 +85,8 @@ class FcsSimOutput(C.Structure):
                 ("elayer", _vp), ("n_hits", C.c_int64), ("n_hits_out_of_acceptance", C.c_int64),
                 ("n_tasks", C.c_int64), ("n_cells_nonzero", C.c_int64),
                 ("required_cell_capacity", C.c_int64), ("required_hit_capacity", C.c_int64),
-                ("n_work_items", C.c_int64), ("device_ms", C.c_double)]
+                ("n_work_items", C.c_int64), ("device_ms", C.c_double),
+                ("kernel_ms", C.c_double)]
 
 
 class FcsSizes(C.Structure):
@@ -262,7 +263,8 @@ class Simulator:
                         mode="batched", outputs=("compact",), hit_energy_scale=100.0,
                         nhit_cap=20000, min_layer_energy=1e-6, chunk_hits=0, big_task_hits=0,
                         tile_hits=0, wg_per_cu=0, use_graph=True, elayer_override=None,
-                        cell_capacity=None, hit_capacity=None, n_particles=None, out=None):
+                        cell_capacity=None, hit_capacity=None, n_particles=None, out=None,
+                        profile=False):
         """Run fcs_simulate_events.  Returns a dict of the requested outputs
         (numpy for host inputs, torch CUDA tensors for device inputs) and the
         statistics.  Capacities default to the sizes fcs_query_sizes
@@ -271,6 +273,7 @@ class Simulator:
         o = self._options(seed, event_index_base, mode, outputs, hit_energy_scale, nhit_cap,
                           min_layer_energy, chunk_hits, big_task_hits, tile_hits, wg_per_cu,
                           use_graph, dev, ov, stream)
+        o.profile = 1 if profile else 0
         N = (int(p.shape[0]) if dev else len(p)) if n_particles is None else n_particles
         L = self.n_layers
         need_sizes = (("compact" in outputs and cell_capacity is None) or
@@ -321,7 +324,8 @@ class Simulator:
                                          C.byref(so))
         self._check(rc)
         stats = {k: getattr(so, k) for k in ("n_hits", "n_hits_out_of_acceptance", "n_tasks",
-                                             "n_cells_nonzero", "n_work_items", "device_ms")}
+                                             "n_cells_nonzero", "n_work_items", "device_ms",
+                                             "kernel_ms")}
         nnz = so.n_cells_nonzero
         if "compact" in outputs:
             res["cell_ids"] = res["cell_ids"][:nnz]

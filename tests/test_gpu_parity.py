@@ -179,7 +179,9 @@ def test_edge_cases(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
             (22, 2.0e5, 2.49, -3.0)]
     parts = _particles(rows)
     # events: [0,2), empty, [2,5), [5,7)
-    w = W.Workload("edges", 77, parts, np.array([0, 2, 2, 5, 7], np.int64))
+    # 20 MeV per expected hit so that the 4 TeV electron reaches the hit cap
+    w = W.Workload("edges", 77, parts, np.array([0, 2, 2, 5, 7], np.int64),
+                   hit_energy_scale=20.0)
     for mode in ("batched", "per_event"):
         r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode)
         check_parity(r, ref, geo, label=f"edges {mode}")
