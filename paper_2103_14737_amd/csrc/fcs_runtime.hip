@@ -33,11 +33,11 @@ struct DevBuf {
 
 struct GraphKey {
     long long n_particles, n_events;
-    int dense, validate, grid, profile;
+    int dense, validate, grid, part;
     bool operator<(const GraphKey& o) const
     {
-        return std::tie(n_particles, n_events, dense, validate, grid, profile) <
-               std::tie(o.n_particles, o.n_events, o.dense, o.validate, o.grid, o.profile);
+        return std::tie(n_particles, n_events, dense, validate, grid, part) <
+               std::tie(o.n_particles, o.n_events, o.dense, o.validate, o.grid, o.part);
     }
 };
 
@@ -585,31 +585,60 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     return FCS_OK;
 }
 
-// Enqueue the launch sequence of one batch on c->stream (all kernels read
-// the device Params block, so the sequence can be captured and replayed).
-void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, bool profile, int grid)
+// Enqueue the launch sequence of one batch on c->stream.  All kernels read
+// the device Params block, so a sequence can be captured once and replayed.
+// part: 0 = everything, 1 = up to the work queue, 2 = the hit kernel,
+// 3 = compaction and reset.
+enum Part { kAll = 0, kPre = 1, kHits = 2, kPost = 3 };
+
+void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, int grid, int part)
 {
     const Params* dP = (const Params*)c->w_params.p;
     hipStream_t s = c->stream;
-    hipLaunchKernelGGL(fcsk::k_reset_counters, dim3(1), dim3(64), 0, s, dP);
-    if (validate)
-        hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(P.n_particles, P.n_events), 256)),
-                           dim3(256), 0, s, dP);
-    if (dense) hipLaunchKernelGGL(fcsk::k_fill_dense, dim3(2048), dim3(256), 0, s, dP);
-    const int ppb = fcsk::kBlock / P.n_layers;
-    hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(P.n_particles, ppb)), dim3(fcsk::kBlock), 0, s, dP);
-    hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
-    hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, s, dP);
-    hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
-    if (profile) (void)hipEventRecord(c->ev_k0, s);
-    hipLaunchKernelGGL(fcsk::k_hits, dim3(grid), dim3(fcsk::kBlock), 0, s, dP);
-    if (profile) (void)hipEventRecord(c->ev_k1, s);
-    const unsigned nw = grid_for(P.n_events * P.n_seg, fcsk::kBlock / fcsk::kWave);
-    hipLaunchKernelGGL(fcsk::k_seg_count, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
-    hipLaunchKernelGGL(fcsk::k_seg_reduce, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
-    hipLaunchKernelGGL(fcsk::k_seg_top, dim3(1), dim3(1024), 0, s, dP);
-    hipLaunchKernelGGL(fcsk::k_seg_apply, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
-    hipLaunchKernelGGL(fcsk::k_seg_write, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
+    if (part == kAll || part == kPre) {
+        hipLaunchKernelGGL(fcsk::k_reset_counters, dim3(1), dim3(64), 0, s, dP);
+        if (validate)
+            hipLaunchKernelGGL(fcsk::k_validate,
+                               dim3(grid_for(std::max(P.n_particles, P.n_events), 256)), dim3(256),
+                               0, s, dP);
+        if (dense) hipLaunchKernelGGL(fcsk::k_fill_dense, dim3(2048), dim3(256), 0, s, dP);
+        const int ppb = fcsk::kBlock / P.n_layers;
+        hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(P.n_particles, ppb)), dim3(fcsk::kBlock), 0,
+                           s, dP);
+        hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
+    }
+    if (part == kAll || part == kHits)
+        hipLaunchKernelGGL(fcsk::k_hits, dim3(grid), dim3(fcsk::kBlock), 0, s, dP);
+    if (part == kAll || part == kPost) {
+        const unsigned nw = grid_for(P.n_events * P.n_seg, fcsk::kBlock / fcsk::kWave);
+        hipLaunchKernelGGL(fcsk::k_seg_count, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_seg_reduce, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_seg_top, dim3(1), dim3(1024), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_seg_apply, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_seg_write, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
+    }
+}
+
+// instantiate (once per batch shape) and launch the graph of one part
+int launch_graph(fcs_ctx* c, const Params& P, const GraphKey& key, bool dense, bool validate,
+                 int grid, int part)
+{
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_batch(c, P, dense, validate, grid, part);
+        HIPCHK(c, hipStreamEndCapture(c->stream, &g));
+        const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(c, e);
+        it = c->graphs.emplace(key, ge).first;
+    }
+    HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+    return FCS_OK;
 }
 
 int counters_error(fcs_ctx* c, const Counters& k)
@@ -636,23 +665,27 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         if (rc) return rc;
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, P, sizeof(Params), hipMemcpyHostToDevice, c->stream));
         const bool dense = dense_out != nullptr;
-        if (use_graph) {
-            GraphKey key{sh.n_particles, sh.n_events, dense ? 1 : 0, validate ? 1 : 0, grid,
-                         profile ? 1 : 0};
-            auto it = c->graphs.find(key);
-            if (it == c->graphs.end()) {
-                hipGraph_t g = nullptr;
-                hipGraphExec_t ge = nullptr;
-                HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                enqueue_batch(c, *P, dense, validate, profile, grid);
-                HIPCHK(c, hipStreamEndCapture(c->stream, &g));
-                HIPCHK(c, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-                (void)hipGraphDestroy(g);
-                it = c->graphs.emplace(key, ge).first;
-            }
-            HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+        GraphKey key{sh.n_particles, sh.n_events, dense ? 1 : 0, validate ? 1 : 0, grid, kAll};
+        if (use_graph && !profile) {
+            if ((rc = launch_graph(c, *P, key, dense, validate, grid, kAll))) return rc;
         } else {
-            enqueue_batch(c, *P, dense, validate, profile, grid);
+            // profiled: the hit kernel is launched on its own between two event
+            // records (graphs for the parts before and after it)
+            if (use_graph) {
+                key.part = kPre;
+                if ((rc = launch_graph(c, *P, key, dense, validate, grid, kPre))) return rc;
+            } else {
+                enqueue_batch(c, *P, dense, validate, grid, kPre);
+            }
+            if (profile) HIPCHK(c, hipEventRecord(c->ev_k0, c->stream));
+            enqueue_batch(c, *P, dense, validate, grid, kHits);
+            if (profile) HIPCHK(c, hipEventRecord(c->ev_k1, c->stream));
+            if (use_graph) {
+                key.part = kPost;
+                if ((rc = launch_graph(c, *P, key, dense, validate, grid, kPost))) return rc;
+            } else {
+                enqueue_batch(c, *P, dense, validate, grid, kPost);
+            }
             HIPCHK(c, hipGetLastError());
         }
         HIPCHK(c, hipMemcpyAsync(c->h_ctr, c->w_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
