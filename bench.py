@@ -63,6 +63,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="time only the headline batched workload (for profiling)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default tuning instead of the autotuner's")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="chunk_hits,big_task_hits,tile_hits,wg_per_cu (skips the autotuner)")
+    ap.add_argument("--workload", default="single_particle_sweep",
+                    choices=["single_particle_sweep", "hard_scatter", "pileup"],
+                    help="headline workload to time (the other choices are for profiling)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -99,15 +108,27 @@ def main():
         return dp, doff, out, cap, q
 
     # ------------------------------------------------ headline: batched sweep
-    w = W.single_particle_sweep()
+    w = W.CONFIGS[args.workload]()
     dp, doff, out, cap, q = prepare(w)
     hits_per_step = q["n_hits"]
     print(f"bench: {w.name}: {w.n_events} events, {hits_per_step} hits per step", flush=True)
+    tuning = {}
+    if args.tuning:
+        c_, b_, t_, w_ = (int(x) for x in args.tuning.split(","))
+        tuning = dict(chunk_hits=c_, big_task_hits=b_, tile_hits=t_, wg_per_cu=w_)
+    elif not args.no_autotune:
+        from paper_2103_14737_amd import autotune
+        t0 = time.perf_counter()
+        tuning = autotune.tune(sim, dp, doff, w.seed, out=out, cell_capacity=cap,
+                               hit_energy_scale=w.hit_energy_scale,
+                               verbose=bool(os.environ.get("FCS_TUNE_VERBOSE")))
+        print(f"bench: autotuned {tuning} in {time.perf_counter() - t0:.1f} s", flush=True)
     stats = []
 
     def step_batched(profile=True):
         r = sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap,
-                                out=out, profile=profile)
+                                out=out, profile=profile, hit_energy_scale=w.hit_energy_scale,
+                                **tuning)
         stats.append(r["stats"])
         return r["stats"]["n_hits"]
 
@@ -125,12 +146,11 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_step * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "single_particle_sweep", "n_events": w.n_events,
-                   "particles_per_event": 1, "mix_e_gamma_pi": [0.4, 0.2, 0.4],
-                   "energy_MeV": "log-uniform 1e3-4e6", "abs_eta_max": 2.5, "seed": w.seed,
+        "config": {"workload": args.workload, "n_events": w.n_events,
+                   "n_particles": w.n_particles, "seed": w.seed,
                    "hit_energy_scale_MeV": w.hit_energy_scale, "n_cells": geo["n_cells"],
                    "mode": "batched", "outputs": "compact (cell_id, E) per event",
-                   "hits_per_step": hits_per_step},
+                   "hits_per_step": hits_per_step, "tuning": tuning or "library defaults"},
         "events_per_s": w.n_events / t_step,
         "device_ms_per_call": call_ms,
         "geometry_param_load_ms": load_ms,
@@ -144,14 +164,14 @@ def main():
                         "ops_per_hit": OPS_PER_HIT, "hits_per_launch": hits_per_step,
                         "kernel_ms": kernel_ms}
 
-    if not args.only_headline:
+    if not args.only_headline and args.workload == "single_particle_sweep":
         # -------------------------------------------- per-event launch form
         pe_steps = max(1, min(2, args.steps))
         stats.clear()
 
         def step_per_event():
             r = sim.simulate_events(dp, doff, w.seed, mode="per_event", outputs=("compact",),
-                                    cell_capacity=cap, out=out)
+                                    cell_capacity=cap, out=out, **tuning)
             return r["stats"]["n_hits"]
 
         t_pe, res = _time_steps(torch, step_per_event, pe_steps, 1)
@@ -224,6 +244,17 @@ def main():
             print(f"bench: {wo.name} {qo['n_hits'] / t_o:.4g} hits/s", flush=True)
             del dpo, doffo, outo
         line["other_workloads"] = others
+
+    if args.copy_probe_mb:
+        # a plain device copy of known size: the HBM counters of the profiled
+        # kernels are scaled by what the same counters read for this copy
+        n = args.copy_probe_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = n * 4
 
     # ------------------------------------------------- CPU oracle baseline
     if not args.no_cpu_baseline:

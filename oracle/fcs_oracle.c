@@ -608,10 +608,16 @@ int oracle_simulate(const og_geom *G, const og_param *P, const og_particle *part
                 }
             }
         }
-        /* gather the event's hit cells in ascending cell order */
+        /* gather the event's hit cells in ascending cell order (cells whose
+         * hits all carry zero energy, possible only with an override, are
+         * left out) */
         for (int64_t c = 0, done = 0; c < C && done < n_touched; ++c) {
             if (cellN[c] == 0) continue;
             done++;
+            if (cellE[c] == 0.0) {
+                cellN[c] = 0;
+                continue;
+            }
             if (ncell_out < out->cell_cap && out->cell_idx) {
                 out->cell_idx[ncell_out] = (int32_t)c;
                 out->cell_e[ncell_out] = cellE[c];

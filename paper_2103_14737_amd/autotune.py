@@ -1,0 +1,90 @@
+"""Autotuner for the batched launch: picks chunk size, large-task threshold,
+tile size and persistent workgroups per CU for a workload by timing the
+candidates on the device, and caches the choice in a JSON file keyed by the
+device and a signature of the workload.
+
+The tuning never changes hit counts, hit positions or cell indices (only the
+FP32 summation order of cell energies), so any candidate is a valid result.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fcs_mi355x_tune.json")
+
+# (chunk_hits, big_task_hits, tile_hits, wg_per_cu)
+CANDIDATES = [
+    (c, b, t, w)
+    for c in (512, 1024, 2048, 4096)
+    for b in (32, 64, 128)
+    for t in (256, 512)
+    for w in (4, 5, 8)
+    if b <= t
+]
+
+
+def signature(n_events, n_particles, n_hits, n_cells, outputs):
+    """Workloads with the same event count, particle count, hit count (to
+    within a factor of two) and outputs share a tuning."""
+    hb = int(max(n_hits, 1)).bit_length()
+    return f"ev{n_events}-p{n_particles}-h2^{hb}-c{n_cells}-{'+'.join(sorted(outputs))}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, data):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(sim, particles, event_offsets, seed, *, outputs=("compact",), hit_energy_scale=100.0,
+         candidates=None, reps=3, cache_path=DEFAULT_CACHE, force=False, out=None,
+         cell_capacity=None, verbose=False):
+    """Return the best tuning dict for this workload (cached)."""
+    import torch
+    info = sim.info()
+    q = sim.query_sizes(particles, event_offsets, seed, hit_energy_scale=hit_energy_scale)
+    n_events = int(event_offsets.shape[0]) - 1
+    n_particles = int(particles.shape[0])
+    key = f"{info['device_name']}-cu{info['compute_units']}/" + signature(
+        n_events, n_particles, q["n_hits"], info["n_cells"], outputs)
+    cache = _load(cache_path)
+    if not force and key in cache:
+        return dict(cache[key]["tuning"])
+    cands = candidates or CANDIDATES
+    cap = q["max_cells"] if cell_capacity is None else cell_capacity
+    results = []
+    for (c, b, t, w) in cands:
+        kw = dict(chunk_hits=c, big_task_hits=b, tile_hits=t, wg_per_cu=w)
+        run = lambda: sim.simulate_events(particles, event_offsets, seed, outputs=outputs,  # noqa: E731
+                                          hit_energy_scale=hit_energy_scale,
+                                          cell_capacity=cap, out=out, **kw)
+        run()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        results.append((ts[len(ts) // 2], kw))
+        if verbose:
+            print(f"autotune {kw}: {ts[len(ts) // 2] * 1e3:.3f} ms", flush=True)
+    results.sort(key=lambda r: r[0])
+    best_t, best = results[0]
+    cache = _load(cache_path)
+    cache[key] = {"tuning": best, "ms": best_t * 1e3, "n_candidates": len(results)}
+    _store(cache_path, cache)
+    return dict(best)

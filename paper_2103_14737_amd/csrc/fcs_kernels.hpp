@@ -22,12 +22,13 @@ namespace fcsk {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kBins = 256;
-constexpr int kHashSlots = 2048;          // LDS cell accumulator of one chunk
 constexpr int kHashProbes = 16;
 constexpr uint32_t kEmpty = 0xffffffffu;
-constexpr int kTileMax = 4096;            // max hits of one packed tile
+constexpr int kTileMax = 512;             // max hits of one packed tile (one wave)
 constexpr int kScanItems = 8;             // items per thread in scans
 constexpr int kScanBlock = kBlock * kScanItems;
+constexpr int kQueues = 8;                // work-queue ranges (one ticket each)
+constexpr int kQueueStride = 64;          // ints between tickets: one 256-byte line each
 
 struct Particle {
     int32_t pdg;
@@ -45,7 +46,6 @@ struct Counters {
     int32_t n_small_hits;
     int32_t n_small_tasks;
     int32_t n_tiles;
-    int32_t ticket;
     int32_t error;        // bit set, see kErr*
     int32_t need_chunks;  // chunk entries required when over capacity
     int32_t pad;
@@ -57,6 +57,7 @@ enum : int32_t {
     kErrOffsets = 4,      // malformed event offsets
     kErrTooManyHits = 8,  // more than 2^31-1 hits in one batch
     kErrChunkCap = 16,    // chunk list capacity exceeded (internal retry)
+    kErrOverride = 32,    // negative or non-finite layer-energy override
 };
 
 struct Params {
@@ -113,8 +114,9 @@ struct Params {
     int32_t* blk_offs;   // [n_scan_blocks * 4]
     int32_t* task_hoff;  // [n_tasks] when want_hits
     int4* chunks;        // [chunk_cap] (task key, first hit, count, -)
-    int32_t* small_key;  // [n_tasks]
-    int32_t* small_off;  // [n_tasks]
+    int4* small_rec;     // [2 * n_tasks] records of the small tasks
+    const int4* geo_layers;   // [n_layers * 3] per-layer lookup records
+    const int4* geo_regions;  // [n_layers * n_regions * 2] per-region records
     int32_t* tile_first; // [n_tasks + 1]
     float* cells;        // [n_events * n_cells] accumulator
     uint8_t* flags;      // [n_events * n_blk]
@@ -122,6 +124,7 @@ struct Params {
     int32_t* seg_off;    // [n_events * n_seg]
     int32_t* seg_blk;    // [n_seg_blocks]
     Counters* ctr;
+    int32_t* queue;      // [kQueues * kQueueStride * 2]: tickets, then drained flags
     // outputs (device)
     float* out_elayer;
     int32_t* out_counts;
@@ -147,6 +150,75 @@ struct Params {
 };
 
 // ------------------------------------------------------------ utilities ---
+// Pointers read from the Params block are generic; G() retypes them into the
+// global address space so that accesses compile to global (not flat) memory
+// instructions.  Atomics on such pointers go through the helpers below.
+#define FCS_AS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ FCS_AS_GLOBAL T* G(T* p)
+{
+    return (FCS_AS_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const FCS_AS_GLOBAL T* G(const T* p)
+{
+    return (const FCS_AS_GLOBAL T*)p;
+}
+
+// relaxed device-scope atomics on global memory; the FP adds use the native
+// instructions (denormal inputs are outside the value ranges used here)
+__device__ __forceinline__ void gadd(FCS_AS_GLOBAL float* p, float v)
+{
+    [[clang::atomic(ignore_denormal_mode)]] {
+        (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+__device__ __forceinline__ void gadd(FCS_AS_GLOBAL double* p, double v)
+{
+    [[clang::atomic(ignore_denormal_mode)]] {
+        (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+// 16-byte records (particles, work items, scan partials) move as native int
+// vectors, which load and store from the global address space directly
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ Particle load_particle(const Particle* base, long long i)
+{
+    const v4i v = ((const FCS_AS_GLOBAL v4i*)base)[i];
+    Particle p;
+    p.pdg = v.x;
+    p.e = __int_as_float(v.y);
+    p.eta = __int_as_float(v.z);
+    p.phi = __int_as_float(v.w);
+    return p;
+}
+__device__ __forceinline__ int4 load_i4(const int4* base, long long i)
+{
+    const v4i v = ((const FCS_AS_GLOBAL v4i*)base)[i];
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void store_i4(int4* base, long long i, int4 x)
+{
+    v4i v;
+    v.x = x.x;
+    v.y = x.y;
+    v.z = x.z;
+    v.w = x.w;
+    ((FCS_AS_GLOBAL v4i*)base)[i] = v;
+}
+
+template <typename T>
+__device__ __forceinline__ T gfetch_add(FCS_AS_GLOBAL T* p, T v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void gor(FCS_AS_GLOBAL T* p, T v)
+{
+    (void)__hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 template <typename T>
@@ -247,36 +319,6 @@ __device__ __forceinline__ double block_sum_ll_d(double v)
     return t;
 }
 
-// inclusive max-scan of the tile owner marks, T / 256 consecutive per thread
-__device__ __forceinline__ void owner_max_scan(uint16_t* s_owner, int* s_wmax, int T)
-{
-    const int tid = threadIdx.x;
-    const int per = T / kBlock;
-    int m = 0;
-    for (int k = 0; k < per; ++k) {
-        const int v = s_owner[tid * per + k];
-        m = v > m ? v : m;
-    }
-    int wm = m;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int o = __shfl_up(wm, d, kWave);
-        if (lane_id() >= d) wm = o > wm ? o : wm;
-    }
-    int excl = __shfl_up(wm, 1, kWave);
-    if (lane_id() == 0) excl = 0;
-    if (lane_id() == kWave - 1) s_wmax[tid / kWave] = wm;
-    __syncthreads();
-    for (int w = 0; w < tid / kWave; ++w) excl = s_wmax[w] > excl ? s_wmax[w] : excl;
-    int run = excl;
-    for (int k = 0; k < per; ++k) {
-        const int v = s_owner[tid * per + k];
-        run = v > run ? v : run;
-        s_owner[tid * per + k] = (uint16_t)run;
-    }
-    __syncthreads();
-}
-
 // ---------------------------------------------------- set selection (a1) ---
 __device__ __forceinline__ int select_set(const Params& P, int pdg, float e, float eta)
 {
@@ -284,15 +326,16 @@ __device__ __forceinline__ int select_set(const Params& P, int pdg, float e, flo
     const int t = apdg == 11 ? 0 : apdg == 22 ? 1 : apdg == 211 ? 2 : -1;
     if (t < 0) return -1;
     int ie = 0;
-    for (int k = 1; k < P.n_ebins; ++k) ie += (e >= P.e_edges[k]) ? 1 : 0;
+    for (int k = 1; k < P.n_ebins; ++k) ie += (e >= G(P.e_edges)[k]) ? 1 : 0;
     const float ae = fabsf(eta);
     int ih = 0;
-    for (int k = 1; k < P.n_etabins; ++k) ih += (ae >= P.eta_edges[k]) ? 1 : 0;
+    for (int k = 1; k < P.n_etabins; ++k) ih += (ae >= G(P.eta_edges)[k]) ? 1 : 0;
     return (t * P.n_ebins + ie) * P.n_etabins + ih;
 }
 
 // largest e with ev_off[e] <= gp
-__device__ __forceinline__ int find_event(const long long* ev_off, long long n_events, long long gp)
+template <typename Ptr>
+__device__ __forceinline__ int find_event(Ptr ev_off, long long n_events, long long gp)
 {
     long long lo = 0, hi = n_events - 1;
     while (lo < hi) {
@@ -324,7 +367,7 @@ __global__ void k_fill_dense(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
     const long long n = P.n_events * P.n_cells;
-    float* p = P.cells;
+    auto p = G(P.cells);
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
         p[i] = 0.0f;
@@ -332,6 +375,7 @@ __global__ void k_fill_dense(const Params* __restrict__ Pp)
 
 __global__ void k_reset_counters(const Params* __restrict__ Pp)
 {
+    for (int i = threadIdx.x; i < 2 * kQueues; i += blockDim.x) G(Pp->queue)[i * kQueueStride] = 0;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         Counters* c = Pp->ctr;
         c->hits_total = 0;
@@ -341,7 +385,6 @@ __global__ void k_reset_counters(const Params* __restrict__ Pp)
         c->n_small_hits = 0;
         c->n_small_tasks = 0;
         c->n_tiles = 0;
-        c->ticket = 0;
         c->error = 0;
         c->need_chunks = 0;
     }
@@ -392,7 +435,7 @@ __global__ void k_validate(const Params* __restrict__ Pp)
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int err = 0;
     if (i < P.n_particles) {
-        const Particle pt = P.particles[i];
+        const Particle pt = load_particle(P.particles, i);
         const int a = pt.pdg < 0 ? -pt.pdg : pt.pdg;
         if (a != 11 && a != 22 && a != 211) err |= kErrPdg;
         if (!(pt.e > 0.0f) || !isfinite(pt.e) || !isfinite(pt.eta) || !isfinite(pt.phi) ||
@@ -400,13 +443,13 @@ __global__ void k_validate(const Params* __restrict__ Pp)
             err |= kErrParticle;
     }
     if (i < P.n_events) {
-        if (P.ev_off[i] > P.ev_off[i + 1]) err |= kErrOffsets;
+        if (G(P.ev_off)[i] > G(P.ev_off)[i + 1]) err |= kErrOffsets;
     }
     if (i == 0) {
-        if (P.ev_off[0] != P.part_base || P.ev_off[P.n_events] != P.part_base + P.n_particles)
+        if (G(P.ev_off)[0] != P.part_base || G(P.ev_off)[P.n_events] != P.part_base + P.n_particles)
             err |= kErrOffsets;
     }
-    if (err) atomicOr(&P.ctr->error, err);
+    if (err) gor(&G(P.ctr)->error, err);
 }
 
 // ------------------------------------------- per-task setup (a1 - a3) ---
@@ -428,14 +471,14 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
     uint32_t pin = 0, evg = 0;
     double g = 0.0;
     if (active) {
-        pt = P.particles[gp];
-        ev = find_event(P.ev_off, P.n_events, P.part_base + gp);
-        pin = (uint32_t)(P.part_base + gp - P.ev_off[ev]);
+        pt = load_particle(P.particles, gp);
+        ev = find_event(G(P.ev_off), P.n_events, P.part_base + gp);
+        pin = (uint32_t)(P.part_base + gp - G(P.ev_off)[ev]);
         evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
         set = select_set(P, pt.pdg, pt.e, pt.eta);
         if (set >= 0) {
             const int t = set / (P.n_ebins * P.n_etabins);
-            g = gamma_draw((double)P.alpha[t * L + l], P.key0, P.key1, (uint32_t)l, pin, evg);
+            g = gamma_draw((double)G(P.alpha)[t * L + l], P.key0, P.key1, (uint32_t)l, pin, evg);
         }
     }
     g_s[tid] = g;
@@ -456,17 +499,22 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
             if (k > P.cap) k = P.cap;
             n = (int)k;
         }
-        const double e_used = P.elayer_override ? (double)P.elayer_override[t] : el;
+        double e_used = el;
+        if (G(P.elayer_override)) {
+            const float ov = G(P.elayer_override)[t];
+            if (!(ov >= 0.0f) || !isfinite(ov)) gor(&G(P.ctr)->error, (int)kErrOverride);
+            e_used = ov >= 0.0f ? (double)ov : 0.0;
+        }
         ehit = n > 0 ? (float)(e_used / (double)n) : 0.0f;
     }
-    P.task_n[t] = n;
-    P.task_ehit[t] = ehit;
-    if (P.out_elayer) P.out_elayer[t] = (float)el;
-    if (P.out_counts) P.out_counts[t] = n;
+    G(P.task_n)[t] = n;
+    G(P.task_ehit)[t] = ehit;
+    if (G(P.out_elayer)) G(P.out_elayer)[t] = (float)el;
+    if (G(P.out_counts)) G(P.out_counts)[t] = n;
     if (l == 0) {
-        P.part_ev[gp] = ev;
-        P.part_p[gp] = pin;
-        P.part_set[gp] = set;
+        G(P.part_ev)[gp] = ev;
+        G(P.part_p)[gp] = pin;
+        G(P.part_set)[gp] = set;
     }
 }
 
@@ -488,11 +536,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const Params* __restrict
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const long long t = base + k;
-        if (t < P.n_tasks) s = add4(s, task_terms(P, P.task_n[t]));
+        if (t < P.n_tasks) s = add4(s, task_terms(P, G(P.task_n)[t]));
     }
     int4 tot;
     (void)block_excl_scan4(s, tot);
-    if (threadIdx.x == 0) reinterpret_cast<int4*>(P.blk_sums)[blockIdx.x] = tot;
+    if (threadIdx.x == 0) store_i4(reinterpret_cast<int4*>(P.blk_sums), blockIdx.x, tot);
 }
 
 // one block: exclusive scan of the block sums; totals into the counters
@@ -509,7 +557,8 @@ __global__ __launch_bounds__(1024) void k_scan_top(const Params* __restrict__ Pp
     int4* out = reinterpret_cast<int4*>(P.blk_offs);
     for (int b0 = 0; b0 < nb; b0 += 1024) {
         const int b = b0 + tid;
-        const int4 v = b < nb ? in[b] : make_int4(0, 0, 0, 0);
+        int4 v = make_int4(0, 0, 0, 0);
+        if (b < nb) v = load_i4(in, b);
         long long x[4] = {v.x, v.y, v.z, v.w};
         long long inc[4];
         for (int c = 0; c < 4; ++c) inc[c] = wave_incl_scan<long long>(x[c]);
@@ -529,14 +578,15 @@ __global__ __launch_bounds__(1024) void k_scan_top(const Params* __restrict__ Pp
             o.y = (int)(carry_s[1] + off[1] + inc[1] - x[1]);
             o.z = (int)(carry_s[2] + off[2] + inc[2] - x[2]);
             o.w = (int)(carry_s[3] + off[3] + inc[3] - x[3]);
-            out[b] = o;
+            store_i4(out, b, o);
         }
         __syncthreads();
         if (tid < 4) carry_s[tid] += tot[tid];
         __syncthreads();
     }
+    if (tid < 2 * kQueues) G(P.queue)[tid * kQueueStride] = 0;
     if (tid == 0) {
-        Counters* c = P.ctr;
+        auto c = G(P.ctr);
         c->hits_total = carry_s[0];
         int err = 0;
         if (carry_s[0] > 2147483647LL) err |= kErrTooManyHits;
@@ -548,74 +598,110 @@ __global__ __launch_bounds__(1024) void k_scan_top(const Params* __restrict__ Pp
         c->n_small_hits = err ? 0 : (int)carry_s[2];
         c->n_small_tasks = err ? 0 : (int)carry_s[3];
         c->n_tiles = err ? 0 : (int)((carry_s[2] + P.tile_hits - 1) / P.tile_hits);
-        c->ticket = 0;
-        if (err) atomicOr(&c->error, err);
-        if (P.out_task_hoff && !err) P.out_task_hoff[P.n_tasks] = P.hit_base + carry_s[0];
+        if (err) gor(&c->error, err);
+        if (G(P.out_task_hoff) && !err) G(P.out_task_hoff)[P.n_tasks] = P.hit_base + carry_s[0];
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_write(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
-    if (P.ctr->error & (kErrTooManyHits | kErrChunkCap)) return;
+    if (G(P.ctr)->error & (kErrTooManyHits | kErrChunkCap)) return;
     const long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanItems;
     int nv[kScanItems];
     int4 s = make_int4(0, 0, 0, 0);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const long long t = base + k;
-        nv[k] = t < P.n_tasks ? P.task_n[t] : 0;
+        nv[k] = t < P.n_tasks ? G(P.task_n)[t] : 0;
         s = add4(s, task_terms(P, nv[k]));
     }
     int4 tot;
-    int4 run = add4(block_excl_scan4(s, tot), reinterpret_cast<const int4*>(P.blk_offs)[blockIdx.x]);
+    int4 run = add4(block_excl_scan4(s, tot), load_i4(reinterpret_cast<const int4*>(P.blk_offs), blockIdx.x));
     const int L = P.n_layers;
     for (int k = 0; k < kScanItems; ++k) {
         const long long t = base + k;
         if (t >= P.n_tasks) break;
         const int n = nv[k];
         const int4 d = task_terms(P, n);
-        if (P.want_hits) P.task_hoff[t] = run.x;
-        if (P.out_task_hoff) P.out_task_hoff[t] = P.hit_base + run.x;
+        if (P.want_hits) G(P.task_hoff)[t] = run.x;
+        if (G(P.out_task_hoff)) G(P.out_task_hoff)[t] = P.hit_base + run.x;
         const long long gp = t / L;
         const int key = (int)(gp * 64 + (t - gp * L));
         for (int c = 0; c < d.y; ++c) {
             const int first = c * P.chunk_hits;
             const int cnt = min(P.chunk_hits, n - first);
-            P.chunks[run.y + c] = make_int4(key, first, cnt, 0);
+            store_i4(P.chunks, run.y + c, make_int4(key, first, cnt, 0));
         }
         if (d.w) {
-            P.small_key[run.w] = key;
-            P.small_off[run.w] = run.z;
+            // two 16-byte records per small task: (first small hit, task key,
+            // Ehit bits, histogram) and (eta_p, phi_p, global event, particle
+            // in event)
+            const Particle pt = load_particle(P.particles, gp);
+            const int H = G(P.part_set)[gp] * L + (key & 63);
+            store_i4(P.small_rec, 2LL * run.w,
+                     make_int4(run.z, key, __float_as_int(G(P.task_ehit)[t]), H));
+            const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)G(P.part_ev)[gp]);
+            store_i4(P.small_rec, 2LL * run.w + 1,
+                     make_int4(__float_as_int(pt.eta), __float_as_int(pt.phi), (int)evg,
+                               (int)G(P.part_p)[gp]));
             const int T = P.tile_hits;
             const int q = (run.z + T - 1) / T;
-            if ((long long)q * T < (long long)run.z + n) P.tile_first[q] = run.w;
+            if ((long long)q * T < (long long)run.z + n) G(P.tile_first)[q] = run.w;
         }
         run = add4(run, d);
     }
 }
 
 // ------------------------------------------------------ the hit (a4 - a7) ---
-struct Region {
-    float eta_lo, inv_deta, phi_lo, inv_dphi;
-    int neta, nphi, off;
+// Geometry tables, built at load time and staged in LDS by every workgroup
+// of the hit kernels (as int vectors; float fields travel as their bits):
+//   layer l,  3 records: (acc_lo, acc_hi, inv_r, -), eta_lo of regions 0..3,
+//                        eta_lo of regions 4..7 (+inf past the last region)
+//   region r, 2 records: (eta_lo, inv_deta, phi_lo, inv_dphi),
+//                        (neta, nphi, first cell, -)
+struct GeoLds {
+    const v4i* layers;
+    const v4i* regions;
+    int n_regions;
 };
 
-// region grid lookup: -1 outside [eta_lo(first), eta_hi(last))
-__device__ __forceinline__ int lookup_cell(const Params& P, int l, float eta, float phi)
+__device__ __forceinline__ float f_of(int v) { return __int_as_float(v); }
+
+// region-grid lookup (Listing 2's getDDE): -1 outside the acceptance
+// [eta_lo(first region), eta_hi(last region)); the region is the number of
+// interior region edges <= eta; cell indices are clamped into the grid
+__device__ __forceinline__ int lookup_cell(const GeoLds& g, int l, float eta, float phi)
 {
-    const int R = P.n_regions;
-    const int base = l * R;
-    if (!(eta >= P.reg_eta_lo[base]) || !(eta < P.reg_eta_hi[base + R - 1])) return -1;
-    int k = 0;
-    for (int j = 1; j < R; ++j) k += (eta >= P.reg_eta_lo[base + j]) ? 1 : 0;
-    const int r = base + k;
-    const int ne = P.reg_neta[r], np = P.reg_nphi[r];
-    int ie = (int)floorf((eta - P.reg_eta_lo[r]) * P.reg_inv_deta[r]);
-    int ip = (int)floorf((phi - P.reg_phi_lo[r]) * P.reg_inv_dphi[r]);
-    ie = min(max(ie, 0), ne - 1);
-    ip = min(max(ip, 0), np - 1);
-    return P.reg_offset[r] + ie * np + ip;
+    const v4i a = g.layers[3 * l];
+    if (!(eta >= f_of(a.x)) || !(eta < f_of(a.y))) return -1;
+    const v4i b0 = g.layers[3 * l + 1];
+    const v4i b1 = g.layers[3 * l + 2];
+    const int k = (int)(eta >= f_of(b0.y)) + (int)(eta >= f_of(b0.z)) + (int)(eta >= f_of(b0.w)) +
+                  (int)(eta >= f_of(b1.x)) + (int)(eta >= f_of(b1.y)) + (int)(eta >= f_of(b1.z)) +
+                  (int)(eta >= f_of(b1.w));
+    const int r = l * g.n_regions + k;
+    const v4i f = g.regions[2 * r];
+    const v4i iv = g.regions[2 * r + 1];
+    int ie = (int)floorf((eta - f_of(f.x)) * f_of(f.y));
+    int ip = (int)floorf((phi - f_of(f.z)) * f_of(f.w));
+    ie = min(max(ie, 0), iv.x - 1);
+    ip = min(max(ip, 0), iv.y - 1);
+    return iv.z + ie * iv.y + ip;
+}
+
+__device__ __forceinline__ float layer_inv_r(const GeoLds& g, int l) { return f_of(g.layers[3 * l].z); }
+
+// stage the geometry tables into LDS (call with every thread, then sync)
+__device__ __forceinline__ GeoLds stage_geometry(const Params& P, v4i* s_geo)
+{
+    const int nl = 3 * P.n_layers;
+    const int nr = 2 * P.n_layers * P.n_regions;
+    const FCS_AS_GLOBAL v4i* gl = (const FCS_AS_GLOBAL v4i*)P.geo_layers;
+    const FCS_AS_GLOBAL v4i* gr = (const FCS_AS_GLOBAL v4i*)P.geo_regions;
+    for (int i = threadIdx.x; i < nl; i += kBlock) s_geo[i] = gl[i];
+    for (int i = threadIdx.x; i < nr; i += kBlock) s_geo[nl + i] = gr[i];
+    return GeoLds{s_geo, s_geo + nl, P.n_regions};
 }
 
 // first bin with cum > u; the guide narrows the search to [g[j], g[j+1]]
@@ -638,17 +724,20 @@ struct HitOut {
     int cell, bin;
 };
 
+// one hit: counter (i, layer | 3 << 8, particle in event, global event)
+// -> three 24-bit uniforms -> (r, alpha) bin -> position in the bin ->
+// (eta, phi) -> cell
 template <typename CumT, typename GuideT>
-__device__ __forceinline__ HitOut simulate_hit(const Params& P, CumT cum, GuideT guide, uint32_t i,
-                                               uint32_t l, uint32_t pin, uint32_t evg, float eta_p,
-                                               float phi_p, float inv_r)
+__device__ __forceinline__ HitOut simulate_hit(const GeoLds& g, CumT cum, GuideT guide, float dr,
+                                               uint32_t k0, uint32_t k1, uint32_t i, uint32_t l,
+                                               uint32_t pin, uint32_t evg, float eta_p, float phi_p,
+                                               float inv_r)
 {
-    const U4 x = philox4x32_10(i, l | (kTagHit << 8), pin, evg, P.key0, P.key1);
+    const U4 x = philox4x32_10(i, l | (kTagHit << 8), pin, evg, k0, k1);
     const float u0 = unit24(x.x), u1 = unit24(x.y), u2 = unit24(x.z);
     HitOut h;
     h.bin = find_bin(cum, guide, x.x, u0);
     const int ir = h.bin >> 3, ia = h.bin & 7;
-    const float dr = P.r_max / 32.0f;
     const float r = (float)ir * dr + u1 * dr;
     float c, s;
     sincos_bin(ia, u2, c, s);
@@ -662,7 +751,7 @@ __device__ __forceinline__ HitOut simulate_hit(const Params& P, CumT cum, GuideT
     else if (phi < -pi_f) phi = phi + two_pi_f;
     h.eta = eta;
     h.phi = phi;
-    h.cell = lookup_cell(P, (int)l, eta, phi);
+    h.cell = lookup_cell(g, (int)l, eta, phi);
     return h;
 }
 
@@ -670,176 +759,379 @@ __device__ __forceinline__ void write_hit(const Params& P, long long pos, const 
 {
     pos += P.hit_base;
     if (pos < P.hit_cap) {
-        P.hit_eta[pos] = h.eta;
-        P.hit_phi[pos] = h.phi;
-        P.hit_e[pos] = e;
-        P.hit_cell[pos] = h.cell;
+        G(P.hit_eta)[pos] = h.eta;
+        G(P.hit_phi)[pos] = h.phi;
+        G(P.hit_e)[pos] = e;
+        G(P.hit_cell)[pos] = h.cell;
     }
+}
+
+// Uniform description of one chunk of a large (particle, layer) task.
+struct ChunkInfo {
+    int t, l, first, count, ev, H;
+    uint32_t pin, evg;
+    float ehit, eta_p, phi_p;
+};
+
+__device__ __forceinline__ ChunkInfo load_chunk(const Params& P, int item)
+{
+    const int4 ck = load_i4(P.chunks, item);
+    ChunkInfo c;
+    const int key = __builtin_amdgcn_readfirstlane(ck.x);
+    c.first = __builtin_amdgcn_readfirstlane(ck.y);
+    c.count = __builtin_amdgcn_readfirstlane(ck.z);
+    const int gp = key >> 6;
+    c.l = key & 63;
+    c.t = gp * P.n_layers + c.l;
+    c.ehit = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(G(P.task_ehit)[c.t])));
+    c.ev = __builtin_amdgcn_readfirstlane(G(P.part_ev)[gp]);
+    c.pin = (uint32_t)__builtin_amdgcn_readfirstlane((int)G(P.part_p)[gp]);
+    c.evg = (uint32_t)(P.ev_base + (unsigned long long)c.ev);
+    c.H = __builtin_amdgcn_readfirstlane(G(P.part_set)[gp]) * P.n_layers + c.l;
+    const Particle pt = load_particle(P.particles, gp);
+    c.eta_p = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pt.eta)));
+    c.phi_p = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(pt.phi)));
+    return c;
+}
+
+// ------------------------------------------------------ wave-level items ---
+// Every wave of the hit kernels runs its own work items (no workgroup
+// barriers inside the item loop); the LDS below is partitioned per wave.
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kWaveSlots = 512;  // LDS hash slots of one wave's chunk accumulator
+constexpr int kListCap = 512;    // per-wave u16 list: claimed slots or tile owners
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int wave_broadcast_first(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// sum over the lanes of the wave (every lane gets the total)
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Owners of the hits of a tile of small tasks, for one wave: every task that
+// starts inside the tile marks its first hit with its index relative to the
+// tile's first task; an inclusive max-scan fills the gaps.  T <= kListCap.
+__device__ __forceinline__ void wave_tile_owners(const Params& P, const FCS_AS_GLOBAL Counters* ctr,
+                                                 int q, uint16_t* owner, int& s0, int& h0,
+                                                 int& hcount)
+{
+    const int lane = lane_id();
+    const int T = P.tile_hits;
+    h0 = q * T;
+    hcount = min(T, ctr->n_small_hits - h0);
+    s0 = G(P.tile_first)[q];
+    const int s1 = (q + 1 < ctr->n_tiles) ? G(P.tile_first)[q + 1] : ctr->n_small_tasks - 1;
+    for (int k = lane; k < T; k += kWave) owner[k] = 0;
+    wave_sync();
+    for (int j = s0 + lane; j <= s1; j += kWave) {
+        int st = load_i4(P.small_rec, 2LL * j).x - h0;
+        st = st < 0 ? 0 : st;
+        if (st < T) owner[st] = (uint16_t)(j - s0);
+    }
+    wave_sync();
+    const int per = T / kWave;  // consecutive entries per lane
+    int m = 0;
+    for (int k = 0; k < per; ++k) {
+        const int v = owner[lane * per + k];
+        m = v > m ? v : m;
+    }
+    int inc = m;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int o = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc = o > inc ? o : inc;
+    }
+    int run = __shfl_up(inc, 1, kWave);
+    if (lane == 0) run = 0;
+    for (int k = 0; k < per; ++k) {
+        const int v = owner[lane * per + k];
+        run = v > run ? v : run;
+        owner[lane * per + k] = (uint16_t)run;
+    }
+    wave_sync();
+}
+
+// Per-hit description of a hit of a small task (from its two records).
+struct SmallHit {
+    int t, l, i, ev, H;
+    uint32_t pin, evg;
+    float ehit, eta_p, phi_p;
+};
+
+__device__ __forceinline__ SmallHit small_hit(const Params& P, int j, int hit)
+{
+    const int4 r0 = load_i4(P.small_rec, 2LL * j);
+    const int4 r1 = load_i4(P.small_rec, 2LL * j + 1);
+    SmallHit s;
+    s.i = hit - r0.x;
+    const int gp = r0.y >> 6;
+    s.l = r0.y & 63;
+    s.t = gp * P.n_layers + s.l;
+    s.ehit = __int_as_float(r0.z);
+    s.H = r0.w;
+    s.eta_p = __int_as_float(r1.x);
+    s.phi_p = __int_as_float(r1.y);
+    s.evg = (uint32_t)r1.z;
+    s.pin = (uint32_t)r1.w;
+    s.ev = (int)(s.evg - (uint32_t)P.ev_base);
+    return s;
+}
+
+// Deposit into an event's cell and keep the per-64-cell-block count of
+// nonzero cells (one byte per block, packed four to a word): the adder that
+// finds the cell at zero counts it.  Energies are positive, so exactly one
+// adder sees zero.
+__device__ __forceinline__ void deposit(const Params& P, long long ev, int cell, float v)
+{
+    if (!(v > 0.0f)) return;  // zero-energy hits leave the cell untouched
+    const auto cp = G(P.cells) + ev * P.n_cells + cell;
+    float old;
+    [[clang::atomic(ignore_denormal_mode)]] {
+        old = __hip_atomic_fetch_add(cp, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (old == 0.0f) {
+        const long long b = ev * P.n_blk + (cell >> 6);
+        (void)gfetch_add((FCS_AS_GLOBAL uint32_t*)(G(P.flags) + (b & ~3LL)), 1u << (8 * (b & 3)));
+    }
+}
+
+// add `cnt` hits of `key` to a wave's LDS hash table (linear probing); a
+// newly claimed slot is appended to the wave's slot list; when the table is
+// full the energy goes to the cell directly
+__device__ __forceinline__ void wave_hash_add(const Params& P, uint32_t* hkey, uint32_t* hcnt,
+                                              uint16_t* list, int* nlist, uint32_t key, uint32_t cnt,
+                                              long long ev, float ehit)
+{
+    uint32_t slot = (key * 2654435761u) >> (32 - 9);
+    for (int pr = 0; pr < kHashProbes; ++pr) {
+        const uint32_t old = atomicCAS(&hkey[slot], kEmpty, key);
+        if (old == kEmpty) {
+            const int at = atomicAdd(nlist, 1);
+            list[at] = (uint16_t)slot;
+        }
+        if (old == kEmpty || old == key) {
+            atomicAdd(&hcnt[slot], cnt);
+            return;
+        }
+        slot = (slot + 1) & (kWaveSlots - 1);
+    }
+    deposit(P, ev, (int)key, (float)cnt * ehit);
+}
+
+// ----------------------------------------------------------- work queue ---
+// The items are split into kQueues contiguous ranges with one ticket counter
+// each.  A wave starts on the range of its workgroup's slot (workgroups are
+// dispatched round-robin over the chip's 8 XCDs, so neighbouring items, which
+// share events and cells, tend to stay in one XCD's L2) and takes per_grab
+// items per ticket; when its range is drained it moves on to the next.  One
+// counter handing out single items would serialize every wave on one atomic.
+struct WaveQueue {
+    int n_items, per_grab, home, probe, cur, end;
+};
+
+__device__ __forceinline__ WaveQueue make_queue(int n_items)
+{
+    WaveQueue q;
+    q.n_items = n_items;
+    const long long waves = (long long)gridDim.x * (blockDim.x / kWave);
+    const long long k = n_items / (waves * 16);
+    q.per_grab = (int)(k < 1 ? 1 : (k > 32 ? 32 : k));
+    q.home = (int)(blockIdx.x & (kQueues - 1));
+    q.probe = 0;
+    q.cur = q.end = 0;
+    return q;
+}
+
+// next item for the calling wave (uniform), false once every range is drained
+__device__ __forceinline__ bool next_item(const Params& P, WaveQueue& q, int& item)
+{
+    if (q.cur < q.end) {
+        item = q.cur++;
+        return true;
+    }
+    const auto tickets = G(P.queue);
+    const auto drained = G(P.queue) + kQueues * kQueueStride;
+    while (q.probe < kQueues) {
+        const int r = (q.home + q.probe) & (kQueues - 1);
+        ++q.probe;
+        // a plain load of the range's drained flag spares most late atomics
+        if (__builtin_amdgcn_readfirstlane(drained[r * kQueueStride])) continue;
+        const int lo = (int)((long long)r * q.n_items / kQueues);
+        const int hi = (int)((long long)(r + 1) * q.n_items / kQueues);
+        int g = 0;
+        if (lane_id() == 0) g = gfetch_add(tickets + r * kQueueStride, q.per_grab);
+        g = __builtin_amdgcn_readfirstlane(g);
+        if (lo + g < hi) {
+            item = lo + g;
+            q.cur = item + 1;
+            q.end = min(item + q.per_grab, hi);
+            q.probe = 0;  // come back to the home range first next time
+            return true;
+        }
+        if (lane_id() == 0) drained[r * kQueueStride] = 1;
+    }
+    return false;
 }
 
 // ------------------------------------------------- persistent hit kernel ---
-// Work items: [0, n_chunks) chunks of large tasks, then packed tiles of small
-// tasks.  A chunk belongs to one (particle, layer): its histogram and guide
-// sit in LDS and its hits are counted per cell in an LDS hash table, flushed
-// once as count * Ehit (one rounding per cell and chunk).  Tile hits add
-// their energy to the event's cell with one device atomic each.
+// Work items, pulled by each wave from a ticket counter: [0, n_chunks)
+// chunks of large (particle, layer) tasks, then tiles of packed small tasks.
+// A chunk's histogram and guide are staged in the wave's LDS; its hits are
+// counted per cell in the wave's LDS hash table (lanes that share the cell of
+// a leading lane are counted together first, twice per step) and flushed once
+// as count * Ehit, one rounding per cell and chunk.  Tile hits that share an
+// (event, cell) with a leading lane are summed across the wave first; each
+// remaining sum goes to the event's cell with one device atomic.
 __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
-    __shared__ uint32_t h_key[kHashSlots];
-    __shared__ uint32_t h_cnt[kHashSlots];
-    __shared__ float s_cum[kBins];
-    __shared__ uint8_t s_guide[kBins];
-    __shared__ uint16_t s_owner[kTileMax];
-    __shared__ int s_wmax[kBlock / kWave];
-    __shared__ int s_item;
+    extern __shared__ v4i s_geo[];
+    __shared__ uint32_t w_key[kWavesPerBlock][kWaveSlots];
+    __shared__ uint32_t w_cnt[kWavesPerBlock][kWaveSlots];
+    __shared__ uint16_t w_list[kWavesPerBlock][kListCap];
+    __shared__ float w_cum[kWavesPerBlock][kBins];
+    __shared__ uint32_t w_guide4[kWavesPerBlock][kBins / 4];
+    __shared__ int w_n[kWavesPerBlock];
 
-    const int tid = threadIdx.x;
-    const Counters* ctr = P.ctr;
+    const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
+    uint32_t* hkey = w_key[wv];
+    uint32_t* hcnt = w_cnt[wv];
+    uint16_t* list = w_list[wv];
+    float* cum = w_cum[wv];
+    const uint8_t* guide = reinterpret_cast<const uint8_t*>(w_guide4[wv]);
+    int* nlist = &w_n[wv];
+
+    const auto ctr = G(P.ctr);
     if (ctr->error & (kErrTooManyHits | kErrChunkCap)) return;
     const int n_chunks = ctr->n_chunks;
     const int n_items = n_chunks + ctr->n_tiles;
-    const int L = P.n_layers;
-    const long long C = P.n_cells;
+    const float dr = P.r_max / 32.0f;
+    const uint32_t k0 = P.key0, k1 = P.key1;
     long long n_out = 0;
 
-    for (int s = tid; s < kHashSlots; s += kBlock) {
-        h_key[s] = kEmpty;
-        h_cnt[s] = 0;
+    const GeoLds geo = stage_geometry(P, s_geo);
+    for (int s = lane; s < kWaveSlots; s += kWave) {
+        hkey[s] = kEmpty;
+        hcnt[s] = 0;
     }
+    if (lane == 0) *nlist = 0;
+    __syncthreads();
 
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) s_item = atomicAdd(&P.ctr->ticket, 1);
-        __syncthreads();
-        const int item = s_item;
-        if (item >= n_items) break;
+    WaveQueue queue = make_queue(n_items);
+    int item;
+    while (next_item(P, queue, item)) {
 
         if (item < n_chunks) {
             // ------------------------------------------- chunk of a large task
-            const int4 ck = P.chunks[item];
-            const long long gp = ck.x >> 6;
-            const int l = ck.x & 63;
-            const long long t = gp * L + l;
-            const float ehit = P.task_ehit[t];
-            const int ev = P.part_ev[gp];
-            const uint32_t pin = P.part_p[gp];
-            const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
-            const long long H = (long long)P.part_set[gp] * L + l;
-            const Particle pt = P.particles[gp];
-            const float inv_r = P.layer_inv_r[l];
-            s_cum[tid] = P.cum[H * kBins + tid];
-            s_guide[tid] = P.guide[H * kBins + tid];
-            __syncthreads();
-            float* cells_e = P.cells + (long long)ev * C;
-            const long long hbase = P.want_hits ? (long long)P.task_hoff[t] : 0;
-            for (int i = ck.y + tid; i < ck.y + ck.z; i += kBlock) {
-                const HitOut h = simulate_hit(P, s_cum, s_guide, (uint32_t)i, (uint32_t)l, pin, evg,
-                                              pt.eta, pt.phi, inv_r);
-                if (P.want_hits) write_hit(P, hbase + i, h, ehit);
-                if (h.cell < 0) {
-                    ++n_out;
-                    continue;
+            const ChunkInfo ck = load_chunk(P, item);
+            const long long hb = (long long)ck.H * kBins;
+            reinterpret_cast<v4i*>(cum)[lane] = ((const FCS_AS_GLOBAL v4i*)(G(P.cum) + hb))[lane];
+            w_guide4[wv][lane] = ((const FCS_AS_GLOBAL uint32_t*)(G(P.guide) + hb))[lane];
+            wave_sync();
+            const float inv_r = layer_inv_r(geo, ck.l);
+            const long long hbase = P.want_hits ? (long long)G(P.task_hoff)[ck.t] : 0;
+            for (int i = ck.first + lane; i < ck.first + ck.count; i += kWave) {
+                const HitOut h = simulate_hit(geo, cum, guide, dr, k0, k1, (uint32_t)i,
+                                              (uint32_t)ck.l, ck.pin, ck.evg, ck.eta_p, ck.phi_p,
+                                              inv_r);
+                if (P.want_hits) write_hit(P, hbase + i, h, ck.ehit);
+                n_out += h.cell < 0 ? 1 : 0;
+                bool pending = h.cell >= 0;
+                for (int round = 0; round < 2; ++round) {
+                    const unsigned long long act = __ballot(pending);
+                    if (!act) break;
+                    const int leader = __ffsll((long long)act) - 1;
+                    const int lk = __builtin_amdgcn_readlane(h.cell, leader);
+                    const bool same = pending && h.cell == lk;
+                    const unsigned long long sm = __ballot(same);
+                    if (lane == leader)
+                        wave_hash_add(P, hkey, hcnt, list, nlist, (uint32_t)lk,
+                                      (uint32_t)__popcll(sm), ck.ev, ck.ehit);
+                    pending = pending && !same;
                 }
-                const uint32_t key = (uint32_t)h.cell;
-                uint32_t slot = (key * 2654435761u) >> (32 - 11);
-                bool done = false;
-                for (int pr = 0; pr < kHashProbes; ++pr) {
-                    const uint32_t old = atomicCAS(&h_key[slot], kEmpty, key);
-                    if (old == kEmpty || old == key) {
-                        atomicAdd(&h_cnt[slot], 1u);
-                        done = true;
-                        break;
-                    }
-                    slot = (slot + 1) & (kHashSlots - 1);
-                }
-                if (!done) {
-                    unsafeAtomicAdd(cells_e + h.cell, ehit);
-                    P.flags[(long long)ev * P.n_blk + (h.cell >> 6)] = 1;
-                }
+                if (pending)
+                    wave_hash_add(P, hkey, hcnt, list, nlist, (uint32_t)h.cell, 1u, ck.ev, ck.ehit);
             }
-            __syncthreads();
-            for (int s = tid; s < kHashSlots; s += kBlock) {
-                const uint32_t key = h_key[s];
-                if (key != kEmpty) {
-                    unsafeAtomicAdd(cells_e + key, (float)h_cnt[s] * ehit);
-                    P.flags[(long long)ev * P.n_blk + (key >> 6)] = 1;
-                    h_key[s] = kEmpty;
-                    h_cnt[s] = 0;
-                }
+            wave_sync();
+            const int n = *nlist;
+            for (int k = lane; k < n; k += kWave) {
+                const int slot = list[k];
+                deposit(P, ck.ev, (int)hkey[slot], (float)hcnt[slot] * ck.ehit);
+                hkey[slot] = kEmpty;
+                hcnt[slot] = 0;
             }
+            wave_sync();
+            if (lane == 0) *nlist = 0;
+            wave_sync();
         } else {
             // ------------------------------------------ tile of small tasks
-            const int q = item - n_chunks;
-            const int T = P.tile_hits;
-            const int h0 = q * T;
-            const int hcount = min(T, ctr->n_small_hits - h0);
-            const int s0 = P.tile_first[q];
-            const int s1 = (q + 1 < ctr->n_tiles) ? P.tile_first[q + 1] : ctr->n_small_tasks - 1;
-            for (int k = tid; k < T; k += kBlock) s_owner[k] = 0;
-            __syncthreads();
-            for (int j = s0 + tid; j <= s1; j += kBlock) {
-                int st = P.small_off[j] - h0;
-                st = st < 0 ? 0 : st;
-                if (st < T) s_owner[st] = (uint16_t)(j - s0);
-            }
-            __syncthreads();
-            owner_max_scan(s_owner, s_wmax, T);
-            for (int k = tid; k < hcount; k += kBlock) {
-                const int j = s0 + s_owner[k];
-                const int key = P.small_key[j];
-                const long long gp = key >> 6;
-                const int l = key & 63;
-                const long long t = gp * L + l;
-                const int i = h0 + k - P.small_off[j];
-                const float ehit = P.task_ehit[t];
-                const int ev = P.part_ev[gp];
-                const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
-                const long long H = (long long)P.part_set[gp] * L + l;
-                const Particle pt = P.particles[gp];
-                const HitOut h = simulate_hit(P, P.cum + H * kBins, P.guide + H * kBins, (uint32_t)i,
-                                              (uint32_t)l, P.part_p[gp], evg, pt.eta, pt.phi,
-                                              P.layer_inv_r[l]);
-                if (P.want_hits) write_hit(P, (long long)P.task_hoff[t] + i, h, ehit);
-                if (h.cell < 0) {
-                    ++n_out;
-                    continue;
+            int s0, h0, hcount;
+            wave_tile_owners(P, ctr, item - n_chunks, list, s0, h0, hcount);
+            // uniform trip count: every lane takes part in the wave sums below
+            for (int kb = 0; kb < hcount; kb += kWave) {
+                const int k = kb + lane;
+                const bool valid = k < hcount;
+                const int kk = valid ? k : hcount - 1;
+                const SmallHit sh = small_hit(P, s0 + list[kk], h0 + kk);
+                const HitOut h = simulate_hit(geo, G(P.cum) + (long long)sh.H * kBins,
+                                              G(P.guide) + (long long)sh.H * kBins, dr, k0, k1,
+                                              (uint32_t)sh.i, (uint32_t)sh.l, sh.pin, sh.evg,
+                                              sh.eta_p, sh.phi_p, layer_inv_r(geo, sh.l));
+                if (valid && P.want_hits)
+                    write_hit(P, (long long)G(P.task_hoff)[sh.t] + sh.i, h, sh.ehit);
+                n_out += (valid && h.cell < 0) ? 1 : 0;
+                bool pending = valid && h.cell >= 0;
+                for (int round = 0; round < 2; ++round) {
+                    const unsigned long long act = __ballot(pending);
+                    if (!act) break;
+                    const int leader = __ffsll((long long)act) - 1;
+                    const int lc = __builtin_amdgcn_readlane(h.cell, leader);
+                    const int le = __builtin_amdgcn_readlane(sh.ev, leader);
+                    const bool same = pending && h.cell == lc && sh.ev == le;
+                    const float tot = wave_sum(same ? sh.ehit : 0.0f);
+                    if (lane == leader) deposit(P, le, lc, tot);
+                    pending = pending && !same;
                 }
-                unsafeAtomicAdd(P.cells + (long long)ev * C + h.cell, ehit);
-                P.flags[(long long)ev * P.n_blk + (h.cell >> 6)] = 1;
+                if (pending) deposit(P, sh.ev, h.cell, sh.ehit);
             }
+            wave_sync();
         }
     }
     const long long tot = block_sum_ll(n_out);
-    if (tid == 0 && tot)
-        atomicAdd(reinterpret_cast<unsigned long long*>(&P.ctr->hits_out), (unsigned long long)tot);
+    if (threadIdx.x == 0 && tot) (void)gfetch_add(&G(P.ctr)->hits_out, tot);
 }
 
 // ------------------------------------------ ordered compaction (a10) ---
-// One wave per segment of 64 flag blocks (4096 cells) of one event.  Only
-// flagged blocks are read; ballots give each lane its output slot, so the
-// output is in ascending dense cell index per event.
+// The hit kernels keep, per event and 64-cell block, the number of nonzero
+// cells (one byte per block).  A wave per segment of 256 blocks sums them;
+// after a scan over segments, a wave per segment walks its blocks in order,
+// writes the nonzero cells as (cell_id, E) at consecutive positions, resets
+// the cells and the counts.  The output is in ascending dense cell order.
+constexpr int kSegBlocks = 256;
+
 __global__ __launch_bounds__(kBlock) void k_seg_count(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
-    const long long gw = (long long)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const long long gw = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (gw >= P.n_events * P.n_seg) return;
     const long long e = gw / P.n_seg;
     const int seg = (int)(gw - e * P.n_seg);
-    const int lane = lane_id();
-    const int fb = seg * 64 + lane;
-    const bool flagged = fb < P.n_blk && P.flags[e * P.n_blk + fb] != 0;
-    unsigned long long mask = __ballot(flagged);
-    const float* cells = P.cells + e * P.n_cells;
-    int cnt = 0;
-    while (mask) {
-        const int b = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        const long long cell = (long long)(seg * 64 + b) * 64 + lane;
-        const float v = cell < P.n_cells ? cells[cell] : 0.0f;
-        cnt += __popcll(__ballot(v != 0.0f));
-    }
-    if (lane == 0) P.seg_cnt[gw] = cnt;
+    const auto words = (const FCS_AS_GLOBAL uint32_t*)(G(P.flags) + e * P.n_blk + seg * kSegBlocks);
+    const uint32_t w = words[lane_id()];
+    int s = (int)(w & 0xff) + (int)((w >> 8) & 0xff) + (int)((w >> 16) & 0xff) + (int)(w >> 24);
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
+    if (lane_id() == 0) G(P.seg_cnt)[gw] = s;
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_reduce(const Params* __restrict__ Pp)
@@ -849,10 +1141,10 @@ __global__ __launch_bounds__(kBlock) void k_seg_reduce(const Params* __restrict_
     const long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanItems;
     int s = 0;
     for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) s += P.seg_cnt[base + k];
+        if (base + k < n) s += G(P.seg_cnt)[base + k];
     int tot;
     (void)block_excl_scan1(s, tot);
-    if (threadIdx.x == 0) P.seg_blk[blockIdx.x] = tot;
+    if (threadIdx.x == 0) G(P.seg_blk)[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(1024) void k_seg_top(const Params* __restrict__ Pp)
@@ -866,7 +1158,7 @@ __global__ __launch_bounds__(1024) void k_seg_top(const Params* __restrict__ Pp)
     const int nb = P.n_seg_blocks;
     for (int b0 = 0; b0 < nb; b0 += 1024) {
         const int b = b0 + tid;
-        const long long v = b < nb ? P.seg_blk[b] : 0;
+        const long long v = b < nb ? G(P.seg_blk)[b] : 0;
         const long long inc = wave_incl_scan<long long>(v);
         if (lane_id() == kWave - 1) part[tid / kWave] = inc;
         __syncthreads();
@@ -875,14 +1167,14 @@ __global__ __launch_bounds__(1024) void k_seg_top(const Params* __restrict__ Pp)
             if (w < tid / kWave) off += part[w];
             tot += part[w];
         }
-        if (b < nb) P.seg_blk[b] = (int)(carry + off + inc - v);
+        if (b < nb) G(P.seg_blk)[b] = (int)(carry + off + inc - v);
         __syncthreads();
         if (tid == 0) carry += tot;
         __syncthreads();
     }
     if (tid == 0) {
-        P.ctr->nnz_total = carry;
-        if (P.out_ev_off) P.out_ev_off[P.n_events] = P.out_base + carry;
+        G(P.ctr)->nnz_total = carry;
+        if (G(P.out_ev_off)) G(P.out_ev_off)[P.n_events] = P.out_base + carry;
     }
 }
 
@@ -894,13 +1186,13 @@ __global__ __launch_bounds__(kBlock) void k_seg_apply(const Params* __restrict__
     int v[kScanItems];
     int s = 0;
     for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < n ? P.seg_cnt[base + k] : 0;
+        v[k] = base + k < n ? G(P.seg_cnt)[base + k] : 0;
         s += v[k];
     }
     int tot;
-    int run = block_excl_scan1(s, tot) + P.seg_blk[blockIdx.x];
+    int run = block_excl_scan1(s, tot) + G(P.seg_blk)[blockIdx.x];
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) P.seg_off[base + k] = run;
+        if (base + k < n) G(P.seg_off)[base + k] = run;
         run += v[k];
     }
 }
@@ -908,138 +1200,133 @@ __global__ __launch_bounds__(kBlock) void k_seg_apply(const Params* __restrict__
 __global__ __launch_bounds__(kBlock) void k_seg_write(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
-    const long long gw = (long long)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const long long gw = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (gw >= P.n_events * P.n_seg) return;
     const long long e = gw / P.n_seg;
     const int seg = (int)(gw - e * P.n_seg);
     const int lane = lane_id();
-    const int fb = seg * 64 + lane;
-    const bool flagged = fb < P.n_blk && P.flags[e * P.n_blk + fb] != 0;
-    unsigned long long mask = __ballot(flagged);
-    float* cells = P.cells + e * P.n_cells;
-    long long pos = P.out_base + P.seg_off[gw];
-    if (seg == 0 && lane == 0 && P.out_ev_off) P.out_ev_off[e] = pos;
+    const auto words = (FCS_AS_GLOBAL uint32_t*)(G(P.flags) + e * P.n_blk + seg * kSegBlocks);
+    const uint32_t w = words[lane];
+    // output position of this lane's first block: exclusive scan of lane sums
+    const int mine = (int)(w & 0xff) + (int)((w >> 8) & 0xff) + (int)((w >> 16) & 0xff) + (int)(w >> 24);
+    const int incl = wave_incl_scan(mine);
+    const long long base = P.out_base + G(P.seg_off)[gw];
+    if (seg == 0 && lane == 0 && G(P.out_ev_off)) G(P.out_ev_off)[e] = base;
+    const int lane_off = incl - mine;
+    const auto cells = G(P.cells) + e * P.n_cells;
     const unsigned long long below = (1ull << lane) - 1ull;
-    while (mask) {
-        const int b = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        const long long cell = (long long)(seg * 64 + b) * 64 + lane;
-        const bool in = cell < P.n_cells;
-        const float v = in ? cells[cell] : 0.0f;
-        const unsigned long long nz = __ballot(v != 0.0f);
-        if (v != 0.0f) {
-            const long long o = pos + __popcll(nz & below);
-            if (o < P.out_cap) {
-                P.out_ids[o] = P.cell_id[cell];
-                P.out_e[o] = v;
-            }
+    unsigned long long lanes = __ballot(w != 0);
+    while (lanes) {
+        const int src = __ffsll((long long)lanes) - 1;
+        lanes &= lanes - 1;
+        const uint32_t ws = (uint32_t)__builtin_amdgcn_readlane((int)w, src);
+        int pos = __builtin_amdgcn_readlane(lane_off, src);
+        // the (up to four) blocks of lane src: load all, then write
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long long cell = (long long)(seg * kSegBlocks + src * 4 + j) * 64 + lane;
+            v[j] = ((ws >> (8 * j)) & 0xff) && cell < P.n_cells ? cells[cell] : 0.0f;
         }
-        if (P.clean_cells && in) cells[cell] = 0.0f;
-        pos += __popcll(nz);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (((ws >> (8 * j)) & 0xff) == 0) continue;
+            const long long cell = (long long)(seg * kSegBlocks + src * 4 + j) * 64 + lane;
+            const unsigned long long nz = __ballot(v[j] != 0.0f);
+            if (v[j] != 0.0f) {
+                const long long o = base + pos + __popcll(nz & below);
+                if (o < P.out_cap) {
+                    G(P.out_ids)[o] = G(P.cell_id)[cell];
+                    G(P.out_e)[o] = v[j];
+                }
+                if (P.clean_cells) cells[cell] = 0.0f;
+            }
+            pos += __popcll(nz);
+        }
     }
-    if (flagged) P.flags[e * P.n_blk + fb] = 0;
+    if (w) words[lane] = 0;
 }
 
-
 // ------------------------------------------------------ adjoint (a12) ---
-// Same work items as k_hits.  Each hit's bin and cell are recomputed from its
-// Philox counter; g = dL/dE_cell is gathered at the cell and accumulated in
-// FP64 per task (sum of g) and per histogram bin (sum of g * Ehit).  A chunk
-// of a large task keeps its 256 bin sums in LDS and flushes them once.
+// Same work items and wave organization as k_hits.  Each hit's bin and cell
+// are recomputed from its Philox counter; g = dL/dE_cell is gathered at the
+// cell and accumulated in FP64 per task (sum of g) and per histogram bin (sum
+// of g * Ehit); a chunk keeps its 256 bin sums in the wave's LDS and flushes
+// them once.
 __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
-    __shared__ float s_cum[kBins];
-    __shared__ uint8_t s_guide[kBins];
-    __shared__ double s_bin[kBins];
-    __shared__ uint16_t s_owner[kTileMax];
-    __shared__ int s_wmax[kBlock / kWave];
-    __shared__ int s_item;
+    extern __shared__ v4i s_geo[];
+    __shared__ double w_bin[kWavesPerBlock][kBins];
+    __shared__ uint16_t w_list[kWavesPerBlock][kListCap];
+    __shared__ float w_cum[kWavesPerBlock][kBins];
+    __shared__ uint32_t w_guide4[kWavesPerBlock][kBins / 4];
 
-    const int tid = threadIdx.x;
-    const Counters* ctr = P.ctr;
+    const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
+    double* bins = w_bin[wv];
+    uint16_t* list = w_list[wv];
+    float* cum = w_cum[wv];
+    const uint8_t* guide = reinterpret_cast<const uint8_t*>(w_guide4[wv]);
+    const auto ctr = G(P.ctr);
     if (ctr->error & (kErrTooManyHits | kErrChunkCap)) return;
     const int n_chunks = ctr->n_chunks;
     const int n_items = n_chunks + ctr->n_tiles;
-    const int L = P.n_layers;
     const long long C = P.n_cells;
-    s_bin[tid] = 0.0;
+    const float dr = P.r_max / 32.0f;
+    const uint32_t k0 = P.key0, k1 = P.key1;
+    const GeoLds geo = stage_geometry(P, s_geo);
+    for (int b = lane; b < kBins; b += kWave) bins[b] = 0.0;
+    __syncthreads();
 
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) s_item = atomicAdd(&P.ctr->ticket, 1);
-        __syncthreads();
-        const int item = s_item;
-        if (item >= n_items) break;
+    WaveQueue queue = make_queue(n_items);
+    int item;
+    while (next_item(P, queue, item)) {
         if (item < n_chunks) {
-            const int4 ck = P.chunks[item];
-            const long long gp = ck.x >> 6;
-            const int l = ck.x & 63;
-            const long long t = gp * L + l;
-            const float ehit = P.task_ehit[t];
-            const int ev = P.part_ev[gp];
-            const uint32_t pin = P.part_p[gp];
-            const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
-            const long long H = (long long)P.part_set[gp] * L + l;
-            const Particle pt = P.particles[gp];
-            const float inv_r = P.layer_inv_r[l];
-            s_cum[tid] = P.cum[H * kBins + tid];
-            s_guide[tid] = P.guide[H * kBins + tid];
-            __syncthreads();
-            const float* g = P.grad_cells + (long long)ev * C;
+            const ChunkInfo ck = load_chunk(P, item);
+            const long long hb = (long long)ck.H * kBins;
+            reinterpret_cast<v4i*>(cum)[lane] = ((const FCS_AS_GLOBAL v4i*)(G(P.cum) + hb))[lane];
+            w_guide4[wv][lane] = ((const FCS_AS_GLOBAL uint32_t*)(G(P.guide) + hb))[lane];
+            wave_sync();
+            const float inv_r = layer_inv_r(geo, ck.l);
+            const auto g = G(P.grad_cells) + (long long)ck.ev * C;
             double gsum = 0.0;
-            for (int i = ck.y + tid; i < ck.y + ck.z; i += kBlock) {
-                const HitOut h = simulate_hit(P, s_cum, s_guide, (uint32_t)i, (uint32_t)l, pin, evg,
-                                              pt.eta, pt.phi, inv_r);
+            for (int i = ck.first + lane; i < ck.first + ck.count; i += kWave) {
+                const HitOut h = simulate_hit(geo, cum, guide, dr, k0, k1, (uint32_t)i,
+                                              (uint32_t)ck.l, ck.pin, ck.evg, ck.eta_p, ck.phi_p,
+                                              inv_r);
                 if (h.cell < 0) continue;
                 const double gc = (double)g[h.cell];
                 gsum += gc;
-                atomicAdd(&s_bin[h.bin], gc * (double)ehit);
+                atomicAdd(&bins[h.bin], gc * (double)ck.ehit);
             }
-            gsum = block_sum_ll_d(gsum);
-            if (tid == 0 && gsum != 0.0) unsafeAtomicAdd(P.acc_elayer + t, gsum);
-            __syncthreads();
-            const double v = s_bin[tid];
-            if (v != 0.0) {
-                unsafeAtomicAdd(P.acc_bins + H * kBins + tid, v);
-                s_bin[tid] = 0.0;
+#pragma unroll
+            for (int d = kWave / 2; d > 0; d >>= 1) gsum += __shfl_xor(gsum, d, kWave);
+            if (lane == 0 && gsum != 0.0) gadd(G(P.acc_elayer) + ck.t, gsum);
+            wave_sync();
+            for (int b = lane; b < kBins; b += kWave) {
+                const double v = bins[b];
+                if (v != 0.0) {
+                    gadd(G(P.acc_bins) + hb + b, v);
+                    bins[b] = 0.0;
+                }
             }
+            wave_sync();
         } else {
-            const int q = item - n_chunks;
-            const int T = P.tile_hits;
-            const int h0 = q * T;
-            const int hcount = min(T, ctr->n_small_hits - h0);
-            const int s0 = P.tile_first[q];
-            const int s1 = (q + 1 < ctr->n_tiles) ? P.tile_first[q + 1] : ctr->n_small_tasks - 1;
-            for (int k = tid; k < T; k += kBlock) s_owner[k] = 0;
-            __syncthreads();
-            for (int j = s0 + tid; j <= s1; j += kBlock) {
-                int st = P.small_off[j] - h0;
-                st = st < 0 ? 0 : st;
-                if (st < T) s_owner[st] = (uint16_t)(j - s0);
-            }
-            __syncthreads();
-            owner_max_scan(s_owner, s_wmax, T);
-            for (int k = tid; k < hcount; k += kBlock) {
-                const int j = s0 + s_owner[k];
-                const int key = P.small_key[j];
-                const long long gp = key >> 6;
-                const int l = key & 63;
-                const long long t = gp * L + l;
-                const int i = h0 + k - P.small_off[j];
-                const float ehit = P.task_ehit[t];
-                const int ev = P.part_ev[gp];
-                const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
-                const long long H = (long long)P.part_set[gp] * L + l;
-                const Particle pt = P.particles[gp];
-                const HitOut h = simulate_hit(P, P.cum + H * kBins, P.guide + H * kBins, (uint32_t)i,
-                                              (uint32_t)l, P.part_p[gp], evg, pt.eta, pt.phi,
-                                              P.layer_inv_r[l]);
+            int s0, h0, hcount;
+            wave_tile_owners(P, ctr, item - n_chunks, list, s0, h0, hcount);
+            for (int k = lane; k < hcount; k += kWave) {
+                const SmallHit sh = small_hit(P, s0 + list[k], h0 + k);
+                const HitOut h = simulate_hit(geo, G(P.cum) + (long long)sh.H * kBins,
+                                              G(P.guide) + (long long)sh.H * kBins, dr, k0, k1,
+                                              (uint32_t)sh.i, (uint32_t)sh.l, sh.pin, sh.evg,
+                                              sh.eta_p, sh.phi_p, layer_inv_r(geo, sh.l));
                 if (h.cell < 0) continue;
-                const double gc = (double)P.grad_cells[(long long)ev * C + h.cell];
-                unsafeAtomicAdd(P.acc_elayer + t, gc);
-                unsafeAtomicAdd(P.acc_bins + H * kBins + h.bin, gc * (double)ehit);
+                const double gc = (double)G(P.grad_cells)[(long long)sh.ev * C + h.cell];
+                gadd(G(P.acc_elayer) + sh.t, gc);
+                gadd(G(P.acc_bins) + (long long)sh.H * kBins + h.bin, gc * (double)sh.ehit);
             }
+            wave_sync();
         }
     }
 }
@@ -1050,8 +1337,8 @@ __global__ void k_adj_elayer(const Params* __restrict__ Pp)
     const Params& P = *Pp;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= P.n_tasks) return;
-    const int n = P.task_n[t];
-    P.grad_elayer[t] = n > 0 ? (float)(P.acc_elayer[t] / (double)n) : 0.0f;
+    const int n = G(P.task_n)[t];
+    G(P.grad_elayer)[t] = n > 0 ? (float)(G(P.acc_elayer)[t] / (double)n) : 0.0f;
 }
 
 // dL/dw_b = A_b / w_b - S / W per histogram (one block per histogram)
@@ -1060,12 +1347,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_weights(const Params* __restrict
     const Params& P = *Pp;
     const long long H = blockIdx.x;
     const int b = threadIdx.x;
-    const double w = (double)P.weights[H * kBins + b];
-    const double A = P.acc_bins[H * kBins + b];
+    const double w = (double)G(P.weights)[H * kBins + b];
+    const double A = G(P.acc_bins)[H * kBins + b];
     const double W = block_sum_ll_d(w);
     const double S = block_sum_ll_d(A);
     const double lr = w > 0.0 ? A / w : 0.0;
-    P.grad_weights[H * kBins + b] = (float)(lr - S / W);
+    G(P.grad_weights)[H * kBins + b] = (float)(lr - S / W);
 }
 
 }  // namespace fcsk

@@ -26,10 +26,10 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t lo_b = 0xCD9E8D57u * c2;
+        const uint64_t pa = (uint64_t)c0 * 0xD2511F53u;  // one v_mad_u64_u32 each
+        const uint64_t pb = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t hi_a = (uint32_t)(pa >> 32), lo_a = (uint32_t)pa;
+        const uint32_t hi_b = (uint32_t)(pb >> 32), lo_b = (uint32_t)pb;
         const uint32_t y0 = hi_b ^ c1 ^ k0;
         const uint32_t y2 = hi_a ^ c3 ^ k1;
         c0 = y0;

@@ -60,6 +60,7 @@ struct fcs_ctx {
     int n_layers = 0, n_regions = 0;
     DevBuf g_eta_lo, g_eta_hi, g_inv_deta, g_inv_dphi, g_phi_lo, g_neta, g_nphi, g_offset,
         g_inv_r, g_cell_id;
+    DevBuf g_layers, g_regions;  // lookup records staged in LDS by the hit kernels
 
     // parametrization
     bool has_param = false;
@@ -70,8 +71,8 @@ struct fcs_ctx {
 
     // workspace
     DevBuf w_particles, w_evoff, w_override, w_task_n, w_task_ehit, w_part_ev, w_part_p,
-        w_part_set, w_blk_sums, w_blk_offs, w_task_hoff, w_chunks, w_small_key, w_small_off,
-        w_tile_first, w_cells, w_flags, w_seg_cnt, w_seg_off, w_seg_blk, w_ctr, w_params,
+        w_part_set, w_blk_sums, w_blk_offs, w_task_hoff, w_chunks, w_small_rec,
+        w_tile_first, w_cells, w_flags, w_seg_cnt, w_seg_off, w_seg_blk, w_ctr, w_queue, w_params,
         w_acc_el, w_acc_bins;
     long long cells_events = 0;  // events the accumulator holds (kept zero)
     long long flag_events = 0;
@@ -213,7 +214,8 @@ int fcs_create(fcs_ctx** out, int device)
         fcs_destroy(c);
         return fail(nullptr, FCS_E_HIP, "stream/event/pinned allocation failed");
     }
-    if (ensure(c, c->w_params, sizeof(Params)) || ensure(c, c->w_ctr, sizeof(Counters))) {
+    if (ensure(c, c->w_params, sizeof(Params)) || ensure(c, c->w_ctr, sizeof(Counters)) ||
+        ensure(c, c->w_queue, 2 * fcsk::kQueues * fcsk::kQueueStride * sizeof(int32_t))) {
         fcs_destroy(c);
         return fail(nullptr, FCS_E_NOMEM, "device allocation failed");
     }
@@ -237,8 +239,8 @@ void fcs_destroy(fcs_ctx* c)
                       &c->p_guide, &c->w_particles, &c->w_evoff, &c->w_override, &c->w_task_n,
                       &c->w_task_ehit, &c->w_part_ev, &c->w_part_p, &c->w_part_set,
                       &c->w_blk_sums, &c->w_blk_offs, &c->w_task_hoff, &c->w_chunks,
-                      &c->w_small_key, &c->w_small_off, &c->w_tile_first, &c->w_cells,
-                      &c->w_flags, &c->w_seg_cnt, &c->w_seg_off, &c->w_seg_blk, &c->w_ctr,
+                      &c->w_small_rec, &c->w_tile_first, &c->w_cells, &c->g_layers, &c->g_regions,
+                      &c->w_flags, &c->w_seg_cnt, &c->w_seg_off, &c->w_seg_blk, &c->w_ctr, &c->w_queue,
                       &c->w_params, &c->w_acc_el, &c->w_acc_bins, &c->o_cells, &c->o_ids,
                       &c->o_e, &c->o_evoff, &c->o_heta, &c->o_hphi, &c->o_he, &c->o_hcell,
                       &c->o_thoff, &c->o_counts, &c->o_elayer};
@@ -334,6 +336,39 @@ int fcs_load_geometry(fcs_ctx* c, const fcs_geometry* g)
         (rc = upload(c, c->g_inv_r, g->layer_inv_r, (size_t)L)) ||
         (rc = upload(c, c->g_cell_id, g->cell_id, (size_t)g->n_cells)))
         return rc;
+    {
+        // lookup records (see GeoLds): per layer (acc_lo, acc_hi, inv_r, -),
+        // region lower edges 0..7 (+inf past the last); per region
+        // (eta_lo, inv_deta, phi_lo, inv_dphi), (neta, nphi, offset, -)
+        auto bits = [](float f) {
+            int32_t v;
+            std::memcpy(&v, &f, 4);
+            return v;
+        };
+        const float inf = INFINITY;
+        std::vector<int32_t> lay((size_t)L * 12, 0), reg((size_t)L * R * 8, 0);
+        for (int l = 0; l < L; ++l) {
+            int32_t* a = &lay[(size_t)l * 12];
+            a[0] = bits(g->reg_eta_lo[l * R]);
+            a[1] = bits(g->reg_eta_hi[l * R + R - 1]);
+            a[2] = bits(g->layer_inv_r[l]);
+            for (int k = 0; k < 8; ++k) a[4 + k] = bits(k < R ? g->reg_eta_lo[l * R + k] : inf);
+            for (int k = 0; k < R; ++k) {
+                int32_t* b = &reg[(size_t)(l * R + k) * 8];
+                const int r = l * R + k;
+                b[0] = bits(g->reg_eta_lo[r]);
+                b[1] = bits(g->reg_inv_deta[r]);
+                b[2] = bits(g->reg_phi_lo[r]);
+                b[3] = bits(g->reg_inv_dphi[r]);
+                b[4] = g->reg_neta[r];
+                b[5] = g->reg_nphi[r];
+                b[6] = g->reg_offset[r];
+            }
+        }
+        if ((rc = upload(c, c->g_layers, lay.data(), lay.size())) ||
+            (rc = upload(c, c->g_regions, reg.data(), reg.size())))
+            return rc;
+    }
     const bool changed = !c->has_geom || c->n_cells != g->n_cells;
     c->n_cells = g->n_cells;
     c->n_layers = L;
@@ -442,12 +477,12 @@ int check_tuning(fcs_ctx* c, const fcs_sim_options* o, Tuning* t)
 {
     t->chunk = o->chunk_hits ? o->chunk_hits : 2048;
     t->big = o->big_task_hits ? o->big_task_hits : 128;
-    t->tile = o->tile_hits ? o->tile_hits : 2048;
+    t->tile = o->tile_hits ? o->tile_hits : 512;
     t->wg_per_cu = o->wg_per_cu ? o->wg_per_cu : 4;
     if (t->chunk < 1 || t->chunk > (1 << 20))
         return fail(c, FCS_E_INVALID_ARG, "chunk_hits = %d outside [1, 2^20]", t->chunk);
-    if (t->tile < fcsk::kBlock || t->tile > fcsk::kTileMax || t->tile % fcsk::kBlock)
-        return fail(c, FCS_E_INVALID_ARG, "tile_hits = %d must be a multiple of 256 in [256, %d]",
+    if (t->tile < fcsk::kWave || t->tile > fcsk::kTileMax || t->tile % fcsk::kWave)
+        return fail(c, FCS_E_INVALID_ARG, "tile_hits = %d must be a multiple of 64 in [64, %d]",
                     t->tile, fcsk::kTileMax);
     if (t->big < 1 || t->big > t->tile)
         return fail(c, FCS_E_INVALID_ARG, "big_task_hits = %d outside [1, tile_hits]", t->big);
@@ -466,8 +501,9 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     const long long N = sh.n_particles;
     const long long nt = N * L;
     const long long E = sh.n_events;
-    const int n_blk = (int)((c->n_cells + 63) / 64);
-    const int n_seg = (n_blk + 63) / 64;
+    // flag stride per event: 64-cell blocks rounded up to whole segments
+    const int n_seg = (int)(((c->n_cells + 63) / 64 + fcsk::kSegBlocks - 1) / fcsk::kSegBlocks);
+    const int n_blk = n_seg * fcsk::kSegBlocks;
     const long long nsb = (nt + fcsk::kScanBlock - 1) / fcsk::kScanBlock;
     const long long nseg = E * n_seg;
     const long long nsegb = (nseg + fcsk::kScanBlock - 1) / fcsk::kScanBlock;
@@ -479,7 +515,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
         (rc = ensure(c, c->w_blk_offs, nsb * 16)) ||
         (rc = ensure(c, c->w_task_hoff, want_hits ? nt * 4 : 4)) ||
         (rc = ensure(c, c->w_chunks, (size_t)c->chunk_cap * 16)) ||
-        (rc = ensure(c, c->w_small_key, nt * 4)) || (rc = ensure(c, c->w_small_off, nt * 4)) ||
+        (rc = ensure(c, c->w_small_rec, (size_t)nt * 32)) ||
         (rc = ensure(c, c->w_tile_first, (nt + 1) * 4)) ||
         (rc = ensure(c, c->w_seg_cnt, nseg * 4)) || (rc = ensure(c, c->w_seg_off, nseg * 4)) ||
         (rc = ensure(c, c->w_seg_blk, nsegb * 4)))
@@ -557,8 +593,9 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->blk_offs = (int32_t*)c->w_blk_offs.p;
     P->task_hoff = (int32_t*)c->w_task_hoff.p;
     P->chunks = (int4*)c->w_chunks.p;
-    P->small_key = (int32_t*)c->w_small_key.p;
-    P->small_off = (int32_t*)c->w_small_off.p;
+    P->small_rec = (int4*)c->w_small_rec.p;
+    P->geo_layers = (const int4*)c->g_layers.p;
+    P->geo_regions = (const int4*)c->g_regions.p;
     P->tile_first = (int32_t*)c->w_tile_first.p;
     P->cells = dense_out ? dense_out : (float*)c->w_cells.p;
     P->flags = (uint8_t*)c->w_flags.p;
@@ -566,6 +603,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->seg_off = (int32_t*)c->w_seg_off.p;
     P->seg_blk = (int32_t*)c->w_seg_blk.p;
     P->ctr = (Counters*)c->w_ctr.p;
+    P->queue = (int32_t*)c->w_queue.p;
     if (dout) {
         P->out_elayer = dout->elayer;
         P->out_counts = dout->counts;
@@ -584,6 +622,9 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->out_base = sh.out_base;
     return FCS_OK;
 }
+
+// LDS bytes of the geometry records the hit kernels stage
+size_t geo_lds_bytes(const Params& P) { return (size_t)(3 * P.n_layers + 2 * P.n_layers * P.n_regions) * 16; }
 
 // Enqueue the launch sequence of one batch on c->stream.  All kernels read
 // the device Params block, so a sequence can be captured once and replayed.
@@ -610,7 +651,7 @@ void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, int g
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
     }
     if (part == kAll || part == kHits)
-        hipLaunchKernelGGL(fcsk::k_hits, dim3(grid), dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_hits, dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
     if (part == kAll || part == kPost) {
         const unsigned nw = grid_for(P.n_events * P.n_seg, fcsk::kBlock / fcsk::kWave);
         hipLaunchKernelGGL(fcsk::k_seg_count, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
@@ -647,6 +688,8 @@ int counters_error(fcs_ctx* c, const Counters& k)
     if (k.error & fcsk::kErrParticle)
         return fail(c, FCS_E_INVALID_ARG, "particle energy must be finite and > 0, eta/phi finite");
     if (k.error & fcsk::kErrOffsets) return fail(c, FCS_E_INVALID_ARG, "malformed event_offsets");
+    if (k.error & fcsk::kErrOverride)
+        return fail(c, FCS_E_INVALID_ARG, "elayer_override holds a negative or non-finite energy");
     if (k.error & fcsk::kErrTooManyHits)
         return fail(c, FCS_E_CAPACITY, "more than 2^31-1 hits in one batch: split the batch");
     return FCS_OK;
@@ -1082,7 +1125,8 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
-        hipLaunchKernelGGL(fcsk::k_adjoint, dim3(c->n_cu * tu.wg_per_cu), dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_adjoint, dim3(c->n_cu * tu.wg_per_cu), dim3(fcsk::kBlock),
+                           geo_lds_bytes(*P), s, dP);
         if (grad_elayer)
             hipLaunchKernelGGL(fcsk::k_adj_elayer, dim3(grid_for(nt, 256)), dim3(256), 0, s, dP);
         if (grad_weights)

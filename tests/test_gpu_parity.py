@@ -133,9 +133,9 @@ def test_single_pion_diff_config(sim, oracle_lib, geom_full, param_full, geo, to
 
 
 @pytest.mark.parametrize("tuning", [
-    dict(chunk_hits=256, big_task_hits=1, tile_hits=256, wg_per_cu=1),
-    dict(chunk_hits=4096, big_task_hits=4096, tile_hits=4096, wg_per_cu=8),
-    dict(chunk_hits=1000, big_task_hits=37, tile_hits=512, wg_per_cu=2, use_graph=False),
+    dict(chunk_hits=64, big_task_hits=1, tile_hits=64, wg_per_cu=1),
+    dict(chunk_hits=8192, big_task_hits=512, tile_hits=512, wg_per_cu=8),
+    dict(chunk_hits=1000, big_task_hits=37, tile_hits=192, wg_per_cu=2, use_graph=False),
 ])
 def test_tuning_does_not_change_results(sim, oracle_lib, geom_full, param_full, geo, torch_cuda,
                                         tuning):
