@@ -33,12 +33,45 @@ N_CU, CLOCK_HZ = 256, 2.4e9
 VALU_LANE_OPS_PEAK = N_CU * 64 * CLOCK_HZ       # 32-bit VALU lane-ops per second
 HBM_PEAK = 8.0e12
 
-# Algorithmic 32-bit operations per hit (lane-ops): Philox4x32-10 = 10 rounds
-# x (2 32x32->64 multiplies + 4 xor) + 9 x 2 key adds = 78; three 24-bit
-# uniforms = 9; guide-table bin search ~ 4; placement (radius, octant sine /
-# cosine polynomials, quadrant, deta / dphi, add, wrap) = 37; region-grid
-# lookup = 19.  One deposit per hit.
-OPS_PER_HIT = 78 + 9 + 4 + 37 + 19
+# Algorithmic 32-bit operations per hit (a 32x32->64 product counts as its two
+# 32-bit halves): Philox4x32-10 = 10 rounds x (2 products = 4 + 4 xor) = 80
+# (the key schedule is shared by all hits); three 24-bit uniforms (shift,
+# convert, scale) = 9; bin choice from the guide table (index + ~2 compares)
+# = 3; radial / angular bin split = 2; radius = 4; octant sine and cosine
+# (offset, square, 4 + 5 multiply-add steps, final multiply, quadrant select)
+# = 24; deta / dphi = 4; eta / phi = 2; phi wrap = 3; region-grid lookup
+# (acceptance, region, two floor-and-clamp indices, linear index) = 22;
+# deposit = 1.
+OPS_PER_HIT = 80 + 9 + 3 + 2 + 4 + 24 + 4 + 2 + 3 + 22 + 1
+KERNEL_SOURCES = ("paper_2103_14737_amd/csrc/fcs_math.hpp",
+                  "paper_2103_14737_amd/csrc/fcs_kernels.hpp",
+                  "paper_2103_14737_amd/csrc/fcs_runtime.hip",
+                  "paper_2103_14737_amd/build.py")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hits_traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, tuning):
+    """HBM bytes per launch of the hit kernel from the committed counter
+    summary, if it was taken on the current kernel sources, this workload and
+    this tuning; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload
+            or t.get("tuning") != tuning):
+        return None
+    return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
 
 
 def _sync(torch):
@@ -70,6 +103,8 @@ def main():
     ap.add_argument("--workload", default="single_particle_sweep",
                     choices=["single_particle_sweep", "hard_scatter", "pileup"],
                     help="headline workload to time (the other choices are for profiling)")
+    ap.add_argument("--write-tuning", type=str, default="",
+                    help="write the tuning used as chunk,big,tile,wg to this file")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter scaling)")
     args = ap.parse_args()
@@ -123,6 +158,11 @@ def main():
                                hit_energy_scale=w.hit_energy_scale,
                                verbose=bool(os.environ.get("FCS_TUNE_VERBOSE")))
         print(f"bench: autotuned {tuning} in {time.perf_counter() - t0:.1f} s", flush=True)
+    if args.write_tuning:
+        with open(args.write_tuning, "w") as f:
+            t_ = tuning or {}
+            f.write(",".join(str(t_.get(k, 0)) for k in ("chunk_hits", "big_task_hits",
+                                                          "tile_hits", "wg_per_cu")))
     stats = []
 
     def step_batched(profile=True):
@@ -160,7 +200,9 @@ def main():
     achieved = ops / (kernel_ms * 1e-3)
     line["roofline"] = {"kernel": "k_hits", "bound": "alu", "achieved": achieved / 1e12,
                         "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tops/s",
-                        "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None,
+                        "frac": achieved / VALU_LANE_OPS_PEAK,
+                        "traffic": measured_traffic(args.workload, tuning),
+                        "kernel_source_hash": kernel_source_hash(),
                         "ops_per_hit": OPS_PER_HIT, "hits_per_launch": hits_per_step,
                         "kernel_ms": kernel_ms}
 

@@ -17,10 +17,10 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fcs_mi355x_tune
 # (chunk_hits, big_task_hits, tile_hits, wg_per_cu)
 CANDIDATES = [
     (c, b, t, w)
-    for c in (512, 1024, 2048, 4096)
-    for b in (32, 64, 128)
+    for c in (1024, 2048, 4096, 8192)
+    for b in (32, 64, 128, 256)
     for t in (256, 512)
-    for w in (4, 5, 8)
+    for w in (3, 4, 5, 8)
     if b <= t
 ]
 

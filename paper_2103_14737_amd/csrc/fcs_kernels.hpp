@@ -1209,39 +1209,59 @@ __global__ __launch_bounds__(kBlock) void k_seg_write(const Params* __restrict__
     const uint32_t w = words[lane];
     // output position of this lane's first block: exclusive scan of lane sums
     const int mine = (int)(w & 0xff) + (int)((w >> 8) & 0xff) + (int)((w >> 16) & 0xff) + (int)(w >> 24);
-    const int incl = wave_incl_scan(mine);
+    const int lane_off = wave_incl_scan(mine) - mine;
     const long long base = P.out_base + G(P.seg_off)[gw];
     if (seg == 0 && lane == 0 && G(P.out_ev_off)) G(P.out_ev_off)[e] = base;
-    const int lane_off = incl - mine;
     const auto cells = G(P.cells) + e * P.n_cells;
     const unsigned long long below = (1ull << lane) - 1ull;
     unsigned long long lanes = __ballot(w != 0);
-    while (lanes) {
-        const int src = __ffsll((long long)lanes) - 1;
-        lanes &= lanes - 1;
-        const uint32_t ws = (uint32_t)__builtin_amdgcn_readlane((int)w, src);
-        int pos = __builtin_amdgcn_readlane(lane_off, src);
-        // the (up to four) blocks of lane src: load all, then write
-        float v[4];
+    uint32_t cur = 0;  // remaining block counts of the lane being walked
+    int cur_src = 0, cur_pos = 0;
+    constexpr int kBatch = 8;
+    // Walk the nonzero blocks in ascending order, kBatch at a time: the
+    // counts give each block's output position up front, so all loads of a
+    // batch are issued before any of them is used.
+    while (cur != 0 || lanes != 0) {
+        int blk[kBatch], pos[kBatch], nb = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const long long cell = (long long)(seg * kSegBlocks + src * 4 + j) * 64 + lane;
-            v[j] = ((ws >> (8 * j)) & 0xff) && cell < P.n_cells ? cells[cell] : 0.0f;
+        for (int b = 0; b < kBatch; ++b) {
+            blk[b] = -1;
+            pos[b] = 0;
+            if (cur == 0 && lanes != 0) {
+                cur_src = __ffsll((long long)lanes) - 1;
+                lanes &= lanes - 1;
+                cur = (uint32_t)__builtin_amdgcn_readlane((int)w, cur_src);
+                cur_pos = __builtin_amdgcn_readlane(lane_off, cur_src);
+            }
+            if (cur != 0) {
+                const int j = (__ffs((int)cur) - 1) >> 3;
+                const int cnt = (int)((cur >> (8 * j)) & 0xffu);
+                cur &= ~(0xffu << (8 * j));
+                blk[b] = seg * kSegBlocks + cur_src * 4 + j;
+                pos[b] = cur_pos;
+                cur_pos += cnt;
+                nb = b + 1;
+            }
+        }
+        float v[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const long long cell = (long long)blk[b] * 64 + lane;
+            v[b] = (blk[b] >= 0 && cell < P.n_cells) ? cells[cell] : 0.0f;
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (((ws >> (8 * j)) & 0xff) == 0) continue;
-            const long long cell = (long long)(seg * kSegBlocks + src * 4 + j) * 64 + lane;
-            const unsigned long long nz = __ballot(v[j] != 0.0f);
-            if (v[j] != 0.0f) {
-                const long long o = base + pos + __popcll(nz & below);
+        for (int b = 0; b < kBatch; ++b) {
+            if (b >= nb) break;
+            const long long cell = (long long)blk[b] * 64 + lane;
+            const unsigned long long nz = __ballot(v[b] != 0.0f);
+            if (v[b] != 0.0f) {
+                const long long o = base + pos[b] + __popcll(nz & below);
                 if (o < P.out_cap) {
                     G(P.out_ids)[o] = G(P.cell_id)[cell];
-                    G(P.out_e)[o] = v[j];
+                    G(P.out_e)[o] = v[b];
                 }
                 if (P.clean_cells) cells[cell] = 0.0f;
             }
-            pos += __popcll(nz);
         }
     }
     if (w) words[lane] = 0;

@@ -72,7 +72,7 @@ struct fcs_ctx {
     // workspace
     DevBuf w_particles, w_evoff, w_override, w_task_n, w_task_ehit, w_part_ev, w_part_p,
         w_part_set, w_blk_sums, w_blk_offs, w_task_hoff, w_chunks, w_small_rec,
-        w_tile_first, w_cells, w_flags, w_seg_cnt, w_seg_off, w_seg_blk, w_ctr, w_queue, w_params,
+        w_tile_first, w_cells, w_flags, w_seg_cnt, w_seg_off, w_seg_blk, w_queue, w_params,
         w_acc_el, w_acc_bins;
     long long cells_events = 0;  // events the accumulator holds (kept zero)
     long long flag_events = 0;
@@ -81,8 +81,12 @@ struct fcs_ctx {
     DevBuf o_cells, o_ids, o_e, o_evoff, o_heta, o_hphi, o_he, o_hcell, o_thoff, o_counts,
         o_elayer;
 
-    Params* h_params = nullptr;  // pinned
-    Counters* h_ctr = nullptr;   // pinned
+    // pinned host block holding the Params of a launch followed by its
+    // Counters; one copy uploads both (the counters zeroed), and the counters
+    // come back into the same place at the end of the launch
+    char* h_block = nullptr;
+    Params* h_params = nullptr;
+    Counters* h_ctr = nullptr;
     std::map<GraphKey, hipGraphExec_t> graphs;
 };
 
@@ -149,6 +153,9 @@ int upload(fcs_ctx* c, DevBuf& b, const T* src, size_t n)
 
 unsigned grid_for(long long n, int block) { return (unsigned)((n + block - 1) / block); }
 
+constexpr size_t kCtrOffset = (sizeof(Params) + 255) & ~(size_t)255;
+constexpr size_t kBlockBytes = kCtrOffset + ((sizeof(Counters) + 255) & ~(size_t)255);
+
 void drop_graphs(fcs_ctx* c)
 {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -209,12 +216,13 @@ int fcs_create(fcs_ctx** out, int device)
         hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_params, sizeof(Params)) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_ctr, sizeof(Counters)) != hipSuccess) {
+        hipHostMalloc((void**)&c->h_block, kBlockBytes) != hipSuccess) {
         fcs_destroy(c);
         return fail(nullptr, FCS_E_HIP, "stream/event/pinned allocation failed");
     }
-    if (ensure(c, c->w_params, sizeof(Params)) || ensure(c, c->w_ctr, sizeof(Counters)) ||
+    c->h_params = (Params*)c->h_block;
+    c->h_ctr = (Counters*)(c->h_block + kCtrOffset);
+    if (ensure(c, c->w_params, kBlockBytes) ||
         ensure(c, c->w_queue, 2 * fcsk::kQueues * fcsk::kQueueStride * sizeof(int32_t))) {
         fcs_destroy(c);
         return fail(nullptr, FCS_E_NOMEM, "device allocation failed");
@@ -240,13 +248,12 @@ void fcs_destroy(fcs_ctx* c)
                       &c->w_task_ehit, &c->w_part_ev, &c->w_part_p, &c->w_part_set,
                       &c->w_blk_sums, &c->w_blk_offs, &c->w_task_hoff, &c->w_chunks,
                       &c->w_small_rec, &c->w_tile_first, &c->w_cells, &c->g_layers, &c->g_regions,
-                      &c->w_flags, &c->w_seg_cnt, &c->w_seg_off, &c->w_seg_blk, &c->w_ctr, &c->w_queue,
+                      &c->w_flags, &c->w_seg_cnt, &c->w_seg_off, &c->w_seg_blk, &c->w_queue,
                       &c->w_params, &c->w_acc_el, &c->w_acc_bins, &c->o_cells, &c->o_ids,
                       &c->o_e, &c->o_evoff, &c->o_heta, &c->o_hphi, &c->o_he, &c->o_hcell,
                       &c->o_thoff, &c->o_counts, &c->o_elayer};
     for (DevBuf* b : bufs) release(c, *b);
-    if (c->h_params) (void)hipHostFree(c->h_params);
-    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+    if (c->h_block) (void)hipHostFree(c->h_block);
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
@@ -602,7 +609,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->seg_cnt = (int32_t*)c->w_seg_cnt.p;
     P->seg_off = (int32_t*)c->w_seg_off.p;
     P->seg_blk = (int32_t*)c->w_seg_blk.p;
-    P->ctr = (Counters*)c->w_ctr.p;
+    P->ctr = (Counters*)((char*)c->w_params.p + kCtrOffset);
     P->queue = (int32_t*)c->w_queue.p;
     if (dout) {
         P->out_elayer = dout->elayer;
@@ -637,7 +644,6 @@ void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, int g
     const Params* dP = (const Params*)c->w_params.p;
     hipStream_t s = c->stream;
     if (part == kAll || part == kPre) {
-        hipLaunchKernelGGL(fcsk::k_reset_counters, dim3(1), dim3(64), 0, s, dP);
         if (validate)
             hipLaunchKernelGGL(fcsk::k_validate,
                                dim3(grid_for(std::max(P.n_particles, P.n_events), 256)), dim3(256),
@@ -699,14 +705,19 @@ int counters_error(fcs_ctx* c, const Counters& k)
 int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
               const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
               float* dense_out, const fcs_sim_output* dout, bool want_hits, bool validate,
-              bool use_graph, bool profile, Counters* res, double* kernel_ms)
+              bool use_graph, bool profile, Counters* res, double* kernel_ms, bool small_launch)
 {
-    const int grid = c->n_cu * tu.wg_per_cu;
+    // a launch over few particles (per-event mode) gets a grid sized to its
+    // tasks instead of filling the chip with idle persistent workgroups
+    int grid = c->n_cu * tu.wg_per_cu;
+    if (small_launch)
+        grid = (int)std::min<long long>(grid, std::max<long long>(16, (sh.n_particles * c->n_layers + 3) / 4));
     for (int attempt = 0; attempt < 2; ++attempt) {
         Params* P = c->h_params;
         int rc = prepare(c, o, tu, sh, d_particles, d_evoff, d_override, dense_out, dout, want_hits, P);
         if (rc) return rc;
-        HIPCHK(c, hipMemcpyAsync(c->w_params.p, P, sizeof(Params), hipMemcpyHostToDevice, c->stream));
+        std::memset(c->h_ctr, 0, sizeof(Counters));
+        HIPCHK(c, hipMemcpyAsync(c->w_params.p, c->h_block, kBlockBytes, hipMemcpyHostToDevice, c->stream));
         const bool dense = dense_out != nullptr;
         GraphKey key{sh.n_particles, sh.n_events, dense ? 1 : 0, validate ? 1 : 0, grid, kAll};
         if (use_graph && !profile) {
@@ -731,7 +742,8 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             }
             HIPCHK(c, hipGetLastError());
         }
-        HIPCHK(c, hipMemcpyAsync(c->h_ctr, c->w_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->h_ctr, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
+                                 hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         *res = *c->h_ctr;
         if ((res->error & fcsk::kErrChunkCap) && attempt == 0) {
@@ -950,7 +962,7 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
         Shape sh{N, 0, n_events, 0, 0, 0};
         Counters k;
         rc = run_range(c, o, tu, sh, in.d_particles, in.d_evoff, in.d_override, d.cells, &d,
-                       want_hits, in.validate_on_device, o->use_graph != 0, profile, &k, &kms);
+                       want_hits, in.validate_on_device, o->use_graph != 0, profile, &k, &kms, false);
         if (rc) return rc;
         hits = k.hits_total;
         hits_out = k.hits_out;
@@ -979,7 +991,7 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
             const float* dov = in.d_override ? in.d_override + p0 * L : nullptr;
             Counters k;
             rc = run_range(c, o, tu, sh, dp, in.d_evoff + e, dov, de.cells, &de, want_hits,
-                           in.validate_on_device, false, profile, &k, &kms);
+                           in.validate_on_device, false, profile, &k, &kms, true);
             if (rc) return rc;
             hits += k.hits_total;
             hits_out += k.hits_out;
@@ -1059,8 +1071,8 @@ int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* ev
     if ((rc = prepare(c, o, tu, sh, in.d_particles, in.d_evoff, nullptr, nullptr, nullptr, false, P)))
         return rc;
     const Params* dP = (const Params*)c->w_params.p;
-    HIPCHK(c, hipMemcpyAsync(c->w_params.p, P, sizeof(Params), hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL(fcsk::k_reset_counters, dim3(1), dim3(64), 0, c->stream, dP);
+    std::memset(c->h_ctr, 0, sizeof(Counters));
+    HIPCHK(c, hipMemcpyAsync(c->w_params.p, c->h_block, kBlockBytes, hipMemcpyHostToDevice, c->stream));
     if (in.validate_on_device)
         hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(in.N, (long long)n_events), 256)),
                            dim3(256), 0, c->stream, dP);
@@ -1069,7 +1081,8 @@ int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* ev
     hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, c->stream, dP);
     hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, c->stream, dP);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(c->h_ctr, c->w_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_ctr, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
+                             hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const Counters k = *c->h_ctr;
     if ((rc = counters_error(c, k))) return rc;
@@ -1112,8 +1125,8 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         P->grad_weights = grad_weights;
         const Params* dP = (const Params*)c->w_params.p;
         hipStream_t s = c->stream;
-        HIPCHK(c, hipMemcpyAsync(c->w_params.p, P, sizeof(Params), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(fcsk::k_reset_counters, dim3(1), dim3(64), 0, s, dP);
+        std::memset(c->h_ctr, 0, sizeof(Counters));
+        HIPCHK(c, hipMemcpyAsync(c->w_params.p, c->h_block, kBlockBytes, hipMemcpyHostToDevice, s));
         if (in.validate_on_device)
             hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(in.N, (long long)n_events), 256)),
                                dim3(256), 0, s, dP);
@@ -1132,7 +1145,8 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         if (grad_weights)
             hipLaunchKernelGGL(fcsk::k_adj_weights, dim3((unsigned)c->n_hist), dim3(fcsk::kBlock), 0, s, dP);
         HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipMemcpyAsync(c->h_ctr, c->w_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(c->h_ctr, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
+                                 hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
         const Counters k = *c->h_ctr;
         if ((k.error & fcsk::kErrChunkCap) && attempt == 0) {
