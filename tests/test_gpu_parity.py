@@ -313,3 +313,49 @@ def test_backward_matches_oracle_gradient(sim, oracle_lib, geom_full, param_full
     sW = np.abs(dW_ref).max()
     assert np.all(np.abs(dW - dW_ref) <= 1e-5 * np.abs(dW_ref) + 1e-6 * sW)
     assert np.count_nonzero(dW_ref) > 0
+
+
+def test_autograd_function(sim, oracle_lib, geom_full, param_full, geo, par, torch_cuda):
+    """simulate_dense: forward equals the oracle run with the same layer
+    energies; backward equals fcs_backward on the incoming gradient."""
+    torch = torch_cuda
+    from paper_2103_14737_amd.autograd import simulate_dense
+    w = W.subset_events(W.single_pion_diff(), 0, 16)
+    C = geo["n_cells"]
+    base = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed)
+    el_ref = base["elayer"].astype(np.float32)
+    ref = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
+                              elayer_override=el_ref)
+    ep = oracle_lib.perturbed_elayer(param_full, w.particles, w.event_offsets, w.seed)
+    T = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
+                            elayer_override=ep)
+    Td = np.zeros((w.n_events, C))
+    for e in range(w.n_events):
+        s, t = T["ev_cell_off"][e], T["ev_cell_off"][e + 1]
+        Td[e, T["cell_idx"][s:t]] = T["cell_e"][s:t]
+
+    dp, doff = _dev(w, torch)
+    el = torch.from_numpy(el_ref).cuda().requires_grad_()
+    wt = torch.from_numpy(par["weights"]).cuda().requires_grad_()
+    cells = simulate_dense(sim, dp, doff, w.seed, el, wt)
+    torch.cuda.synchronize()
+    print(f"[parity] autograd forward: {ref['n_hits_total']} hits", flush=True)
+    got = _np(cells.detach()).astype(np.float64)
+    for e in range(w.n_events):
+        s, t = ref["ev_cell_off"][e], ref["ev_cell_off"][e + 1]
+        idx = ref["cell_idx"][s:t]
+        assert np.count_nonzero(got[e]) == t - s
+        err = np.abs(got[e, idx] - ref["cell_e"][s:t])
+        assert np.all(err <= np.maximum(REL * np.abs(ref["cell_e"][s:t]), ABS))
+
+    loss = ((cells - torch.from_numpy(Td).float().cuda()) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    g = (2.0 * (cells.detach() - torch.from_numpy(Td).float().cuda())).reshape(-1)
+    dE, dW = sim.backward(dp, doff, w.seed, g, elayer_override=el.detach())
+    torch.cuda.synchronize()
+    for a, b in ((el.grad, dE), (wt.grad, dW)):
+        a, b = _np(a).astype(np.float64), _np(b).astype(np.float64)
+        assert np.count_nonzero(b) > 0
+        # same kernel, same incoming gradient: FP64 atomic order only
+        assert np.all(np.abs(a - b) <= 1e-6 * np.abs(b) + 1e-9 * np.abs(b).max())
