@@ -668,18 +668,30 @@ struct GeoLds {
 
 __device__ __forceinline__ float f_of(int v) { return __int_as_float(v); }
 
+// The three records of a layer (acceptance and 1/R; region lower edges).
+struct LayerRec {
+    v4i a, b0, b1;
+};
+
+__device__ __forceinline__ LayerRec layer_rec(const GeoLds& g, int l)
+{
+    return LayerRec{g.layers[3 * l], g.layers[3 * l + 1], g.layers[3 * l + 2]};
+}
+
 // region-grid lookup (Listing 2's getDDE): -1 outside the acceptance
 // [eta_lo(first region), eta_hi(last region)); the region is the number of
-// interior region edges <= eta; cell indices are clamped into the grid
-__device__ __forceinline__ int lookup_cell(const GeoLds& g, int l, float eta, float phi)
+// interior region edges <= eta (only the layer's n_regions - 1 real edges are
+// compared); cell indices are clamped into the grid
+__device__ __forceinline__ int lookup_cell(const GeoLds& g, const LayerRec& lr, int l, float eta,
+                                           float phi)
 {
-    const v4i a = g.layers[3 * l];
-    if (!(eta >= f_of(a.x)) || !(eta < f_of(a.y))) return -1;
-    const v4i b0 = g.layers[3 * l + 1];
-    const v4i b1 = g.layers[3 * l + 2];
-    const int k = (int)(eta >= f_of(b0.y)) + (int)(eta >= f_of(b0.z)) + (int)(eta >= f_of(b0.w)) +
-                  (int)(eta >= f_of(b1.x)) + (int)(eta >= f_of(b1.y)) + (int)(eta >= f_of(b1.z)) +
-                  (int)(eta >= f_of(b1.w));
+    if (!(eta >= f_of(lr.a.x)) || !(eta < f_of(lr.a.y))) return -1;
+    // edges past the last region are +inf and never counted; layers of at
+    // most four regions (a uniform branch) compare only the first three
+    int k = (int)(eta >= f_of(lr.b0.y)) + (int)(eta >= f_of(lr.b0.z)) + (int)(eta >= f_of(lr.b0.w));
+    if (g.n_regions > 4)
+        k += (int)(eta >= f_of(lr.b1.x)) + (int)(eta >= f_of(lr.b1.y)) + (int)(eta >= f_of(lr.b1.z)) +
+             (int)(eta >= f_of(lr.b1.w));
     const int r = l * g.n_regions + k;
     const v4i f = g.regions[2 * r];
     const v4i iv = g.regions[2 * r + 1];
@@ -689,8 +701,6 @@ __device__ __forceinline__ int lookup_cell(const GeoLds& g, int l, float eta, fl
     ip = min(max(ip, 0), iv.y - 1);
     return iv.z + ie * iv.y + ip;
 }
-
-__device__ __forceinline__ float layer_inv_r(const GeoLds& g, int l) { return f_of(g.layers[3 * l].z); }
 
 // stage the geometry tables into LDS (call with every thread, then sync)
 __device__ __forceinline__ GeoLds stage_geometry(const Params& P, v4i* s_geo)
@@ -728,11 +738,12 @@ struct HitOut {
 // -> three 24-bit uniforms -> (r, alpha) bin -> position in the bin ->
 // (eta, phi) -> cell
 template <typename CumT, typename GuideT>
-__device__ __forceinline__ HitOut simulate_hit(const GeoLds& g, CumT cum, GuideT guide, float dr,
-                                               uint32_t k0, uint32_t k1, uint32_t i, uint32_t l,
-                                               uint32_t pin, uint32_t evg, float eta_p, float phi_p,
-                                               float inv_r)
+__device__ __forceinline__ HitOut simulate_hit(const GeoLds& g, const LayerRec& lr, CumT cum,
+                                               GuideT guide, float dr, uint32_t k0, uint32_t k1,
+                                               uint32_t i, uint32_t l, uint32_t pin, uint32_t evg,
+                                               float eta_p, float phi_p)
 {
+    const float inv_r = f_of(lr.a.z);
     const U4 x = philox4x32_10(i, l | (kTagHit << 8), pin, evg, k0, k1);
     const float u0 = unit24(x.x), u1 = unit24(x.y), u2 = unit24(x.z);
     HitOut h;
@@ -747,11 +758,12 @@ __device__ __forceinline__ HitOut simulate_hit(const GeoLds& g, CumT cum, GuideT
     float phi = phi_p + dphi;
     const float pi_f = 3.14159265358979323846f;
     const float two_pi_f = 6.28318530717958647692f;
-    if (phi >= pi_f) phi = phi - two_pi_f;
-    else if (phi < -pi_f) phi = phi + two_pi_f;
+    // one wrap into [-pi_f, pi_f), both candidates computed, no branch
+    const float lo = phi - two_pi_f, hi = phi + two_pi_f;
+    phi = phi >= pi_f ? lo : (phi < -pi_f ? hi : phi);
     h.eta = eta;
     h.phi = phi;
-    h.cell = lookup_cell(g, (int)l, eta, phi);
+    h.cell = lookup_cell(g, lr, (int)l, eta, phi);
     return h;
 }
 
@@ -1038,12 +1050,11 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
             reinterpret_cast<v4i*>(cum)[lane] = ((const FCS_AS_GLOBAL v4i*)(G(P.cum) + hb))[lane];
             w_guide4[wv][lane] = ((const FCS_AS_GLOBAL uint32_t*)(G(P.guide) + hb))[lane];
             wave_sync();
-            const float inv_r = layer_inv_r(geo, ck.l);
+            const LayerRec lrec = layer_rec(geo, ck.l);
             const long long hbase = P.want_hits ? (long long)G(P.task_hoff)[ck.t] : 0;
             for (int i = ck.first + lane; i < ck.first + ck.count; i += kWave) {
-                const HitOut h = simulate_hit(geo, cum, guide, dr, k0, k1, (uint32_t)i,
-                                              (uint32_t)ck.l, ck.pin, ck.evg, ck.eta_p, ck.phi_p,
-                                              inv_r);
+                const HitOut h = simulate_hit(geo, lrec, cum, guide, dr, k0, k1, (uint32_t)i,
+                                              (uint32_t)ck.l, ck.pin, ck.evg, ck.eta_p, ck.phi_p);
                 if (P.want_hits) write_hit(P, hbase + i, h, ck.ehit);
                 n_out += h.cell < 0 ? 1 : 0;
                 bool pending = h.cell >= 0;
@@ -1083,10 +1094,11 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                 const bool valid = k < hcount;
                 const int kk = valid ? k : hcount - 1;
                 const SmallHit sh = small_hit(P, s0 + list[kk], h0 + kk);
-                const HitOut h = simulate_hit(geo, G(P.cum) + (long long)sh.H * kBins,
+                const HitOut h = simulate_hit(geo, layer_rec(geo, sh.l),
+                                              G(P.cum) + (long long)sh.H * kBins,
                                               G(P.guide) + (long long)sh.H * kBins, dr, k0, k1,
                                               (uint32_t)sh.i, (uint32_t)sh.l, sh.pin, sh.evg,
-                                              sh.eta_p, sh.phi_p, layer_inv_r(geo, sh.l));
+                                              sh.eta_p, sh.phi_p);
                 if (valid && P.want_hits)
                     write_hit(P, (long long)G(P.task_hoff)[sh.t] + sh.i, h, sh.ehit);
                 n_out += (valid && h.cell < 0) ? 1 : 0;
@@ -1109,6 +1121,29 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     }
     const long long tot = block_sum_ll(n_out);
     if (threadIdx.x == 0 && tot) (void)gfetch_add(&G(P.ctr)->hits_out, tot);
+}
+
+// ---------------------------------------------- range-checked loads ---
+// Raw buffer loads: a load at a byte offset at or beyond the resource's size
+// returns 0 and reads no memory, so a batch of loads needs no branch (and no
+// wait between its loads) to skip unused slots.  Word 3 selects the 32-bit
+// data format of the gfx9 family.
+constexpr int kBufWord3 = 0x00020000;
+constexpr uint32_t kBufNone = 0xFFFFFFF0u;  // an offset beyond every resource here
+
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kBufWord3);
+}
+
+__device__ inline float buf_load_f32(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+__device__ inline long long buf_load_i64(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(long long, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
 // ------------------------------------------ ordered compaction (a10) ---
@@ -1202,9 +1237,15 @@ __global__ __launch_bounds__(kBlock) void k_seg_write(const Params* __restrict__
     const Params& P = *Pp;
     const long long gw = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (gw >= P.n_events * P.n_seg) return;
+    // Parameters used after the first store are kept in registers: the
+    // compiler cannot tell the output stores from the parameter block.
     const long long e = gw / P.n_seg;
     const int seg = (int)(gw - e * P.n_seg);
     const int lane = lane_id();
+    const long long n_cells = P.n_cells, out_cap = P.out_cap;
+    const bool clean = P.clean_cells != 0;
+    const auto out_ids = G(P.out_ids);
+    const auto out_e = G(P.out_e);
     const auto words = (FCS_AS_GLOBAL uint32_t*)(G(P.flags) + e * P.n_blk + seg * kSegBlocks);
     const uint32_t w = words[lane];
     // output position of this lane's first block: exclusive scan of lane sums
@@ -1212,7 +1253,10 @@ __global__ __launch_bounds__(kBlock) void k_seg_write(const Params* __restrict__
     const int lane_off = wave_incl_scan(mine) - mine;
     const long long base = P.out_base + G(P.seg_off)[gw];
     if (seg == 0 && lane == 0 && G(P.out_ev_off)) G(P.out_ev_off)[e] = base;
-    const auto cells = G(P.cells) + e * P.n_cells;
+    const auto cells = G(P.cells) + e * n_cells;
+    // n_cells <= 2^28, so every byte offset below fits 32 bits
+    const auto cells_r = buf_rsrc((const float*)cells, (uint32_t)(n_cells * 4));
+    const auto ids_r = buf_rsrc((const long long*)G(P.cell_id), (uint32_t)(n_cells * 8));
     const unsigned long long below = (1ull << lane) - 1ull;
     unsigned long long lanes = __ballot(w != 0);
     uint32_t cur = 0;  // remaining block counts of the lane being walked
@@ -1243,12 +1287,16 @@ __global__ __launch_bounds__(kBlock) void k_seg_write(const Params* __restrict__
                 nb = b + 1;
             }
         }
+        // range-checked loads: unused slots and cells past the last one read 0
         float v[kBatch];
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            const long long cell = (long long)blk[b] * 64 + lane;
-            v[b] = (blk[b] >= 0 && cell < P.n_cells) ? cells[cell] : 0.0f;
-        }
+        for (int b = 0; b < kBatch; ++b)
+            v[b] = buf_load_f32(cells_r, blk[b] < 0 ? kBufNone : (uint32_t)(blk[b] * 64 + lane) * 4u);
+        // gather the ids of the nonzero cells before the first store
+        long long id[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+            id[b] = buf_load_i64(ids_r, v[b] != 0.0f ? (uint32_t)(blk[b] * 64 + lane) * 8u : kBufNone);
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             if (b >= nb) break;
@@ -1256,11 +1304,11 @@ __global__ __launch_bounds__(kBlock) void k_seg_write(const Params* __restrict__
             const unsigned long long nz = __ballot(v[b] != 0.0f);
             if (v[b] != 0.0f) {
                 const long long o = base + pos[b] + __popcll(nz & below);
-                if (o < P.out_cap) {
-                    G(P.out_ids)[o] = G(P.cell_id)[cell];
-                    G(P.out_e)[o] = v[b];
+                if (o < out_cap) {
+                    out_ids[o] = id[b];
+                    out_e[o] = v[b];
                 }
-                if (P.clean_cells) cells[cell] = 0.0f;
+                if (clean) cells[cell] = 0.0f;
             }
         }
     }
@@ -1308,13 +1356,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
             reinterpret_cast<v4i*>(cum)[lane] = ((const FCS_AS_GLOBAL v4i*)(G(P.cum) + hb))[lane];
             w_guide4[wv][lane] = ((const FCS_AS_GLOBAL uint32_t*)(G(P.guide) + hb))[lane];
             wave_sync();
-            const float inv_r = layer_inv_r(geo, ck.l);
+            const LayerRec lrec = layer_rec(geo, ck.l);
             const auto g = G(P.grad_cells) + (long long)ck.ev * C;
             double gsum = 0.0;
             for (int i = ck.first + lane; i < ck.first + ck.count; i += kWave) {
-                const HitOut h = simulate_hit(geo, cum, guide, dr, k0, k1, (uint32_t)i,
-                                              (uint32_t)ck.l, ck.pin, ck.evg, ck.eta_p, ck.phi_p,
-                                              inv_r);
+                const HitOut h = simulate_hit(geo, lrec, cum, guide, dr, k0, k1, (uint32_t)i,
+                                              (uint32_t)ck.l, ck.pin, ck.evg, ck.eta_p, ck.phi_p);
                 if (h.cell < 0) continue;
                 const double gc = (double)g[h.cell];
                 gsum += gc;
@@ -1337,10 +1384,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
             wave_tile_owners(P, ctr, item - n_chunks, list, s0, h0, hcount);
             for (int k = lane; k < hcount; k += kWave) {
                 const SmallHit sh = small_hit(P, s0 + list[k], h0 + k);
-                const HitOut h = simulate_hit(geo, G(P.cum) + (long long)sh.H * kBins,
+                const HitOut h = simulate_hit(geo, layer_rec(geo, sh.l),
+                                              G(P.cum) + (long long)sh.H * kBins,
                                               G(P.guide) + (long long)sh.H * kBins, dr, k0, k1,
                                               (uint32_t)sh.i, (uint32_t)sh.l, sh.pin, sh.evg,
-                                              sh.eta_p, sh.phi_p, layer_inv_r(geo, sh.l));
+                                              sh.eta_p, sh.phi_p);
                 if (h.cell < 0) continue;
                 const double gc = (double)G(P.grad_cells)[(long long)sh.ev * C + h.cell];
                 gadd(G(P.acc_elayer) + sh.t, gc);

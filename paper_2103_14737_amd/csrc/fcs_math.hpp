@@ -30,8 +30,9 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
         const uint64_t pb = (uint64_t)c2 * 0xCD9E8D57u;
         const uint32_t hi_a = (uint32_t)(pa >> 32), lo_a = (uint32_t)pa;
         const uint32_t hi_b = (uint32_t)(pb >> 32), lo_b = (uint32_t)pb;
-        const uint32_t y0 = hi_b ^ c1 ^ k0;
-        const uint32_t y2 = hi_a ^ c3 ^ k1;
+        // three-input xor in one v_bitop3_b32 (truth table 0x96 = a ^ b ^ c)
+        const uint32_t y0 = __builtin_amdgcn_bitop3_b32(hi_b, c1, k0, 0x96);
+        const uint32_t y2 = __builtin_amdgcn_bitop3_b32(hi_a, c3, k1, 0x96);
         c0 = y0;
         c1 = lo_b;
         c2 = y2;
@@ -260,15 +261,16 @@ __device__ __forceinline__ void sincos_bin(int ia, float u, float& cs, float& sn
     const float c0 = cp;
     // quadrant table: even bins  m=0:(c,s) 1:(-s,c) 2:(-c,-s) 3:(s,-c)
     //                 odd bins   m=1:(s,c) 2:(-c,s) 3:(-s,-c) 4:(c,-s)
+    // i.e. a rotation by q = m mod 4 quarter turns of (c0, +-s0), with the
+    // sine negated for odd bins.  Selected without branches: a swap for odd
+    // q, then sign flips (exact) for the negated entries.
     const int q = m & 3;
-    float c, s;
-    if (even) {
-        c = (q == 0) ? c0 : (q == 1) ? -s0 : (q == 2) ? -c0 : s0;
-        s = (q == 0) ? s0 : (q == 1) ? c0 : (q == 2) ? -s0 : -c0;
-    } else {
-        c = (q == 1) ? s0 : (q == 2) ? -c0 : (q == 3) ? -s0 : c0;
-        s = (q == 1) ? c0 : (q == 2) ? s0 : (q == 3) ? -c0 : -s0;
-    }
+    const float s1 = __int_as_float(__float_as_int(s0) ^ ((ia & 1) << 31));
+    const bool swap = (q & 1) != 0;
+    const float a = swap ? s1 : c0;
+    const float b = swap ? c0 : s1;
+    const float c = __int_as_float(__float_as_int(a) ^ (((q ^ (q >> 1)) & 1) << 31));
+    const float s = __int_as_float(__float_as_int(b) ^ ((q & 2) << 30));
     cs = c;
     sn = s;
 }

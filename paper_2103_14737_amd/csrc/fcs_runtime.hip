@@ -287,8 +287,8 @@ int fcs_load_geometry(fcs_ctx* c, const fcs_geometry* g)
         return fail(c, FCS_E_INVALID_ARG, "n_layers = %d outside [1, 64]", g->n_layers);
     if (g->n_regions < 1 || g->n_regions > 8)
         return fail(c, FCS_E_INVALID_ARG, "n_regions = %d outside [1, 8]", g->n_regions);
-    if (g->n_cells < 1 || g->n_cells > (1LL << 30))
-        return fail(c, FCS_E_INVALID_ARG, "n_cells = %lld outside [1, 2^30]", (long long)g->n_cells);
+    if (g->n_cells < 1 || g->n_cells > (1LL << 28))
+        return fail(c, FCS_E_INVALID_ARG, "n_cells = %lld outside [1, 2^28]", (long long)g->n_cells);
     const void* ptrs[] = {g->cell_id, g->reg_eta_lo, g->reg_eta_hi, g->reg_inv_deta,
                           g->reg_inv_dphi, g->reg_phi_lo, g->reg_neta, g->reg_nphi,
                           g->reg_offset, g->layer_inv_r};
