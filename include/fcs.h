@@ -180,7 +180,7 @@ typedef struct {
     int32_t nhit_cap;           /* hits per (particle, layer) are capped     */
     double min_layer_energy_mev;/* layers with less energy get no hits       */
     int32_t chunk_hits;         /* tuning, 0 = default: hits per work item of
-                                   a large (particle, layer) task           */
+                                   a large (particle, layer) task, <= 32768 */
     int32_t big_task_hits;      /* tuning, 0 = default: tasks with at least
                                    this many hits are chunked and get a
                                    private cell accumulator                 */

@@ -22,6 +22,8 @@ namespace fcsk {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kBins = 256;
+constexpr int kGuide = 1024;       // guide entries per histogram (top 10 bits of u0)
+constexpr int kChunkMax = 32768;   // hits per chunk (per-cell counts are 16-bit)
 constexpr int kHashProbes = 16;
 constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr int kTileMax = 512;             // max hits of one packed tile (one wave)
@@ -410,14 +412,16 @@ __global__ void k_build_cum(const float* __restrict__ w, float* __restrict__ cum
 
 // guide table: g[j] = first bin with cum > j/256, so a draw u with
 // floor(256 u) = j lies in bins [g[j], g[j+1]] (g[256] := 255)
+// g[j] = first bin with cum > j / kGuide: a u0 in [j, j+1) / kGuide has its
+// bin in [g[j], g[j+1]] (the last entry's upper end is the last bin)
 __global__ void k_build_guide(const float* __restrict__ cum, uint8_t* __restrict__ guide,
                               long long n_hist)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_hist * kBins) return;
-    const long long h = i / kBins;
-    const int j = (int)(i - h * kBins);
-    const float thr = (float)j * 0x1p-8f;
+    if (i >= n_hist * kGuide) return;
+    const long long h = i / kGuide;
+    const int j = (int)(i - h * kGuide);
+    const float thr = (float)j * (1.0f / kGuide);
     const float* c = cum + h * kBins;
     int lo = 0, hi = kBins - 1;
     while (lo < hi) {
@@ -428,7 +432,6 @@ __global__ void k_build_guide(const float* __restrict__ cum, uint8_t* __restrict
     guide[i] = (uint8_t)lo;
 }
 
-// ------------------------------------------------- input validation ---
 __global__ void k_validate(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
@@ -718,9 +721,9 @@ __device__ __forceinline__ GeoLds stage_geometry(const Params& P, v4i* s_geo)
 template <typename CumT, typename GuideT>
 __device__ __forceinline__ int find_bin(CumT cum, GuideT guide, uint32_t x0, float u)
 {
-    const int j = (int)(x0 >> 24);
+    const int j = (int)(x0 >> 22);  // u0 = (x0 >> 8) 2^-24 lies in [j, j+1) / kGuide
     int lo = guide[j];
-    int hi = j < kBins - 1 ? (int)guide[j + 1] : kBins - 1;
+    int hi = j < kGuide - 1 ? (int)guide[j + 1] : kBins - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (cum[mid] > u) hi = mid;
@@ -811,7 +814,13 @@ __device__ __forceinline__ ChunkInfo load_chunk(const Params& P, int item)
 // barriers inside the item loop); the LDS below is partitioned per wave.
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kWaveSlots = 512;  // LDS hash slots of one wave's chunk accumulator
-constexpr int kListCap = 512;    // per-wave u16 list: claimed slots or tile owners
+constexpr int kListCap = 512;    // per-wave u16 tile-owner list (in the hash key array)
+static_assert(kTileMax <= kListCap, "a tile's owners must fit the owner list");
+static_assert(kListCap * 2 <= kWaveSlots * 4 && kListCap * 2 <= kBins * 8,
+              "the owner list borrows a wave's hash keys or bin sums");
+static_assert(kGuide / 16 == kWave && kBins / 4 == kWave, "one 16-byte record per lane");
+static_assert(kChunkMax < 65536, "per-cell chunk counts are 16-bit");
+static_assert(kWaveSlots == 512, "hash_bits caps the table at 2^9 slots");
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -916,27 +925,53 @@ __device__ __forceinline__ void deposit(const Params& P, long long ev, int cell,
     }
 }
 
-// add `cnt` hits of `key` to a wave's LDS hash table (linear probing); a
-// newly claimed slot is appended to the wave's slot list; when the table is
-// full the energy goes to the cell directly
-__device__ __forceinline__ void wave_hash_add(const Params& P, uint32_t* hkey, uint32_t* hcnt,
-                                              uint16_t* list, int* nlist, uint32_t key, uint32_t cnt,
-                                              long long ev, float ehit)
+// add `cnt` hits of `key` to a wave's LDS hash table (linear probing over
+// the first 2^bits slots; two 16-bit counts per word, a chunk has at most
+// kChunkMax hits); when no slot is found the energy goes to the cell directly
+__device__ __forceinline__ void wave_hash_add(const Params& P, uint32_t* hkey, uint32_t* hcnt2,
+                                              int bits, uint32_t key, uint32_t cnt, long long ev,
+                                              float ehit)
 {
-    uint32_t slot = (key * 2654435761u) >> (32 - 9);
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t slot = (key * 2654435761u) >> (32 - bits);
     for (int pr = 0; pr < kHashProbes; ++pr) {
         const uint32_t old = atomicCAS(&hkey[slot], kEmpty, key);
-        if (old == kEmpty) {
-            const int at = atomicAdd(nlist, 1);
-            list[at] = (uint16_t)slot;
-        }
         if (old == kEmpty || old == key) {
-            atomicAdd(&hcnt[slot], cnt);
+            atomicAdd(&hcnt2[slot >> 1], cnt << (16 * (slot & 1)));
             return;
         }
-        slot = (slot + 1) & (kWaveSlots - 1);
+        slot = (slot + 1) & mask;
     }
     deposit(P, ev, (int)key, (float)cnt * ehit);
+}
+
+// hash slots used for a chunk of n hits: about 2n (at most half full), 64 to
+// kWaveSlots, so that a small chunk's flush reads few words
+__device__ __forceinline__ int hash_bits(int n)
+{
+    const int b = 32 - __clz(2 * n - 1);  // ceil(log2(2n))
+    return b < 6 ? 6 : (b > 9 ? 9 : b);
+}
+
+// deposit every claimed slot among the first 2^bits of a wave's table as
+// count * Ehit and clear it (call with the whole wave after a wave_sync)
+__device__ __forceinline__ void wave_hash_flush(const Params& P, uint32_t* hkey, uint32_t* hcnt2,
+                                                int bits, long long ev, float ehit)
+{
+    for (int w = lane_id(); w < (1 << (bits - 1)); w += kWave) {
+        const uint32_t c2 = hcnt2[w];
+        if (c2 == 0) continue;
+        const uint32_t lo = c2 & 0xffffu, hi = c2 >> 16;
+        if (lo) {
+            deposit(P, ev, (int)hkey[2 * w], (float)lo * ehit);
+            hkey[2 * w] = kEmpty;
+        }
+        if (hi) {
+            deposit(P, ev, (int)hkey[2 * w + 1], (float)hi * ehit);
+            hkey[2 * w + 1] = kEmpty;
+        }
+        hcnt2[w] = 0;
+    }
 }
 
 // ----------------------------------------------------------- work queue ---
@@ -1008,20 +1043,17 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     const Params& P = *Pp;
     extern __shared__ v4i s_geo[];
     __shared__ uint32_t w_key[kWavesPerBlock][kWaveSlots];
-    __shared__ uint32_t w_cnt[kWavesPerBlock][kWaveSlots];
-    __shared__ uint16_t w_list[kWavesPerBlock][kListCap];
+    __shared__ uint32_t w_cnt2[kWavesPerBlock][kWaveSlots / 2];
     __shared__ float w_cum[kWavesPerBlock][kBins];
-    __shared__ uint32_t w_guide4[kWavesPerBlock][kBins / 4];
-    __shared__ int w_n[kWavesPerBlock];
+    __shared__ v4i w_guide16[kWavesPerBlock][kGuide / 16];
 
     const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
     uint32_t* hkey = w_key[wv];
-    uint32_t* hcnt = w_cnt[wv];
-    uint16_t* list = w_list[wv];
+    uint32_t* hcnt2 = w_cnt2[wv];
+    uint16_t* owners = reinterpret_cast<uint16_t*>(hkey);  // tiles only
     float* cum = w_cum[wv];
-    const uint8_t* guide = reinterpret_cast<const uint8_t*>(w_guide4[wv]);
-    int* nlist = &w_n[wv];
+    const uint8_t* guide = reinterpret_cast<const uint8_t*>(w_guide16[wv]);
 
     const auto ctr = G(P.ctr);
     if (ctr->error & (kErrTooManyHits | kErrChunkCap)) return;
@@ -1032,11 +1064,8 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     long long n_out = 0;
 
     const GeoLds geo = stage_geometry(P, s_geo);
-    for (int s = lane; s < kWaveSlots; s += kWave) {
-        hkey[s] = kEmpty;
-        hcnt[s] = 0;
-    }
-    if (lane == 0) *nlist = 0;
+    for (int s = lane; s < kWaveSlots; s += kWave) hkey[s] = kEmpty;
+    for (int s = lane; s < kWaveSlots / 2; s += kWave) hcnt2[s] = 0;
     __syncthreads();
 
     WaveQueue queue = make_queue(n_items);
@@ -1048,9 +1077,10 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
             const ChunkInfo ck = load_chunk(P, item);
             const long long hb = (long long)ck.H * kBins;
             reinterpret_cast<v4i*>(cum)[lane] = ((const FCS_AS_GLOBAL v4i*)(G(P.cum) + hb))[lane];
-            w_guide4[wv][lane] = ((const FCS_AS_GLOBAL uint32_t*)(G(P.guide) + hb))[lane];
+            w_guide16[wv][lane] = ((const FCS_AS_GLOBAL v4i*)(G(P.guide) + (long long)ck.H * kGuide))[lane];
             wave_sync();
             const LayerRec lrec = layer_rec(geo, ck.l);
+            const int hbits = hash_bits(ck.count);
             const long long hbase = P.want_hits ? (long long)G(P.task_hoff)[ck.t] : 0;
             for (int i = ck.first + lane; i < ck.first + ck.count; i += kWave) {
                 const HitOut h = simulate_hit(geo, lrec, cum, guide, dr, k0, k1, (uint32_t)i,
@@ -1066,37 +1096,29 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                     const bool same = pending && h.cell == lk;
                     const unsigned long long sm = __ballot(same);
                     if (lane == leader)
-                        wave_hash_add(P, hkey, hcnt, list, nlist, (uint32_t)lk,
-                                      (uint32_t)__popcll(sm), ck.ev, ck.ehit);
+                        wave_hash_add(P, hkey, hcnt2, hbits, (uint32_t)lk, (uint32_t)__popcll(sm),
+                                      ck.ev, ck.ehit);
                     pending = pending && !same;
                 }
                 if (pending)
-                    wave_hash_add(P, hkey, hcnt, list, nlist, (uint32_t)h.cell, 1u, ck.ev, ck.ehit);
+                    wave_hash_add(P, hkey, hcnt2, hbits, (uint32_t)h.cell, 1u, ck.ev, ck.ehit);
             }
             wave_sync();
-            const int n = *nlist;
-            for (int k = lane; k < n; k += kWave) {
-                const int slot = list[k];
-                deposit(P, ck.ev, (int)hkey[slot], (float)hcnt[slot] * ck.ehit);
-                hkey[slot] = kEmpty;
-                hcnt[slot] = 0;
-            }
-            wave_sync();
-            if (lane == 0) *nlist = 0;
+            wave_hash_flush(P, hkey, hcnt2, hbits, ck.ev, ck.ehit);
             wave_sync();
         } else {
             // ------------------------------------------ tile of small tasks
             int s0, h0, hcount;
-            wave_tile_owners(P, ctr, item - n_chunks, list, s0, h0, hcount);
+            wave_tile_owners(P, ctr, item - n_chunks, owners, s0, h0, hcount);
             // uniform trip count: every lane takes part in the wave sums below
             for (int kb = 0; kb < hcount; kb += kWave) {
                 const int k = kb + lane;
                 const bool valid = k < hcount;
                 const int kk = valid ? k : hcount - 1;
-                const SmallHit sh = small_hit(P, s0 + list[kk], h0 + kk);
+                const SmallHit sh = small_hit(P, s0 + owners[kk], h0 + kk);
                 const HitOut h = simulate_hit(geo, layer_rec(geo, sh.l),
                                               G(P.cum) + (long long)sh.H * kBins,
-                                              G(P.guide) + (long long)sh.H * kBins, dr, k0, k1,
+                                              G(P.guide) + (long long)sh.H * kGuide, dr, k0, k1,
                                               (uint32_t)sh.i, (uint32_t)sh.l, sh.pin, sh.evg,
                                               sh.eta_p, sh.phi_p);
                 if (valid && P.want_hits)
@@ -1116,6 +1138,9 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                 }
                 if (pending) deposit(P, sh.ev, h.cell, sh.ehit);
             }
+            wave_sync();
+            // the owner list borrowed the hash keys: empty them again
+            for (int k = lane; k < kWaveSlots; k += kWave) hkey[k] = kEmpty;
             wave_sync();
         }
     }
@@ -1326,16 +1351,15 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
     const Params& P = *Pp;
     extern __shared__ v4i s_geo[];
     __shared__ double w_bin[kWavesPerBlock][kBins];
-    __shared__ uint16_t w_list[kWavesPerBlock][kListCap];
     __shared__ float w_cum[kWavesPerBlock][kBins];
-    __shared__ uint32_t w_guide4[kWavesPerBlock][kBins / 4];
+    __shared__ v4i w_guide16[kWavesPerBlock][kGuide / 16];
 
     const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
     double* bins = w_bin[wv];
-    uint16_t* list = w_list[wv];
+    uint16_t* owners = reinterpret_cast<uint16_t*>(bins);  // tiles only
     float* cum = w_cum[wv];
-    const uint8_t* guide = reinterpret_cast<const uint8_t*>(w_guide4[wv]);
+    const uint8_t* guide = reinterpret_cast<const uint8_t*>(w_guide16[wv]);
     const auto ctr = G(P.ctr);
     if (ctr->error & (kErrTooManyHits | kErrChunkCap)) return;
     const int n_chunks = ctr->n_chunks;
@@ -1354,7 +1378,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
             const ChunkInfo ck = load_chunk(P, item);
             const long long hb = (long long)ck.H * kBins;
             reinterpret_cast<v4i*>(cum)[lane] = ((const FCS_AS_GLOBAL v4i*)(G(P.cum) + hb))[lane];
-            w_guide4[wv][lane] = ((const FCS_AS_GLOBAL uint32_t*)(G(P.guide) + hb))[lane];
+            w_guide16[wv][lane] = ((const FCS_AS_GLOBAL v4i*)(G(P.guide) + (long long)ck.H * kGuide))[lane];
             wave_sync();
             const LayerRec lrec = layer_rec(geo, ck.l);
             const auto g = G(P.grad_cells) + (long long)ck.ev * C;
@@ -1381,12 +1405,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
             wave_sync();
         } else {
             int s0, h0, hcount;
-            wave_tile_owners(P, ctr, item - n_chunks, list, s0, h0, hcount);
+            wave_tile_owners(P, ctr, item - n_chunks, owners, s0, h0, hcount);
             for (int k = lane; k < hcount; k += kWave) {
-                const SmallHit sh = small_hit(P, s0 + list[k], h0 + k);
+                const SmallHit sh = small_hit(P, s0 + owners[k], h0 + k);
                 const HitOut h = simulate_hit(geo, layer_rec(geo, sh.l),
                                               G(P.cum) + (long long)sh.H * kBins,
-                                              G(P.guide) + (long long)sh.H * kBins, dr, k0, k1,
+                                              G(P.guide) + (long long)sh.H * kGuide, dr, k0, k1,
                                               (uint32_t)sh.i, (uint32_t)sh.l, sh.pin, sh.evg,
                                               sh.eta_p, sh.phi_p);
                 if (h.cell < 0) continue;
@@ -1394,6 +1418,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
                 gadd(G(P.acc_elayer) + sh.t, gc);
                 gadd(G(P.acc_bins) + (long long)sh.H * kBins + h.bin, gc * (double)sh.ehit);
             }
+            wave_sync();
+            // the owner list borrowed the bin sums: zero them again
+            for (int b = lane; b < kBins; b += kWave) bins[b] = 0.0;
             wave_sync();
         }
     }

@@ -449,11 +449,11 @@ int fcs_load_parametrization(fcs_ctx* c, const fcs_param* p)
         (rc = upload(c, c->p_alpha, p->dirichlet_alpha, (size_t)3 * L)) ||
         (rc = upload(c, c->p_weights, p->weights, (size_t)n_hist * 256)) ||
         (rc = ensure(c, c->p_cum, (size_t)n_hist * 256 * sizeof(float))) ||
-        (rc = ensure(c, c->p_guide, (size_t)n_hist * 256)))
+        (rc = ensure(c, c->p_guide, (size_t)n_hist * fcsk::kGuide)))
         return rc;
     hipLaunchKernelGGL(fcsk::k_build_cum, dim3(grid_for(n_hist, 64)), dim3(64), 0, c->stream,
                        (const float*)c->p_weights.p, (float*)c->p_cum.p, n_hist);
-    hipLaunchKernelGGL(fcsk::k_build_guide, dim3(grid_for(n_hist * 256, 256)), dim3(256), 0,
+    hipLaunchKernelGGL(fcsk::k_build_guide, dim3(grid_for(n_hist * fcsk::kGuide, 256)), dim3(256), 0,
                        c->stream, (const float*)c->p_cum.p, (uint8_t*)c->p_guide.p, n_hist);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -486,8 +486,8 @@ int check_tuning(fcs_ctx* c, const fcs_sim_options* o, Tuning* t)
     t->big = o->big_task_hits ? o->big_task_hits : 128;
     t->tile = o->tile_hits ? o->tile_hits : 512;
     t->wg_per_cu = o->wg_per_cu ? o->wg_per_cu : 4;
-    if (t->chunk < 1 || t->chunk > (1 << 20))
-        return fail(c, FCS_E_INVALID_ARG, "chunk_hits = %d outside [1, 2^20]", t->chunk);
+    if (t->chunk < 1 || t->chunk > fcsk::kChunkMax)
+        return fail(c, FCS_E_INVALID_ARG, "chunk_hits = %d outside [1, %d]", t->chunk, fcsk::kChunkMax);
     if (t->tile < fcsk::kWave || t->tile > fcsk::kTileMax || t->tile % fcsk::kWave)
         return fail(c, FCS_E_INVALID_ARG, "tile_hits = %d must be a multiple of 64 in [64, %d]",
                     t->tile, fcsk::kTileMax);
