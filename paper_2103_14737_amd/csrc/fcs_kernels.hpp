@@ -51,6 +51,7 @@ struct Counters {
     int32_t error;        // bit set, see kErr*
     int32_t need_chunks;  // chunk entries required when over capacity
     int32_t pad;
+    long long n_blk_list; // nonzero 64-cell blocks listed by the compaction
 };
 
 enum : int32_t {
@@ -66,8 +67,9 @@ struct Params {
     // geometry
     long long n_cells;
     int32_t n_layers, n_regions;
-    int32_t n_blk;  // accumulator flag blocks (64 cells) per event
-    int32_t n_seg;  // compaction segments (64 flag blocks) per event
+    int32_t n_blk;     // flag stride per event in 64-cell blocks (a power of two)
+    int32_t blk_shift; // log2(n_blk)
+    int32_t n_seg;     // compaction segments (kSegBlocks flag blocks) per event
     const float* reg_eta_lo;
     const float* reg_eta_hi;
     const float* reg_inv_deta;
@@ -122,9 +124,10 @@ struct Params {
     int32_t* tile_first; // [n_tasks + 1]
     float* cells;        // [n_events * n_cells] accumulator
     uint8_t* flags;      // [n_events * n_blk]
-    int32_t* seg_cnt;    // [n_events * n_seg]
-    int32_t* seg_off;    // [n_events * n_seg]
-    int32_t* seg_blk;    // [n_seg_blocks]
+    long long* seg_cnt;  // [n_events * n_seg] (nonzero blocks << 32 | nonzero cells)
+    long long* seg_off;  // [n_events * n_seg] exclusive prefix of seg_cnt
+    unsigned long long* blk_list;  // [n_events * n_seg * kSegBlocks] position << 32 | (event << blk_shift | block)
+    long long* seg_blk;  // [n_seg_blocks]
     Counters* ctr;
     int32_t* queue;      // [kQueues * kQueueStride * 2]: tickets, then drained flags
     // outputs (device)
@@ -284,6 +287,26 @@ __device__ __forceinline__ int block_excl_scan1(int v, int& total)
 #pragma unroll
     for (int w = 0; w < kBlock / kWave; ++w) {
         const int s = wsum1[w];
+        if (w < wave) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return inc - v + off;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_excl_scan_t(T v, T& total)
+{
+    __shared__ T wsum_t[kBlock / kWave];
+    const int wave = threadIdx.x / kWave;
+    const T inc = wave_incl_scan(v);
+    if (lane_id() == kWave - 1) wsum_t[wave] = inc;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        const T s = wsum_t[w];
         if (w < wave) off += s;
         tot += s;
     }
@@ -1173,11 +1196,32 @@ __device__ inline long long buf_load_i64(__amdgpu_buffer_rsrc_t r, uint32_t off)
 
 // ------------------------------------------ ordered compaction (a10) ---
 // The hit kernels keep, per event and 64-cell block, the number of nonzero
-// cells (one byte per block).  A wave per segment of 256 blocks sums them;
-// after a scan over segments, a wave per segment walks its blocks in order,
-// writes the nonzero cells as (cell_id, E) at consecutive positions, resets
-// the cells and the counts.  The output is in ascending dense cell order.
-constexpr int kSegBlocks = 256;
+// cells (one byte per block).  A wave per segment of 1024 blocks (16 per
+// lane) counts its nonzero cells and nonzero blocks; a scan over segments
+// gives every nonzero block its place in a block list and the output
+// position of its first nonzero cell, in ascending (event, cell) order.  The
+// list pass writes the list and resets the counts; the emit pass takes 16
+// listed blocks per wave whatever the events' density, writes the nonzero
+// cells as (cell_id, E) and resets them.
+constexpr int kSegBlocks = 1024;
+constexpr int kEmitBatch = 16;
+static_assert(kSegBlocks == 16 * kWave, "a lane holds 16 block counts");
+
+__device__ __forceinline__ int byte_sum(uint32_t w)
+{
+    return (int)(w & 0xff) + (int)((w >> 8) & 0xff) + (int)((w >> 16) & 0xff) + (int)(w >> 24);
+}
+
+__device__ __forceinline__ int byte_nonzero(uint32_t w)
+{
+    return (int)((w & 0xff) != 0) + (int)((w & 0xff00) != 0) + (int)((w & 0xff0000) != 0) +
+           (int)((w & 0xff000000u) != 0);
+}
+
+__device__ __forceinline__ const FCS_AS_GLOBAL v4i* seg_counts(const Params& P, long long e, int seg)
+{
+    return (const FCS_AS_GLOBAL v4i*)(G(P.flags) + (e << P.blk_shift) + (long long)seg * kSegBlocks);
+}
 
 __global__ __launch_bounds__(kBlock) void k_seg_count(const Params* __restrict__ Pp)
 {
@@ -1186,9 +1230,10 @@ __global__ __launch_bounds__(kBlock) void k_seg_count(const Params* __restrict__
     if (gw >= P.n_events * P.n_seg) return;
     const long long e = gw / P.n_seg;
     const int seg = (int)(gw - e * P.n_seg);
-    const auto words = (const FCS_AS_GLOBAL uint32_t*)(G(P.flags) + e * P.n_blk + seg * kSegBlocks);
-    const uint32_t w = words[lane_id()];
-    int s = (int)(w & 0xff) + (int)((w >> 8) & 0xff) + (int)((w >> 16) & 0xff) + (int)(w >> 24);
+    const v4i w = seg_counts(P, e, seg)[lane_id()];
+    const uint32_t x = (uint32_t)w.x, y = (uint32_t)w.y, z = (uint32_t)w.z, q = (uint32_t)w.w;
+    long long s = (long long)(byte_sum(x) + byte_sum(y) + byte_sum(z) + byte_sum(q)) +
+                  ((long long)(byte_nonzero(x) + byte_nonzero(y) + byte_nonzero(z) + byte_nonzero(q)) << 32);
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
     if (lane_id() == 0) G(P.seg_cnt)[gw] = s;
@@ -1199,11 +1244,11 @@ __global__ __launch_bounds__(kBlock) void k_seg_reduce(const Params* __restrict_
     const Params& P = *Pp;
     const long long n = P.n_events * P.n_seg;
     const long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanItems;
-    int s = 0;
+    long long s = 0;
     for (int k = 0; k < kScanItems; ++k)
         if (base + k < n) s += G(P.seg_cnt)[base + k];
-    int tot;
-    (void)block_excl_scan1(s, tot);
+    long long tot;
+    (void)block_excl_scan_t<long long>(s, tot);
     if (threadIdx.x == 0) G(P.seg_blk)[blockIdx.x] = tot;
 }
 
@@ -1227,14 +1272,16 @@ __global__ __launch_bounds__(1024) void k_seg_top(const Params* __restrict__ Pp)
             if (w < tid / kWave) off += part[w];
             tot += part[w];
         }
-        if (b < nb) G(P.seg_blk)[b] = (int)(carry + off + inc - v);
+        if (b < nb) G(P.seg_blk)[b] = carry + off + inc - v;
         __syncthreads();
         if (tid == 0) carry += tot;
         __syncthreads();
     }
     if (tid == 0) {
-        G(P.ctr)->nnz_total = carry;
-        if (G(P.out_ev_off)) G(P.out_ev_off)[P.n_events] = P.out_base + carry;
+        const long long nnz = carry & 0xffffffffLL;
+        G(P.ctr)->nnz_total = nnz;
+        G(P.ctr)->n_blk_list = carry >> 32;
+        if (G(P.out_ev_off)) G(P.out_ev_off)[P.n_events] = P.out_base + nnz;
     }
 }
 
@@ -1243,101 +1290,111 @@ __global__ __launch_bounds__(kBlock) void k_seg_apply(const Params* __restrict__
     const Params& P = *Pp;
     const long long n = P.n_events * P.n_seg;
     const long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanItems;
-    int v[kScanItems];
-    int s = 0;
+    long long v[kScanItems];
+    long long s = 0;
     for (int k = 0; k < kScanItems; ++k) {
         v[k] = base + k < n ? G(P.seg_cnt)[base + k] : 0;
         s += v[k];
     }
-    int tot;
-    int run = block_excl_scan1(s, tot) + G(P.seg_blk)[blockIdx.x];
+    long long tot;
+    long long run = block_excl_scan_t<long long>(s, tot) + G(P.seg_blk)[blockIdx.x];
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) G(P.seg_off)[base + k] = run;
         run += v[k];
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_seg_write(const Params* __restrict__ Pp)
+// list pass: a wave per segment writes an entry per nonzero block (global
+// block id, output position of its first nonzero cell) and resets the counts
+__global__ __launch_bounds__(kBlock) void k_seg_list(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
     const long long gw = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (gw >= P.n_events * P.n_seg) return;
-    // Parameters used after the first store are kept in registers: the
-    // compiler cannot tell the output stores from the parameter block.
     const long long e = gw / P.n_seg;
     const int seg = (int)(gw - e * P.n_seg);
     const int lane = lane_id();
-    const long long n_cells = P.n_cells, out_cap = P.out_cap;
+    const auto w4p = const_cast<FCS_AS_GLOBAL v4i*>(seg_counts(P, e, seg));
+    const v4i w = w4p[lane];
+    const uint32_t words[4] = {(uint32_t)w.x, (uint32_t)w.y, (uint32_t)w.z, (uint32_t)w.w};
+    const int cells = byte_sum(words[0]) + byte_sum(words[1]) + byte_sum(words[2]) + byte_sum(words[3]);
+    const int blocks = byte_nonzero(words[0]) + byte_nonzero(words[1]) + byte_nonzero(words[2]) +
+                       byte_nonzero(words[3]);
+    const long long so = G(P.seg_off)[gw];
+    int pos = (int)(so & 0xffffffffLL) + wave_incl_scan(cells) - cells;
+    long long at = (so >> 32) + wave_incl_scan(blocks) - blocks;
+    if (seg == 0 && lane == 0 && G(P.out_ev_off)) G(P.out_ev_off)[e] = P.out_base + (so & 0xffffffffLL);
+    const uint32_t gb0 = ((uint32_t)e << P.blk_shift) + (uint32_t)(seg * kSegBlocks + lane * 16);
+    const auto list = G(P.blk_list);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int cnt = (int)((words[j >> 2] >> (8 * (j & 3))) & 0xffu);
+        if (cnt) {
+            list[at] = ((unsigned long long)(uint32_t)pos << 32) | (gb0 + (uint32_t)j);
+            ++at;
+            pos += cnt;
+        }
+    }
+    if (cells) w4p[lane] = v4i{0, 0, 0, 0};
+}
+
+// emit pass: persistent waves take kEmitBatch listed blocks at a time; all
+// loads of a batch are range-checked buffer loads issued before their use
+__global__ __launch_bounds__(kBlock) void k_seg_emit(const Params* __restrict__ Pp)
+{
+    const Params& P = *Pp;
+    // Parameters used after the first store are kept in registers: the
+    // compiler cannot tell the output stores from the parameter block.
+    const long long n = G(P.ctr)->n_blk_list;
+    const int shift = P.blk_shift;
+    const uint32_t bmask = (1u << shift) - 1u;
+    const long long n_cells = P.n_cells, out_cap = P.out_cap, out_base = P.out_base;
     const bool clean = P.clean_cells != 0;
     const auto out_ids = G(P.out_ids);
     const auto out_e = G(P.out_e);
-    const auto words = (FCS_AS_GLOBAL uint32_t*)(G(P.flags) + e * P.n_blk + seg * kSegBlocks);
-    const uint32_t w = words[lane];
-    // output position of this lane's first block: exclusive scan of lane sums
-    const int mine = (int)(w & 0xff) + (int)((w >> 8) & 0xff) + (int)((w >> 16) & 0xff) + (int)(w >> 24);
-    const int lane_off = wave_incl_scan(mine) - mine;
-    const long long base = P.out_base + G(P.seg_off)[gw];
-    if (seg == 0 && lane == 0 && G(P.out_ev_off)) G(P.out_ev_off)[e] = base;
-    const auto cells = G(P.cells) + e * n_cells;
+    const auto cells0 = G(P.cells);
+    const auto list = G(P.blk_list);
     // n_cells <= 2^28, so every byte offset below fits 32 bits
-    const auto cells_r = buf_rsrc((const float*)cells, (uint32_t)(n_cells * 4));
     const auto ids_r = buf_rsrc((const long long*)G(P.cell_id), (uint32_t)(n_cells * 8));
+    const int lane = lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
-    unsigned long long lanes = __ballot(w != 0);
-    uint32_t cur = 0;  // remaining block counts of the lane being walked
-    int cur_src = 0, cur_pos = 0;
-    constexpr int kBatch = 8;
-    // Walk the nonzero blocks in ascending order, kBatch at a time: the
-    // counts give each block's output position up front, so all loads of a
-    // batch are issued before any of them is used.
-    while (cur != 0 || lanes != 0) {
-        int blk[kBatch], pos[kBatch], nb = 0;
+    const long long waves = (long long)gridDim.x * kWavesPerBlock;
+    for (long long b0 = ((long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kEmitBatch;
+         b0 < n; b0 += waves * kEmitBatch) {
+        unsigned long long e64 = 0;
+        if (lane < kEmitBatch && b0 + lane < n) e64 = list[b0 + lane];
+        const int2 ent = make_int2((int)(uint32_t)e64, (int)(uint32_t)(e64 >> 32));
+        const int nb = (int)(n - b0 < kEmitBatch ? n - b0 : kEmitBatch);
+        float v[kEmitBatch];
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            blk[b] = -1;
-            pos[b] = 0;
-            if (cur == 0 && lanes != 0) {
-                cur_src = __ffsll((long long)lanes) - 1;
-                lanes &= lanes - 1;
-                cur = (uint32_t)__builtin_amdgcn_readlane((int)w, cur_src);
-                cur_pos = __builtin_amdgcn_readlane(lane_off, cur_src);
-            }
-            if (cur != 0) {
-                const int j = (__ffs((int)cur) - 1) >> 3;
-                const int cnt = (int)((cur >> (8 * j)) & 0xffu);
-                cur &= ~(0xffu << (8 * j));
-                blk[b] = seg * kSegBlocks + cur_src * 4 + j;
-                pos[b] = cur_pos;
-                cur_pos += cnt;
-                nb = b + 1;
-            }
+        for (int b = 0; b < kEmitBatch; ++b) {
+            const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane(ent.x, b);
+            const auto rs = buf_rsrc((const float*)(cells0 + (long long)(gb >> shift) * n_cells),
+                                     (uint32_t)(n_cells * 4));
+            v[b] = buf_load_f32(rs, b < nb ? ((gb & bmask) * 64u + (uint32_t)lane) * 4u : kBufNone);
         }
-        // range-checked loads: unused slots and cells past the last one read 0
-        float v[kBatch];
+        long long id[kEmitBatch];
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b)
-            v[b] = buf_load_f32(cells_r, blk[b] < 0 ? kBufNone : (uint32_t)(blk[b] * 64 + lane) * 4u);
-        // gather the ids of the nonzero cells before the first store
-        long long id[kBatch];
+        for (int b = 0; b < kEmitBatch; ++b) {
+            const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane(ent.x, b);
+            id[b] = buf_load_i64(ids_r, v[b] != 0.0f ? ((gb & bmask) * 64u + (uint32_t)lane) * 8u : kBufNone);
+        }
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b)
-            id[b] = buf_load_i64(ids_r, v[b] != 0.0f ? (uint32_t)(blk[b] * 64 + lane) * 8u : kBufNone);
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            if (b >= nb) break;
-            const long long cell = (long long)blk[b] * 64 + lane;
+        for (int b = 0; b < kEmitBatch; ++b) {
+            const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane(ent.x, b);
+            const int pos = __builtin_amdgcn_readlane(ent.y, b);
             const unsigned long long nz = __ballot(v[b] != 0.0f);
-            if (v[b] != 0.0f) {
-                const long long o = base + pos[b] + __popcll(nz & below);
+            if (b < nb && v[b] != 0.0f) {
+                const long long o = out_base + pos + __popcll(nz & below);
                 if (o < out_cap) {
                     out_ids[o] = id[b];
                     out_e[o] = v[b];
                 }
-                if (clean) cells[cell] = 0.0f;
+                if (clean)
+                    cells0[(long long)(gb >> shift) * n_cells + (gb & bmask) * 64u + (uint32_t)lane] = 0.0f;
             }
         }
     }
-    if (w) words[lane] = 0;
 }
 
 // ------------------------------------------------------ adjoint (a12) ---

@@ -72,7 +72,7 @@ struct fcs_ctx {
     // workspace
     DevBuf w_particles, w_evoff, w_override, w_task_n, w_task_ehit, w_part_ev, w_part_p,
         w_part_set, w_blk_sums, w_blk_offs, w_task_hoff, w_chunks, w_small_rec,
-        w_tile_first, w_cells, w_flags, w_seg_cnt, w_seg_off, w_seg_blk, w_queue, w_params,
+        w_tile_first, w_cells, w_flags, w_seg_cnt, w_seg_off, w_seg_blk, w_blk_list, w_queue, w_params,
         w_acc_el, w_acc_bins;
     long long cells_events = 0;  // events the accumulator holds (kept zero)
     long long flag_events = 0;
@@ -248,7 +248,7 @@ void fcs_destroy(fcs_ctx* c)
                       &c->w_task_ehit, &c->w_part_ev, &c->w_part_p, &c->w_part_set,
                       &c->w_blk_sums, &c->w_blk_offs, &c->w_task_hoff, &c->w_chunks,
                       &c->w_small_rec, &c->w_tile_first, &c->w_cells, &c->g_layers, &c->g_regions,
-                      &c->w_flags, &c->w_seg_cnt, &c->w_seg_off, &c->w_seg_blk, &c->w_queue,
+                      &c->w_flags, &c->w_seg_cnt, &c->w_seg_off, &c->w_seg_blk, &c->w_blk_list, &c->w_queue,
                       &c->w_params, &c->w_acc_el, &c->w_acc_bins, &c->o_cells, &c->o_ids,
                       &c->o_e, &c->o_evoff, &c->o_heta, &c->o_hphi, &c->o_he, &c->o_hcell,
                       &c->o_thoff, &c->o_counts, &c->o_elayer};
@@ -508,9 +508,15 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     const long long N = sh.n_particles;
     const long long nt = N * L;
     const long long E = sh.n_events;
-    // flag stride per event: 64-cell blocks rounded up to whole segments
+    // flag stride per event: the 64-cell blocks rounded up to whole segments
+    // and then to a power of two, so that (event, block) packs into 32 bits
     const int n_seg = (int)(((c->n_cells + 63) / 64 + fcsk::kSegBlocks - 1) / fcsk::kSegBlocks);
-    const int n_blk = n_seg * fcsk::kSegBlocks;
+    int blk_shift = 0;
+    while ((1 << blk_shift) < n_seg * fcsk::kSegBlocks) ++blk_shift;
+    const int n_blk = 1 << blk_shift;
+    if ((sh.n_events << blk_shift) > 0xffffffffLL)
+        return fail(c, FCS_E_INVALID_ARG, "%lld events in one batch: at most %lld for this geometry",
+                    (long long)sh.n_events, 0xffffffffLL >> blk_shift);
     const long long nsb = (nt + fcsk::kScanBlock - 1) / fcsk::kScanBlock;
     const long long nseg = E * n_seg;
     const long long nsegb = (nseg + fcsk::kScanBlock - 1) / fcsk::kScanBlock;
@@ -524,8 +530,9 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
         (rc = ensure(c, c->w_chunks, (size_t)c->chunk_cap * 16)) ||
         (rc = ensure(c, c->w_small_rec, (size_t)nt * 32)) ||
         (rc = ensure(c, c->w_tile_first, (nt + 1) * 4)) ||
-        (rc = ensure(c, c->w_seg_cnt, nseg * 4)) || (rc = ensure(c, c->w_seg_off, nseg * 4)) ||
-        (rc = ensure(c, c->w_seg_blk, nsegb * 4)))
+        (rc = ensure(c, c->w_seg_cnt, nseg * 8)) || (rc = ensure(c, c->w_seg_off, nseg * 8)) ||
+        (rc = ensure(c, c->w_seg_blk, nsegb * 8)) ||
+        (rc = ensure(c, c->w_blk_list, (size_t)nseg * fcsk::kSegBlocks * 8)))
         return rc;
     // flags and the private accumulator are kept zero between calls
     if (c->flag_events < E) {
@@ -548,6 +555,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->n_layers = L;
     P->n_regions = c->n_regions;
     P->n_blk = n_blk;
+    P->blk_shift = blk_shift;
     P->n_seg = n_seg;
     P->reg_eta_lo = (const float*)c->g_eta_lo.p;
     P->reg_eta_hi = (const float*)c->g_eta_hi.p;
@@ -606,9 +614,10 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->tile_first = (int32_t*)c->w_tile_first.p;
     P->cells = dense_out ? dense_out : (float*)c->w_cells.p;
     P->flags = (uint8_t*)c->w_flags.p;
-    P->seg_cnt = (int32_t*)c->w_seg_cnt.p;
-    P->seg_off = (int32_t*)c->w_seg_off.p;
-    P->seg_blk = (int32_t*)c->w_seg_blk.p;
+    P->seg_cnt = (long long*)c->w_seg_cnt.p;
+    P->seg_off = (long long*)c->w_seg_off.p;
+    P->seg_blk = (long long*)c->w_seg_blk.p;
+    P->blk_list = (unsigned long long*)c->w_blk_list.p;
     P->ctr = (Counters*)((char*)c->w_params.p + kCtrOffset);
     P->queue = (int32_t*)c->w_queue.p;
     if (dout) {
@@ -664,7 +673,8 @@ void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, int g
         hipLaunchKernelGGL(fcsk::k_seg_reduce, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_seg_top, dim3(1), dim3(1024), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_seg_apply, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
-        hipLaunchKernelGGL(fcsk::k_seg_write, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_seg_list, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_seg_emit, dim3(c->n_cu * 8), dim3(fcsk::kBlock), 0, s, dP);
     }
 }
 
