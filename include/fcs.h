@@ -201,6 +201,21 @@ typedef struct {
                                    particle's own layer energies            */
     void *stream;               /* hipStream_t the call orders after; NULL =
                                    the context's stream                     */
+    int64_t n_particles;        /* device inputs: number of records in
+                                   particles (checked on the device against
+                                   event_offsets[n_events]); 0 = read
+                                   event_offsets[n_events] back, one
+                                   device-to-host round trip per call       */
+    int32_t async_launch;       /* 1: enqueue the batch and return without
+                                   waiting (batched mode, device inputs and
+                                   outputs, n_particles given).  opt->stream
+                                   is made to wait for the results.  The
+                                   out->n_* fields are not known and are set
+                                   to -1; event_cell_offsets[n_events] holds
+                                   the compacted total on the device.
+                                   Errors, statistics and hit-kernel times
+                                   of async calls are collected by
+                                   fcs_synchronize.                         */
 } fcs_sim_options;
 
 /* Fill *opt with the defaults: seed 0, batched, compact output, 100 MeV per
@@ -253,7 +268,8 @@ typedef struct {
  * on (seed, event_index_base + e, the particles), never on the mode, the
  * tuning or the launch shape; cell energies are FP32 sums whose rounding
  * may vary with the order of accumulation.
- * The call returns after the results are complete and copied.
+ * The call returns after the results are complete and copied, unless
+ * opt->async_launch is set.
  * Errors: FCS_E_NOT_LOADED, FCS_E_INVALID_ARG (unknown pdg, non-finite or
  * non-positive energy, non-finite eta/phi, bad offsets, missing output
  * pointer), FCS_E_CAPACITY (cell or hit capacity too small: the required
@@ -261,6 +277,22 @@ typedef struct {
 int fcs_simulate_events(fcs_ctx *ctx, const fcs_particle *particles,
                         const int64_t *event_offsets, int64_t n_events,
                         const fcs_sim_options *opt, fcs_sim_output *out);
+
+/* Statistics of the asynchronous calls since the last fcs_synchronize. */
+typedef struct {
+    int64_t n_calls;
+    int64_t n_hits;
+    int64_t n_hits_out_of_acceptance;
+    int64_t n_cells_nonzero;
+    double kernel_ms;           /* summed hit-kernel time of profiled calls */
+} fcs_async_stats;
+
+/* Wait for every call enqueued on the context, then report the first error
+ * the asynchronous calls met (the codes of fcs_simulate_events; on
+ * FCS_E_CAPACITY the outputs of the call that overflowed are incomplete)
+ * and, when stats is not NULL, their summed statistics.  Clears both.
+ * Synchronous calls need no fcs_synchronize. */
+int fcs_synchronize(fcs_ctx *ctx, fcs_async_stats *stats);
 
 typedef struct {
     int64_t n_hits;          /* hits the batch will generate               */

@@ -54,6 +54,16 @@ struct Counters {
     long long n_blk_list; // nonzero 64-cell blocks listed by the compaction
 };
 
+// running totals of the asynchronous calls of a context (device memory)
+struct AsyncAcc {
+    long long n_calls;
+    long long hits;
+    long long hits_out;
+    long long nnz;
+    int32_t error;  // union of the calls' error bits
+    int32_t pad;
+};
+
 enum : int32_t {
     kErrPdg = 1,          // unknown particle type
     kErrParticle = 2,     // non-finite / non-positive inputs
@@ -61,6 +71,8 @@ enum : int32_t {
     kErrTooManyHits = 8,  // more than 2^31-1 hits in one batch
     kErrChunkCap = 16,    // chunk list capacity exceeded (internal retry)
     kErrOverride = 32,    // negative or non-finite layer-energy override
+    kErrCellCap = 64,     // compacted cells beyond the output capacity (async calls)
+    kErrHitCap = 128,     // hits beyond the hit-list capacity (async calls)
 };
 
 struct Params {
@@ -492,11 +504,14 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
     const int l = tid - lp * L;
     const long long gp = (long long)blockIdx.x * ppb + lp;
     const bool active = lp < ppb && gp < P.n_particles;
+    // after a failed input check (bad offsets, particles) no task gets hits:
+    // particles outside the offsets must not reach an event index
+    const bool bad = (G(P.ctr)->error & (kErrPdg | kErrParticle | kErrOffsets)) != 0;
     Particle pt = {0, 0.f, 0.f, 0.f};
     int set = -1, ev = 0;
     uint32_t pin = 0, evg = 0;
     double g = 0.0;
-    if (active) {
+    if (active && !bad) {
         pt = load_particle(P.particles, gp);
         ev = find_event(G(P.ev_off), P.n_events, P.part_base + gp);
         pin = (uint32_t)(P.part_base + gp - G(P.ev_off)[ev]);
@@ -1008,11 +1023,19 @@ struct WaveQueue {
     int n_items, per_grab, home, probe, cur, end;
 };
 
-__device__ __forceinline__ WaveQueue make_queue(int n_items)
+// workgroups of a persistent grid that the items can keep busy (at least one
+// item per wave); the others leave before staging anything
+__device__ __forceinline__ int active_workgroups(int n_items)
+{
+    const int need = (n_items + kWavesPerBlock - 1) / kWavesPerBlock;
+    return need < (int)gridDim.x ? need : (int)gridDim.x;
+}
+
+__device__ __forceinline__ WaveQueue make_queue(int n_items, int active_wg)
 {
     WaveQueue q;
     q.n_items = n_items;
-    const long long waves = (long long)gridDim.x * (blockDim.x / kWave);
+    const long long waves = (long long)active_wg * (blockDim.x / kWave);
     const long long k = n_items / (waves * 16);
     q.per_grab = (int)(k < 1 ? 1 : (k > 32 ? 32 : k));
     q.home = (int)(blockIdx.x & (kQueues - 1));
@@ -1082,6 +1105,8 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     if (ctr->error & (kErrTooManyHits | kErrChunkCap)) return;
     const int n_chunks = ctr->n_chunks;
     const int n_items = n_chunks + ctr->n_tiles;
+    const int active_wg = active_workgroups(n_items);
+    if ((int)blockIdx.x >= active_wg) return;
     const float dr = P.r_max / 32.0f;
     const uint32_t k0 = P.key0, k1 = P.key1;
     long long n_out = 0;
@@ -1091,7 +1116,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     for (int s = lane; s < kWaveSlots / 2; s += kWave) hcnt2[s] = 0;
     __syncthreads();
 
-    WaveQueue queue = make_queue(n_items);
+    WaveQueue queue = make_queue(n_items, active_wg);
     int item;
     while (next_item(P, queue, item)) {
 
@@ -1169,6 +1194,25 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     }
     const long long tot = block_sum_ll(n_out);
     if (threadIdx.x == 0 && tot) (void)gfetch_add(&G(P.ctr)->hits_out, tot);
+}
+
+// ---------------------------------------------------- asynchronous calls ---
+// one thread: fold the call's counters and capacity checks into the
+// context's running totals (stream order serializes the calls)
+__global__ void k_async_tail(const Params* __restrict__ Pp, AsyncAcc* __restrict__ acc)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const Params& P = *Pp;
+    const auto c = G(P.ctr);
+    int err = c->error;
+    if (G(P.out_ids) && c->nnz_total > P.out_cap) err |= kErrCellCap;
+    if (P.want_hits && c->hits_total > P.hit_cap) err |= kErrHitCap;
+    const auto a = G(acc);
+    a->n_calls += 1;
+    a->hits += c->hits_total;
+    a->hits_out += c->hits_out;
+    a->nnz += c->nnz_total;
+    a->error |= err;
 }
 
 // ---------------------------------------------- range-checked loads ---
@@ -1421,6 +1465,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
     if (ctr->error & (kErrTooManyHits | kErrChunkCap)) return;
     const int n_chunks = ctr->n_chunks;
     const int n_items = n_chunks + ctr->n_tiles;
+    const int active_wg = active_workgroups(n_items);
+    if ((int)blockIdx.x >= active_wg) return;
     const long long C = P.n_cells;
     const float dr = P.r_max / 32.0f;
     const uint32_t k0 = P.key0, k1 = P.key1;
@@ -1428,7 +1474,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
     for (int b = lane; b < kBins; b += kWave) bins[b] = 0.0;
     __syncthreads();
 
-    WaveQueue queue = make_queue(n_items);
+    WaveQueue queue = make_queue(n_items, active_wg);
     int item;
     while (next_item(P, queue, item)) {
         if (item < n_chunks) {

@@ -41,7 +41,14 @@ struct GraphKey {
     }
 };
 
+// device block: Params, then Counters at kCtrOffset
+constexpr size_t kCtrOffset = (sizeof(Params) + 255) & ~(size_t)255;
+constexpr size_t kBlockBytes = kCtrOffset + ((sizeof(Counters) + 255) & ~(size_t)255);
+
 }  // namespace
+
+constexpr int kRing = 16;      // pinned parameter blocks
+constexpr int kProfRing = 64;  // event pairs of profiled asynchronous calls
 
 struct fcs_ctx {
     int device = 0;
@@ -81,12 +88,22 @@ struct fcs_ctx {
     DevBuf o_cells, o_ids, o_e, o_evoff, o_heta, o_hphi, o_he, o_hcell, o_thoff, o_counts,
         o_elayer;
 
-    // pinned host block holding the Params of a launch followed by its
-    // Counters; one copy uploads both (the counters zeroed), and the counters
-    // come back into the same place at the end of the launch
-    char* h_block = nullptr;
-    Params* h_params = nullptr;
-    Counters* h_ctr = nullptr;
+    // ring of pinned host blocks, each holding the Params of a launch
+    // followed by its Counters; one copy uploads both (the counters zeroed),
+    // and a synchronous launch reads its counters back into the same block.
+    // A block is reused only after the copy that read it has completed, so
+    // asynchronous calls never overwrite parameters still to be uploaded.
+    char* h_ring = nullptr;
+    hipEvent_t ring_ev[kRing] = {};
+    bool ring_used[kRing] = {};
+    int ring_next = 0;
+    // asynchronous calls: running totals on the device, hit-kernel timing
+    // events of profiled calls not yet read
+    DevBuf w_async;
+    hipEvent_t ev_done = nullptr;
+    hipEvent_t prof_ev[kProfRing][2] = {};
+    int prof_head = 0, prof_count = 0;
+    double async_kernel_ms = 0.0;
     std::map<GraphKey, hipGraphExec_t> graphs;
 };
 
@@ -122,12 +139,32 @@ void release(fcs_ctx* c, DevBuf& b)
     b.bytes = 0;
 }
 
+// The next pinned parameter block of the ring (waits until the copy that
+// last read it has completed); ring_sent() after its upload is enqueued.
+char* ring_take(fcs_ctx* c)
+{
+    const int i = c->ring_next;
+    if (c->ring_used[i] && hipEventSynchronize(c->ring_ev[i]) != hipSuccess) return nullptr;
+    return c->h_ring + (size_t)i * kBlockBytes;
+}
+
+int ring_sent(fcs_ctx* c)
+{
+    const int i = c->ring_next;
+    HIPCHK(c, hipEventRecord(c->ring_ev[i], c->stream));
+    c->ring_used[i] = true;
+    c->ring_next = (i + 1) % kRing;
+    return FCS_OK;
+}
+
 // grow-only device buffer; contents are not preserved
 int ensure(fcs_ctx* c, DevBuf& b, size_t bytes, bool* grown = nullptr)
 {
     if (grown) *grown = false;
     if (bytes == 0) bytes = 256;
     if (b.bytes >= bytes) return FCS_OK;
+    // the old buffer may still be read by enqueued (asynchronous) work
+    if (b.p && c->stream) (void)hipStreamSynchronize(c->stream);
     release(c, b);
     size_t want = bytes + bytes / 8;
     want = (want + 255) & ~(size_t)255;
@@ -152,9 +189,6 @@ int upload(fcs_ctx* c, DevBuf& b, const T* src, size_t n)
 }
 
 unsigned grid_for(long long n, int block) { return (unsigned)((n + block - 1) / block); }
-
-constexpr size_t kCtrOffset = (sizeof(Params) + 255) & ~(size_t)255;
-constexpr size_t kBlockBytes = kCtrOffset + ((sizeof(Counters) + 255) & ~(size_t)255);
 
 void drop_graphs(fcs_ctx* c)
 {
@@ -216,14 +250,26 @@ int fcs_create(fcs_ctx** out, int device)
         hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_block, kBlockBytes) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_ring, kRing * kBlockBytes) != hipSuccess) {
         fcs_destroy(c);
         return fail(nullptr, FCS_E_HIP, "stream/event/pinned allocation failed");
     }
-    c->h_params = (Params*)c->h_block;
-    c->h_ctr = (Counters*)(c->h_block + kCtrOffset);
+    for (int i = 0; i < kRing; ++i)
+        if (hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming) != hipSuccess) {
+            fcs_destroy(c);
+            return fail(nullptr, FCS_E_HIP, "event creation failed");
+        }
+    for (int i = 0; i < kProfRing; ++i)
+        if (hipEventCreate(&c->prof_ev[i][0]) != hipSuccess ||
+            hipEventCreate(&c->prof_ev[i][1]) != hipSuccess) {
+            fcs_destroy(c);
+            return fail(nullptr, FCS_E_HIP, "event creation failed");
+        }
     if (ensure(c, c->w_params, kBlockBytes) ||
-        ensure(c, c->w_queue, 2 * fcsk::kQueues * fcsk::kQueueStride * sizeof(int32_t))) {
+        ensure(c, c->w_queue, 2 * fcsk::kQueues * fcsk::kQueueStride * sizeof(int32_t)) ||
+        ensure(c, c->w_async, sizeof(fcsk::AsyncAcc)) ||
+        hipMemset(c->w_async.p, 0, sizeof(fcsk::AsyncAcc)) != hipSuccess) {
         fcs_destroy(c);
         return fail(nullptr, FCS_E_NOMEM, "device allocation failed");
     }
@@ -251,9 +297,15 @@ void fcs_destroy(fcs_ctx* c)
                       &c->w_flags, &c->w_seg_cnt, &c->w_seg_off, &c->w_seg_blk, &c->w_blk_list, &c->w_queue,
                       &c->w_params, &c->w_acc_el, &c->w_acc_bins, &c->o_cells, &c->o_ids,
                       &c->o_e, &c->o_evoff, &c->o_heta, &c->o_hphi, &c->o_he, &c->o_hcell,
-                      &c->o_thoff, &c->o_counts, &c->o_elayer};
+                      &c->o_thoff, &c->o_counts, &c->o_elayer, &c->w_async};
     for (DevBuf* b : bufs) release(c, *b);
-    if (c->h_block) (void)hipHostFree(c->h_block);
+    if (c->h_ring) (void)hipHostFree(c->h_ring);
+    for (int i = 0; i < kRing; ++i)
+        if (c->ring_ev[i]) (void)hipEventDestroy(c->ring_ev[i]);
+    for (int i = 0; i < kProfRing; ++i)
+        for (int k = 0; k < 2; ++k)
+            if (c->prof_ev[i][k]) (void)hipEventDestroy(c->prof_ev[i][k]);
+    if (c->ev_done) (void)hipEventDestroy(c->ev_done);
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
@@ -502,7 +554,7 @@ int check_tuning(fcs_ctx* c, const fcs_sim_options* o, Tuning* t)
 // `dense_out` (device) is the caller's dense cell buffer or NULL.
 int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
             const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
-            float* dense_out, const fcs_sim_output* dout, bool want_hits, Params* P)
+            float* dense_out, const fcs_sim_output* dout, bool want_hits, bool async, Params* P)
 {
     const int L = c->n_layers;
     const long long N = sh.n_particles;
@@ -521,6 +573,12 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     const long long nseg = E * n_seg;
     const long long nsegb = (nseg + fcsk::kScanBlock - 1) / fcsk::kScanBlock;
     if (c->chunk_cap < nt + 1024) c->chunk_cap = nt + 1024;
+    // an asynchronous call cannot retry with a larger chunk list: reserve
+    // the most chunks the hit cap allows
+    if (async) {
+        const long long most = nt * ((o->nhit_cap + tu.chunk - 1) / tu.chunk) + 1024;
+        if (c->chunk_cap < most) c->chunk_cap = most;
+    }
     int rc = 0;
     if ((rc = ensure(c, c->w_task_n, nt * 4)) || (rc = ensure(c, c->w_task_ehit, nt * 4)) ||
         (rc = ensure(c, c->w_part_ev, N * 4)) || (rc = ensure(c, c->w_part_p, N * 4)) ||
@@ -711,25 +769,52 @@ int counters_error(fcs_ctx* c, const Counters& k)
     return FCS_OK;
 }
 
-// Run one launch sequence over a range of events and wait for it.
+// Run one launch sequence over a range of events and wait for it; with
+// `async`, enqueue it followed by the fold of its counters into the
+// context's running totals and return at once (*res is then zero).
 int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
               const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
               float* dense_out, const fcs_sim_output* dout, bool want_hits, bool validate,
-              bool use_graph, bool profile, Counters* res, double* kernel_ms, bool small_launch)
+              bool use_graph, bool profile, Counters* res, double* kernel_ms, bool small_launch,
+              bool async)
 {
     // a launch over few particles (per-event mode) gets a grid sized to its
     // tasks instead of filling the chip with idle persistent workgroups
     int grid = c->n_cu * tu.wg_per_cu;
     if (small_launch)
         grid = (int)std::min<long long>(grid, std::max<long long>(16, (sh.n_particles * c->n_layers + 3) / 4));
+    std::memset(res, 0, sizeof *res);
     for (int attempt = 0; attempt < 2; ++attempt) {
-        Params* P = c->h_params;
-        int rc = prepare(c, o, tu, sh, d_particles, d_evoff, d_override, dense_out, dout, want_hits, P);
+        char* blk = ring_take(c);
+        if (!blk) return fail(c, FCS_E_HIP, "hipEventSynchronize on a parameter block failed");
+        Params* P = (Params*)blk;
+        Counters* hc = (Counters*)(blk + kCtrOffset);
+        int rc = prepare(c, o, tu, sh, d_particles, d_evoff, d_override, dense_out, dout, want_hits,
+                         async, P);
         if (rc) return rc;
-        std::memset(c->h_ctr, 0, sizeof(Counters));
-        HIPCHK(c, hipMemcpyAsync(c->w_params.p, c->h_block, kBlockBytes, hipMemcpyHostToDevice, c->stream));
+        std::memset(hc, 0, sizeof(Counters));
+        HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
+        if ((rc = ring_sent(c))) return rc;
         const bool dense = dense_out != nullptr;
         GraphKey key{sh.n_particles, sh.n_events, dense ? 1 : 0, validate ? 1 : 0, grid, kAll};
+        hipEvent_t k0 = c->ev_k0, k1 = c->ev_k1;
+        if (profile && async) {
+            // a free event pair for this call; the oldest pending one is read
+            // first when all are in use
+            if (c->prof_count == kProfRing) {
+                const int old = c->prof_head;
+                float ms = 0.f;
+                HIPCHK(c, hipEventSynchronize(c->prof_ev[old][1]));
+                HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[old][0], c->prof_ev[old][1]));
+                c->async_kernel_ms += ms;
+                c->prof_head = (old + 1) % kProfRing;
+                --c->prof_count;
+            }
+            const int slot = (c->prof_head + c->prof_count) % kProfRing;
+            k0 = c->prof_ev[slot][0];
+            k1 = c->prof_ev[slot][1];
+            ++c->prof_count;
+        }
         if (use_graph && !profile) {
             if ((rc = launch_graph(c, *P, key, dense, validate, grid, kAll))) return rc;
         } else {
@@ -741,9 +826,9 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             } else {
                 enqueue_batch(c, *P, dense, validate, grid, kPre);
             }
-            if (profile) HIPCHK(c, hipEventRecord(c->ev_k0, c->stream));
+            if (profile) HIPCHK(c, hipEventRecord(k0, c->stream));
             enqueue_batch(c, *P, dense, validate, grid, kHits);
-            if (profile) HIPCHK(c, hipEventRecord(c->ev_k1, c->stream));
+            if (profile) HIPCHK(c, hipEventRecord(k1, c->stream));
             if (use_graph) {
                 key.part = kPost;
                 if ((rc = launch_graph(c, *P, key, dense, validate, grid, kPost))) return rc;
@@ -752,23 +837,30 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             }
             HIPCHK(c, hipGetLastError());
         }
-        HIPCHK(c, hipMemcpyAsync(c->h_ctr, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
+        if (async) {
+            hipLaunchKernelGGL(fcsk::k_async_tail, dim3(1), dim3(64), 0, c->stream,
+                               (const Params*)c->w_params.p, (fcsk::AsyncAcc*)c->w_async.p);
+            HIPCHK(c, hipGetLastError());
+            return FCS_OK;
+        }
+        HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
                                  hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        *res = *c->h_ctr;
+        *res = *hc;
         if ((res->error & fcsk::kErrChunkCap) && attempt == 0) {
             c->chunk_cap = (long long)res->need_chunks + 1024;
             continue;
         }
         if (profile && kernel_ms) {
             float ms = 0.f;
-            HIPCHK(c, hipEventElapsedTime(&ms, c->ev_k0, c->ev_k1));
+            HIPCHK(c, hipEventElapsedTime(&ms, k0, k1));
             *kernel_ms += ms;
         }
         return counters_error(c, *res);
     }
     return fail(c, FCS_E_HIP, "work queue sizing did not converge");
 }
+
 
 // host-side checks of host inputs
 int check_host_inputs(fcs_ctx* c, const fcs_particle* parts, const int64_t* off, int64_t n_events)
@@ -819,6 +911,7 @@ int stage_inputs(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         return fail(c, FCS_E_INVALID_ARG, "min_layer_energy_mev must be finite and > 0");
     if (o->mode != FCS_MODE_BATCHED && o->mode != FCS_MODE_PER_EVENT)
         return fail(c, FCS_E_INVALID_ARG, "unknown mode %d", o->mode);
+    if (o->n_particles < 0) return fail(c, FCS_E_INVALID_ARG, "n_particles < 0");
     if (c->dry) {
         if (!o->inputs_on_device) {
             const long long N = event_offsets[n_events];
@@ -864,6 +957,12 @@ int stage_inputs(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
                                      hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
             in->N = in->h_off[n_events];
+            if (o->n_particles > 0 && o->n_particles != in->N)
+                return fail(c, FCS_E_INVALID_ARG, "n_particles = %lld but event_offsets[n_events] = %lld",
+                            (long long)o->n_particles, in->N);
+        } else if (o->n_particles > 0) {
+            // checked against event_offsets[n_events] on the device
+            in->N = o->n_particles;
         } else {
             int64_t last = 0;
             HIPCHK(c, hipMemcpyAsync(&last, event_offsets + n_events, sizeof(int64_t),
@@ -903,6 +1002,10 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
     if ((f & FCS_OUT_COUNTS) && !out->counts) return fail(c, FCS_E_INVALID_ARG, "FCS_OUT_COUNTS needs out->counts");
     if ((f & FCS_OUT_ELAYER) && !out->elayer) return fail(c, FCS_E_INVALID_ARG, "FCS_OUT_ELAYER needs out->elayer");
     const bool per_event = o->mode == FCS_MODE_PER_EVENT;
+    const bool async = o->async_launch != 0;
+    if (async && (per_event || !o->inputs_on_device || !o->outputs_on_device || o->n_particles <= 0))
+        return fail(c, FCS_E_INVALID_ARG,
+                    "async_launch needs batched mode, device inputs and outputs and n_particles");
     Inputs in;
     if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, per_event, &in))) return rc;
     const int L = c->n_layers;
@@ -958,7 +1061,7 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
     if (!(f & FCS_OUT_ELAYER)) d.elayer = nullptr;
     const bool want_hits = (f & FCS_OUT_HITS) != 0;
 
-    HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
+    if (!async) HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
     long long hits = 0, hits_out = 0, nnz = 0, items = 0;
     double kms = 0.0;
     const bool profile = o->profile != 0;
@@ -972,7 +1075,8 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
         Shape sh{N, 0, n_events, 0, 0, 0};
         Counters k;
         rc = run_range(c, o, tu, sh, in.d_particles, in.d_evoff, in.d_override, d.cells, &d,
-                       want_hits, in.validate_on_device, o->use_graph != 0, profile, &k, &kms, false);
+                       want_hits, in.validate_on_device, o->use_graph != 0, profile, &k, &kms, false,
+                       async);
         if (rc) return rc;
         hits = k.hits_total;
         hits_out = k.hits_out;
@@ -1001,7 +1105,7 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
             const float* dov = in.d_override ? in.d_override + p0 * L : nullptr;
             Counters k;
             rc = run_range(c, o, tu, sh, dp, in.d_evoff + e, dov, de.cells, &de, want_hits,
-                           in.validate_on_device, false, profile, &k, &kms, true);
+                           in.validate_on_device, false, profile, &k, &kms, true, false);
             if (rc) return rc;
             hits += k.hits_total;
             hits_out += k.hits_out;
@@ -1012,6 +1116,17 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
             HIPCHK(c, hipMemcpyAsync(d.event_cell_offsets + n_events, &nnz, 8, hipMemcpyHostToDevice, c->stream));
         if (d.task_hit_offsets)
             HIPCHK(c, hipMemcpyAsync(d.task_hit_offsets + N * L, &hits, 8, hipMemcpyHostToDevice, c->stream));
+    }
+    if (async) {
+        // the caller's stream waits for the results; nothing is known yet
+        HIPCHK(c, hipEventRecord(c->ev_done, c->stream));
+        if (o->stream) HIPCHK(c, hipStreamWaitEvent((hipStream_t)o->stream, c->ev_done, 0));
+        out->n_hits = out->n_hits_out_of_acceptance = -1;
+        out->n_tasks = N * L;
+        out->n_cells_nonzero = out->required_cell_capacity = out->required_hit_capacity = -1;
+        out->n_work_items = -1;
+        out->device_ms = out->kernel_ms = -1.0;
+        return FCS_OK;
     }
     HIPCHK(c, hipEventRecord(c->ev_stop, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1064,6 +1179,45 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
     return FCS_OK;
 }
 
+int fcs_synchronize(fcs_ctx* c, fcs_async_stats* st)
+{
+    if (!c) return FCS_E_INVALID_ARG;
+    if (st) std::memset(st, 0, sizeof *st);
+    if (c->dry) return fail(c, FCS_E_NO_DEVICE, "context has no device");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    fcsk::AsyncAcc a;
+    HIPCHK(c, hipMemcpy(&a, c->w_async.p, sizeof a, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemset(c->w_async.p, 0, sizeof a));
+    double kms = c->async_kernel_ms;
+    for (; c->prof_count > 0; --c->prof_count) {
+        const int i = c->prof_head;
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->prof_ev[i][0], c->prof_ev[i][1]));
+        kms += ms;
+        c->prof_head = (i + 1) % kProfRing;
+    }
+    c->async_kernel_ms = 0.0;
+    if (st) {
+        st->n_calls = a.n_calls;
+        st->n_hits = a.hits;
+        st->n_hits_out_of_acceptance = a.hits_out;
+        st->n_cells_nonzero = a.nnz;
+        st->kernel_ms = kms;
+    }
+    Counters k{};
+    k.error = a.error;
+    int rc = counters_error(c, k);
+    if (rc) return rc;
+    if (a.error & fcsk::kErrCellCap)
+        return fail(c, FCS_E_CAPACITY, "an asynchronous call had more compacted cells than cell_capacity");
+    if (a.error & fcsk::kErrHitCap)
+        return fail(c, FCS_E_CAPACITY, "an asynchronous call had more hits than hit_capacity");
+    if (a.error & fcsk::kErrChunkCap)
+        return fail(c, FCS_E_HIP, "an asynchronous call overflowed the chunk list");
+    return FCS_OK;
+}
+
 int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
                     int64_t n_events, const fcs_sim_options* o, fcs_sizes* s)
 {
@@ -1076,13 +1230,18 @@ int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* ev
     if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, false, &in))) return rc;
     std::memset(s, 0, sizeof *s);
     if (in.N == 0) return FCS_OK;
-    Params* P = c->h_params;
+    char* blk = ring_take(c);
+    if (!blk) return fail(c, FCS_E_HIP, "hipEventSynchronize on a parameter block failed");
+    Params* P = (Params*)blk;
+    Counters* hc = (Counters*)(blk + kCtrOffset);
     Shape sh{in.N, 0, n_events, 0, 0, 0};
-    if ((rc = prepare(c, o, tu, sh, in.d_particles, in.d_evoff, nullptr, nullptr, nullptr, false, P)))
+    if ((rc = prepare(c, o, tu, sh, in.d_particles, in.d_evoff, nullptr, nullptr, nullptr, false,
+                      false, P)))
         return rc;
     const Params* dP = (const Params*)c->w_params.p;
-    std::memset(c->h_ctr, 0, sizeof(Counters));
-    HIPCHK(c, hipMemcpyAsync(c->w_params.p, c->h_block, kBlockBytes, hipMemcpyHostToDevice, c->stream));
+    std::memset(hc, 0, sizeof(Counters));
+    HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
+    if ((rc = ring_sent(c))) return rc;
     if (in.validate_on_device)
         hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(in.N, (long long)n_events), 256)),
                            dim3(256), 0, c->stream, dP);
@@ -1091,10 +1250,10 @@ int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* ev
     hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, c->stream, dP);
     hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, c->stream, dP);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(c->h_ctr, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
+    HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    const Counters k = *c->h_ctr;
+    const Counters k = *hc;
     if ((rc = counters_error(c, k))) return rc;
     s->n_hits = k.hits_total;
     s->n_tasks = in.N * c->n_layers;
@@ -1123,10 +1282,13 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         (rc = ensure(c, c->w_acc_bins, (size_t)c->n_hist * 256 * 8)))
         return rc;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        Params* P = c->h_params;
+        char* blk = ring_take(c);
+        if (!blk) return fail(c, FCS_E_HIP, "hipEventSynchronize on a parameter block failed");
+        Params* P = (Params*)blk;
+        Counters* hc = (Counters*)(blk + kCtrOffset);
         Shape sh{in.N, 0, n_events, 0, 0, 0};
         if ((rc = prepare(c, o, tu, sh, in.d_particles, in.d_evoff, in.d_override, nullptr, nullptr,
-                          false, P)))
+                          false, false, P)))
             return rc;
         P->grad_cells = grad_cells;
         P->acc_elayer = (double*)c->w_acc_el.p;
@@ -1135,8 +1297,9 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         P->grad_weights = grad_weights;
         const Params* dP = (const Params*)c->w_params.p;
         hipStream_t s = c->stream;
-        std::memset(c->h_ctr, 0, sizeof(Counters));
-        HIPCHK(c, hipMemcpyAsync(c->w_params.p, c->h_block, kBlockBytes, hipMemcpyHostToDevice, s));
+        std::memset(hc, 0, sizeof(Counters));
+        HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, s));
+        if ((rc = ring_sent(c))) return rc;
         if (in.validate_on_device)
             hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(in.N, (long long)n_events), 256)),
                                dim3(256), 0, s, dP);
@@ -1155,10 +1318,10 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         if (grad_weights)
             hipLaunchKernelGGL(fcsk::k_adj_weights, dim3((unsigned)c->n_hist), dim3(fcsk::kBlock), 0, s, dP);
         HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipMemcpyAsync(c->h_ctr, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
+        HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
                                  hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
-        const Counters k = *c->h_ctr;
+        const Counters k = *hc;
         if ((k.error & fcsk::kErrChunkCap) && attempt == 0) {
             c->chunk_cap = (long long)k.need_chunks + 1024;
             continue;

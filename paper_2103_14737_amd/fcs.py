@@ -40,7 +40,7 @@ _OUT_NAMES = {"dense": FCS_OUT_DENSE, "compact": FCS_OUT_COMPACT, "hits": FCS_OU
 # every symbol include/fcs.h declares
 EXPORTS = ("fcs_create", "fcs_destroy", "fcs_last_error", "fcs_get_info", "fcs_load_geometry",
            "fcs_load_parametrization", "fcs_default_options", "fcs_simulate_events",
-           "fcs_query_sizes", "fcs_backward")
+           "fcs_query_sizes", "fcs_backward", "fcs_synchronize")
 
 _vp = C.c_void_p
 
@@ -74,7 +74,8 @@ class FcsSimOptions(C.Structure):
                 ("chunk_hits", C.c_int32), ("big_task_hits", C.c_int32),
                 ("tile_hits", C.c_int32), ("wg_per_cu", C.c_int32), ("use_graph", C.c_int32),
                 ("inputs_on_device", C.c_int32), ("outputs_on_device", C.c_int32),
-                ("profile", C.c_int32), ("elayer_override", _vp), ("stream", _vp)]
+                ("profile", C.c_int32), ("elayer_override", _vp), ("stream", _vp),
+                ("n_particles", C.c_int64), ("async_launch", C.c_int32)]
 
 
 class FcsSimOutput(C.Structure):
@@ -86,6 +87,12 @@ class FcsSimOutput(C.Structure):
                 ("n_tasks", C.c_int64), ("n_cells_nonzero", C.c_int64),
                 ("required_cell_capacity", C.c_int64), ("required_hit_capacity", C.c_int64),
                 ("n_work_items", C.c_int64), ("device_ms", C.c_double),
+                ("kernel_ms", C.c_double)]
+
+
+class FcsAsyncStats(C.Structure):
+    _fields_ = [("n_calls", C.c_int64), ("n_hits", C.c_int64),
+                ("n_hits_out_of_acceptance", C.c_int64), ("n_cells_nonzero", C.c_int64),
                 ("kernel_ms", C.c_double)]
 
 
@@ -127,8 +134,9 @@ def lib():
                                       C.POINTER(FcsSizes)]
         L.fcs_backward.argtypes = [_vp, _vp, _vp, C.c_int64, C.POINTER(FcsSimOptions), _vp, _vp,
                                    _vp]
+        L.fcs_synchronize.argtypes = [_vp, C.POINTER(FcsAsyncStats)]
         for f in ("fcs_get_info", "fcs_load_geometry", "fcs_load_parametrization",
-                  "fcs_simulate_events", "fcs_query_sizes", "fcs_backward"):
+                  "fcs_simulate_events", "fcs_query_sizes", "fcs_backward", "fcs_synchronize"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -219,7 +227,7 @@ class Simulator:
     # ------------------------------------------------------------ options
     def _options(self, seed, event_index_base, mode, outputs, hit_energy_scale, nhit_cap,
                  min_layer_energy, chunk_hits, big_task_hits, tile_hits, wg_per_cu, use_graph,
-                 on_device, elayer_override, stream):
+                 on_device, elayer_override, stream, n_particles=0, async_launch=False):
         o = FcsSimOptions()
         self._L.fcs_default_options(C.byref(o))
         o.seed = seed
@@ -239,6 +247,8 @@ class Simulator:
         o.outputs_on_device = 1 if on_device else 0
         o.elayer_override = _ptr(elayer_override)
         o.stream = stream
+        o.n_particles = n_particles
+        o.async_launch = 1 if async_launch else 0
         return o
 
     def _inputs(self, particles, event_offsets, elayer_override):
@@ -264,17 +274,22 @@ class Simulator:
                         nhit_cap=20000, min_layer_energy=1e-6, chunk_hits=0, big_task_hits=0,
                         tile_hits=0, wg_per_cu=0, use_graph=True, elayer_override=None,
                         cell_capacity=None, hit_capacity=None, n_particles=None, out=None,
-                        profile=False):
+                        profile=False, async_launch=False):
         """Run fcs_simulate_events.  Returns a dict of the requested outputs
         (numpy for host inputs, torch CUDA tensors for device inputs) and the
         statistics.  Capacities default to the sizes fcs_query_sizes
-        reports.  `out` may pass preallocated device buffers (dict)."""
+        reports.  `out` may pass preallocated device buffers (dict).
+
+        async_launch (device inputs): enqueue and return at once; the outputs
+        are full-capacity buffers (event_cell_offsets[-1] holds the compacted
+        total), "stats" is None, and synchronize() reports errors and totals."""
         p, off, ov, dev, stream, n_events = self._inputs(particles, event_offsets, elayer_override)
+        N = (int(p.shape[0]) if dev else len(p)) if n_particles is None else n_particles
         o = self._options(seed, event_index_base, mode, outputs, hit_energy_scale, nhit_cap,
                           min_layer_energy, chunk_hits, big_task_hits, tile_hits, wg_per_cu,
-                          use_graph, dev, ov, stream)
+                          use_graph, dev, ov, stream, n_particles=N if dev else 0,
+                          async_launch=async_launch)
         o.profile = 1 if profile else 0
-        N = (int(p.shape[0]) if dev else len(p)) if n_particles is None else n_particles
         L = self.n_layers
         need_sizes = (("compact" in outputs and cell_capacity is None) or
                       ("hits" in outputs and hit_capacity is None))
@@ -323,6 +338,9 @@ class Simulator:
         rc = self._L.fcs_simulate_events(self._h, _ptr(p), _ptr(off), n_events, C.byref(o),
                                          C.byref(so))
         self._check(rc)
+        if async_launch:
+            res["stats"] = None
+            return res
         stats = {k: getattr(so, k) for k in ("n_hits", "n_hits_out_of_acceptance", "n_tasks",
                                              "n_cells_nonzero", "n_work_items", "device_ms",
                                              "kernel_ms")}
@@ -340,11 +358,19 @@ class Simulator:
                     hit_energy_scale=100.0, nhit_cap=20000, min_layer_energy=1e-6):
         p, off, _, dev, stream, n_events = self._inputs(particles, event_offsets, None)
         o = self._options(seed, event_index_base, "batched", (), hit_energy_scale, nhit_cap,
-                          min_layer_energy, 0, 0, 0, 0, False, dev, None, stream)
+                          min_layer_energy, 0, 0, 0, 0, False, dev, None, stream,
+                          n_particles=int(p.shape[0]) if dev else 0)
         s = FcsSizes()
         self._check(self._L.fcs_query_sizes(self._h, _ptr(p), _ptr(off), n_events, C.byref(o),
                                             C.byref(s)))
         return {"n_hits": s.n_hits, "n_tasks": s.n_tasks, "max_cells": s.max_cells}
+
+    def synchronize(self):
+        """fcs_synchronize: wait for the context's work; raise the first error
+        of the asynchronous calls; return their summed statistics."""
+        st = FcsAsyncStats()
+        self._check(self._L.fcs_synchronize(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in FcsAsyncStats._fields_}
 
     def backward(self, particles, event_offsets, seed, grad_cells, *, event_index_base=0,
                  hit_energy_scale=100.0, nhit_cap=20000, min_layer_energy=1e-6,
@@ -355,10 +381,10 @@ class Simulator:
         import torch
         p, off, ov, dev, stream, n_events = self._inputs(particles, event_offsets, elayer_override)
         assert dev and _is_torch(grad_cells) and grad_cells.is_cuda
+        N = int(p.shape[0])
         o = self._options(seed, event_index_base, "batched", (), hit_energy_scale, nhit_cap,
                           min_layer_energy, chunk_hits, big_task_hits, tile_hits, wg_per_cu,
-                          False, dev, ov, stream)
-        N = int(p.shape[0])
+                          False, dev, ov, stream, n_particles=N)
         g = grad_cells.contiguous().float()
         if grad_elayer is None:
             grad_elayer = torch.empty(N * self.n_layers, dtype=torch.float32, device=g.device)

@@ -156,3 +156,26 @@ def test_simulate_needs_loads(F, dry):
     with pytest.raises(F.FcsError) as e:
         dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10)
     assert e.value.code == F.FCS_E_NOT_LOADED
+
+
+def test_async_argument_checks(F, dry):
+    import ctypes as C
+    dry.load_geometry(W.make_geometry())
+    dry.load_parametrization(W.make_param())
+    w = W.single_particle_sweep(n_events=5)
+    # asynchronous calls need device inputs and outputs
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10, async_launch=True)
+    assert e.value.code == F.FCS_E_INVALID_ARG and "async_launch" in str(e.value)
+    st = F.FcsAsyncStats()
+    assert F.lib().fcs_synchronize(dry._h, C.byref(st)) == F.FCS_E_NO_DEVICE
+    assert st.n_calls == 0
+    o = F.FcsSimOptions()
+    F.lib().fcs_default_options(C.byref(o))
+    assert o.async_launch == 0 and o.n_particles == 0
+    o.n_particles = -3
+    so = F.FcsSimOutput()
+    p = np.ascontiguousarray(w.particles)
+    off = np.ascontiguousarray(w.event_offsets)
+    rc = F.lib().fcs_simulate_events(dry._h, p.ctypes.data, off.ctypes.data, 5, C.byref(o), C.byref(so))
+    assert rc == F.FCS_E_INVALID_ARG
