@@ -386,8 +386,9 @@ int32_t oracle_find_bin(const float *cum, float u)
 }
 
 /* cos and sin of alpha = (ia + u) * pi/4, the angle at fraction u of alpha
- * bin ia: a polynomial on the offset from the nearest multiple of pi/2
- * (offset in [0, pi/4]) and an exact quadrant swap. */
+ * bin ia: a Taylor polynomial on the offset from the nearest multiple of pi/2
+ * (offset in [0, pi/4]), evaluated in Horner form with one fused
+ * multiply-add (single rounding, fmaf) per step, and an exact quadrant swap. */
 void oracle_sincos_bin(int32_t ia, float u, float *cs, float *sn)
 {
     const float Q = (float)(0.78539816339744830962);
@@ -402,17 +403,17 @@ void oracle_sincos_bin(int32_t ia, float u, float *cs, float *sn)
     }
     float d2 = d * d;
     float sp = (float)(1.0 / 362880.0);
-    sp = sp * d2 + (float)(-1.0 / 5040.0);
-    sp = sp * d2 + (float)(1.0 / 120.0);
-    sp = sp * d2 + (float)(-1.0 / 6.0);
-    sp = sp * d2 + 1.0f;
+    sp = fmaf(sp, d2, (float)(-1.0 / 5040.0));
+    sp = fmaf(sp, d2, (float)(1.0 / 120.0));
+    sp = fmaf(sp, d2, (float)(-1.0 / 6.0));
+    sp = fmaf(sp, d2, 1.0f);
     float s0 = d * sp;
     float cp = (float)(-1.0 / 3628800.0);
-    cp = cp * d2 + (float)(1.0 / 40320.0);
-    cp = cp * d2 + (float)(-1.0 / 720.0);
-    cp = cp * d2 + (float)(1.0 / 24.0);
-    cp = cp * d2 + (float)(-0.5);
-    cp = cp * d2 + 1.0f;
+    cp = fmaf(cp, d2, (float)(1.0 / 40320.0));
+    cp = fmaf(cp, d2, (float)(-1.0 / 720.0));
+    cp = fmaf(cp, d2, (float)(1.0 / 24.0));
+    cp = fmaf(cp, d2, -0.5f);
+    cp = fmaf(cp, d2, 1.0f);
     float c0 = cp;
     float c, s;
     if ((ia & 1) == 0) { /* alpha = m pi/2 + d */
@@ -476,7 +477,9 @@ static og_hit one_hit(const og_geom *G, const float *cum, float r_max, uint64_t 
     h.bin = oracle_find_bin(cum, u0);
     int32_t ir = h.bin >> 3, ia = h.bin & 7;
     float dr = r_max / 32.0f;
-    float r = (float)ir * dr + u1 * dr;
+    /* radius uniform in the bin: lower edge ir * dr plus u1 * dr, one fused
+     * multiply-add */
+    float r = fmaf(u1, dr, (float)ir * dr);
     float c, s;
     oracle_sincos_bin(ia, u2, &c, &s);
     float inv_r = G->layer_inv_r[layer];

@@ -790,7 +790,7 @@ __device__ __forceinline__ HitOut simulate_hit(const GeoLds& g, const LayerRec& 
     HitOut h;
     h.bin = find_bin(cum, guide, x.x, u0);
     const int ir = h.bin >> 3, ia = h.bin & 7;
-    const float r = (float)ir * dr + u1 * dr;
+    const float r = __builtin_fmaf(u1, dr, (float)ir * dr);  // lower edge + u1 * dr, one rounding
     float c, s;
     sincos_bin(ia, u2, c, s);
     const float deta = (r * c) * inv_r;

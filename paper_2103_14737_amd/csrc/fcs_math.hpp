@@ -246,18 +246,19 @@ __device__ __forceinline__ void sincos_bin(int ia, float u, float& cs, float& sn
     const float d = even ? u * quarter_pi : (1.0f - u) * quarter_pi;
     const int m = even ? (ia >> 1) : ((ia + 1) >> 1);
     const float d2 = d * d;
+    // Horner steps as single-rounding fused multiply-adds (v_fma_f32)
     float sp = (float)(1.0 / 362880.0);
-    sp = sp * d2 + (float)(-1.0 / 5040.0);
-    sp = sp * d2 + (float)(1.0 / 120.0);
-    sp = sp * d2 + (float)(-1.0 / 6.0);
-    sp = sp * d2 + 1.0f;
+    sp = __builtin_fmaf(sp, d2, (float)(-1.0 / 5040.0));
+    sp = __builtin_fmaf(sp, d2, (float)(1.0 / 120.0));
+    sp = __builtin_fmaf(sp, d2, (float)(-1.0 / 6.0));
+    sp = __builtin_fmaf(sp, d2, 1.0f);
     const float s0 = d * sp;
     float cp = (float)(-1.0 / 3628800.0);
-    cp = cp * d2 + (float)(1.0 / 40320.0);
-    cp = cp * d2 + (float)(-1.0 / 720.0);
-    cp = cp * d2 + (float)(1.0 / 24.0);
-    cp = cp * d2 + (float)(-0.5);
-    cp = cp * d2 + 1.0f;
+    cp = __builtin_fmaf(cp, d2, (float)(1.0 / 40320.0));
+    cp = __builtin_fmaf(cp, d2, (float)(-1.0 / 720.0));
+    cp = __builtin_fmaf(cp, d2, (float)(1.0 / 24.0));
+    cp = __builtin_fmaf(cp, d2, -0.5f);
+    cp = __builtin_fmaf(cp, d2, 1.0f);
     const float c0 = cp;
     // quadrant table: even bins  m=0:(c,s) 1:(-s,c) 2:(-c,-s) 3:(s,-c)
     //                 odd bins   m=1:(s,c) 2:(-c,s) 3:(-s,-c) 4:(c,-s)
