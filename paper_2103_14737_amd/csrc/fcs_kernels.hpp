@@ -971,7 +971,11 @@ __device__ __forceinline__ void wave_hash_add(const Params& P, uint32_t* hkey, u
                                               float ehit)
 {
     const uint32_t mask = (1u << bits) - 1u;
-    uint32_t slot = (key * 2654435761u) >> (32 - bits);
+    // multiplicative hash on the key's low 24 bits with the full-rate 24-bit
+    // multiplier (v_mul_u32_u24; a 32-bit v_mul_lo_u32 is quarter rate).
+    // __umul24 returns a signed int: the product is taken as unsigned before
+    // the shift, so the slot stays in [0, 2^bits).
+    uint32_t slot = (uint32_t)__umul24(key, 0x9E3779u) >> (32 - bits);
     for (int pr = 0; pr < kHashProbes; ++pr) {
         const uint32_t old = atomicCAS(&hkey[slot], kEmpty, key);
         if (old == kEmpty || old == key) {
@@ -1079,9 +1083,9 @@ __device__ __forceinline__ bool next_item(const Params& P, WaveQueue& q, int& it
 // Work items, pulled by each wave from a ticket counter: [0, n_chunks)
 // chunks of large (particle, layer) tasks, then tiles of packed small tasks.
 // A chunk's histogram and guide are staged in the wave's LDS; its hits are
-// counted per cell in the wave's LDS hash table (lanes that share the cell of
-// a leading lane are counted together first, twice per step) and flushed once
-// as count * Ehit, one rounding per cell and chunk.  Tile hits that share an
+// counted per cell in the wave's LDS hash table (the lanes that share the cell
+// of a leading lane are counted together first, once per step) and flushed
+// once as count * Ehit, one rounding per cell and chunk.  Tile hits that share an
 // (event, cell) with a leading lane are summed across the wave first; each
 // remaining sum goes to the event's cell with one device atomic.
 __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
@@ -1136,9 +1140,10 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                 if (P.want_hits) write_hit(P, hbase + i, h, ck.ehit);
                 n_out += h.cell < 0 ? 1 : 0;
                 bool pending = h.cell >= 0;
-                for (int round = 0; round < 2; ++round) {
-                    const unsigned long long act = __ballot(pending);
-                    if (!act) break;
+                // the lanes in the first pending lane's cell (often the
+                // shower core) are counted with one insert
+                const unsigned long long act = __ballot(pending);
+                if (act) {
                     const int leader = __ffsll((long long)act) - 1;
                     const int lk = __builtin_amdgcn_readlane(h.cell, leader);
                     const bool same = pending && h.cell == lk;
