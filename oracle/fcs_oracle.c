@@ -144,7 +144,10 @@ static const double SQRT_HALF = 0.70710678118654752440;
 static const double TWO_PI = 6.28318530717958647692;
 static const double HALF_LOG_2PI = 0.91893853320467274178;
 
-/* natural log for finite x > 0 (normal numbers): x = m 2^e, m in
+/* Each Horner step of the series in oracle_log, oracle_exp and
+ * oracle_cos_turns is one fused multiply-add (C fma: a single rounding).
+ *
+ * natural log for finite x > 0 (normal numbers): x = m 2^e, m in
  * [sqrt(1/2), sqrt(2)), log m = 2 atanh(s), s = (m-1)/(m+1), series to s^21 */
 double oracle_log(double x)
 {
@@ -161,16 +164,16 @@ double oracle_log(double x)
     double s = (m - 1.0) / (m + 1.0);
     double s2 = s * s;
     double p = 1.0 / 21.0;
-    p = p * s2 + 1.0 / 19.0;
-    p = p * s2 + 1.0 / 17.0;
-    p = p * s2 + 1.0 / 15.0;
-    p = p * s2 + 1.0 / 13.0;
-    p = p * s2 + 1.0 / 11.0;
-    p = p * s2 + 1.0 / 9.0;
-    p = p * s2 + 1.0 / 7.0;
-    p = p * s2 + 1.0 / 5.0;
-    p = p * s2 + 1.0 / 3.0;
-    p = p * s2 + 1.0;
+    p = fma(p, s2, 1.0 / 19.0);
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    p = fma(p, s2, 1.0);
     double lm = (2.0 * s) * p;
     double k = (double)e;
     return k * LN2_HI + (k * LN2_LO + lm);
@@ -184,19 +187,19 @@ double oracle_exp(double x)
     double kd = floor(x * INV_LN2 + 0.5);
     double r = (x - kd * LN2_HI) - kd * LN2_LO;
     double p = 1.0 / 6227020800.0;       /* 1/13! */
-    p = p * r + 1.0 / 479001600.0;       /* 1/12! */
-    p = p * r + 1.0 / 39916800.0;        /* 1/11! */
-    p = p * r + 1.0 / 3628800.0;         /* 1/10! */
-    p = p * r + 1.0 / 362880.0;          /* 1/9!  */
-    p = p * r + 1.0 / 40320.0;           /* 1/8!  */
-    p = p * r + 1.0 / 5040.0;            /* 1/7!  */
-    p = p * r + 1.0 / 720.0;             /* 1/6!  */
-    p = p * r + 1.0 / 120.0;             /* 1/5!  */
-    p = p * r + 1.0 / 24.0;              /* 1/4!  */
-    p = p * r + 1.0 / 6.0;               /* 1/3!  */
-    p = p * r + 0.5;                     /* 1/2!  */
-    p = p * r + 1.0;
-    p = p * r + 1.0;
+    p = fma(p, r, 1.0 / 479001600.0);  /* 1/12! */
+    p = fma(p, r, 1.0 / 39916800.0);  /* 1/11! */
+    p = fma(p, r, 1.0 / 3628800.0);  /* 1/10! */
+    p = fma(p, r, 1.0 / 362880.0);  /* 1/9! */
+    p = fma(p, r, 1.0 / 40320.0);  /* 1/8! */
+    p = fma(p, r, 1.0 / 5040.0);  /* 1/7! */
+    p = fma(p, r, 1.0 / 720.0);  /* 1/6! */
+    p = fma(p, r, 1.0 / 120.0);  /* 1/5! */
+    p = fma(p, r, 1.0 / 24.0);  /* 1/4! */
+    p = fma(p, r, 1.0 / 6.0);  /* 1/3! */
+    p = fma(p, r, 0.5);  /* 1/2! */
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
     int k = (int)kd;
     double scale;
     if (k < -1000) {
@@ -220,25 +223,25 @@ double oracle_cos_turns(double u)
     int qi = ((int)q) & 3;
     if (qi == 0 || qi == 2) {
         double c = 1.0 / 20922789888000.0;        /* 1/16! */
-        c = c * t2 - 1.0 / 87178291200.0;          /* 1/14! */
-        c = c * t2 + 1.0 / 479001600.0;            /* 1/12! */
-        c = c * t2 - 1.0 / 3628800.0;              /* 1/10! */
-        c = c * t2 + 1.0 / 40320.0;                /* 1/8!  */
-        c = c * t2 - 1.0 / 720.0;                  /* 1/6!  */
-        c = c * t2 + 1.0 / 24.0;                   /* 1/4!  */
-        c = c * t2 - 0.5;                          /* 1/2!  */
-        c = c * t2 + 1.0;
+        c = fma(c, t2, -(1.0 / 87178291200.0));  /* 1/14! */
+        c = fma(c, t2, 1.0 / 479001600.0);  /* 1/12! */
+        c = fma(c, t2, -(1.0 / 3628800.0));  /* 1/10! */
+        c = fma(c, t2, 1.0 / 40320.0);  /* 1/8! */
+        c = fma(c, t2, -(1.0 / 720.0));  /* 1/6! */
+        c = fma(c, t2, 1.0 / 24.0);  /* 1/4! */
+        c = fma(c, t2, -(0.5));  /* 1/2! */
+        c = fma(c, t2, 1.0);
         return qi == 0 ? c : -c;
     }
     double s = 1.0 / 355687428096000.0;            /* 1/17! */
-    s = s * t2 - 1.0 / 1307674368000.0;            /* 1/15! */
-    s = s * t2 + 1.0 / 6227020800.0;               /* 1/13! */
-    s = s * t2 - 1.0 / 39916800.0;                 /* 1/11! */
-    s = s * t2 + 1.0 / 362880.0;                   /* 1/9!  */
-    s = s * t2 - 1.0 / 5040.0;                     /* 1/7!  */
-    s = s * t2 + 1.0 / 120.0;                      /* 1/5!  */
-    s = s * t2 - 1.0 / 6.0;                        /* 1/3!  */
-    s = s * t2 + 1.0;
+    s = fma(s, t2, -(1.0 / 1307674368000.0));  /* 1/15! */
+    s = fma(s, t2, 1.0 / 6227020800.0);  /* 1/13! */
+    s = fma(s, t2, -(1.0 / 39916800.0));  /* 1/11! */
+    s = fma(s, t2, 1.0 / 362880.0);  /* 1/9! */
+    s = fma(s, t2, -(1.0 / 5040.0));  /* 1/7! */
+    s = fma(s, t2, 1.0 / 120.0);  /* 1/5! */
+    s = fma(s, t2, -(1.0 / 6.0));  /* 1/3! */
+    s = fma(s, t2, 1.0);
     s = t * s;
     return qi == 1 ? -s : s;
 }

@@ -584,63 +584,79 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const Params* __restrict
     if (threadIdx.x == 0) store_i4(reinterpret_cast<int4*>(P.blk_sums), blockIdx.x, tot);
 }
 
-// one block: exclusive scan of the block sums; totals into the counters
+// one block: exclusive scan of the block sums (hits, chunks, small hits,
+// small tasks); totals into the counters.  A thread owns `per` consecutive
+// block sums, so the whole scan takes one pass with two barriers.  Hits are
+// summed in 64 bits (more than 2^31 - 1 hits in a batch is an error, found
+// here); the other components are bounded by the task count.
 __global__ __launch_bounds__(1024) void k_scan_top(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
-    __shared__ long long carry_s[4];
-    __shared__ long long part_s[1024 / kWave][4];
-    const int tid = threadIdx.x;
-    if (tid < 4) carry_s[tid] = 0;
-    __syncthreads();
+    constexpr int kT = 1024, kW = kT / kWave;
+    __shared__ long long w_hits[kW];
+    __shared__ int4 w_rest[kW];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const int nb = P.n_scan_blocks;
+    const int per = (nb + kT - 1) / kT;
+    const int b0 = tid * per;
     const int4* in = reinterpret_cast<const int4*>(P.blk_sums);
     int4* out = reinterpret_cast<int4*>(P.blk_offs);
-    for (int b0 = 0; b0 < nb; b0 += 1024) {
-        const int b = b0 + tid;
-        int4 v = make_int4(0, 0, 0, 0);
-        if (b < nb) v = load_i4(in, b);
-        long long x[4] = {v.x, v.y, v.z, v.w};
-        long long inc[4];
-        for (int c = 0; c < 4; ++c) inc[c] = wave_incl_scan<long long>(x[c]);
-        const int wave = tid / kWave;
-        if (lane_id() == kWave - 1)
-            for (int c = 0; c < 4; ++c) part_s[wave][c] = inc[c];
-        __syncthreads();
-        long long off[4] = {0, 0, 0, 0}, tot[4] = {0, 0, 0, 0};
-        for (int w = 0; w < 1024 / kWave; ++w)
-            for (int c = 0; c < 4; ++c) {
-                if (w < wave) off[c] += part_s[w][c];
-                tot[c] += part_s[w][c];
-            }
+    long long h = 0;
+    int c = 0, sh = 0, st = 0;
+    for (int k = 0; k < per; ++k) {
+        const int b = b0 + k;
         if (b < nb) {
-            int4 o;
-            o.x = (int)(carry_s[0] + off[0] + inc[0] - x[0]);
-            o.y = (int)(carry_s[1] + off[1] + inc[1] - x[1]);
-            o.z = (int)(carry_s[2] + off[2] + inc[2] - x[2]);
-            o.w = (int)(carry_s[3] + off[3] + inc[3] - x[3]);
-            store_i4(out, b, o);
+            const int4 v = load_i4(in, b);
+            h += v.x;
+            c += v.y;
+            sh += v.z;
+            st += v.w;
         }
-        __syncthreads();
-        if (tid < 4) carry_s[tid] += tot[tid];
-        __syncthreads();
+    }
+    const long long hi = wave_incl_scan<long long>(h);
+    const int4 ri = wave_incl_scan4(make_int4(0, c, sh, st));
+    if (lane == kWave - 1) {
+        w_hits[wave] = hi;
+        w_rest[wave] = ri;
+    }
+    __syncthreads();
+    long long ho = hi - h, htot = 0;
+    int4 ro = make_int4(0, ri.y - c, ri.z - sh, ri.w - st), rtot = make_int4(0, 0, 0, 0);
+    for (int w = 0; w < kW; ++w) {
+        const long long wh = w_hits[w];
+        const int4 wr = w_rest[w];
+        if (w < wave) {
+            ho += wh;
+            ro = add4(ro, wr);
+        }
+        htot += wh;
+        rtot = add4(rtot, wr);
+    }
+    for (int k = 0; k < per; ++k) {
+        const int b = b0 + k;
+        if (b < nb) {
+            const int4 v = load_i4(in, b);
+            store_i4(out, b, make_int4((int)ho, ro.y, ro.z, ro.w));
+            ho += v.x;
+            ro = add4(ro, v);
+        }
     }
     if (tid < 2 * kQueues) G(P.queue)[tid * kQueueStride] = 0;
     if (tid == 0) {
-        auto c = G(P.ctr);
-        c->hits_total = carry_s[0];
+        auto cc = G(P.ctr);
+        cc->hits_total = htot;
         int err = 0;
-        if (carry_s[0] > 2147483647LL) err |= kErrTooManyHits;
-        if (carry_s[1] > P.chunk_cap) {
+        if (htot > 2147483647LL) err |= kErrTooManyHits;
+        if (rtot.y > P.chunk_cap) {
             err |= kErrChunkCap;
-            c->need_chunks = (int)(carry_s[1] < 2147483647LL ? carry_s[1] : 2147483647LL);
+            cc->need_chunks = rtot.y;
         }
-        c->n_chunks = err ? 0 : (int)carry_s[1];
-        c->n_small_hits = err ? 0 : (int)carry_s[2];
-        c->n_small_tasks = err ? 0 : (int)carry_s[3];
-        c->n_tiles = err ? 0 : (int)((carry_s[2] + P.tile_hits - 1) / P.tile_hits);
-        if (err) gor(&c->error, err);
-        if (G(P.out_task_hoff) && !err) G(P.out_task_hoff)[P.n_tasks] = P.hit_base + carry_s[0];
+        cc->n_chunks = err ? 0 : rtot.y;
+        cc->n_small_hits = err ? 0 : rtot.z;
+        cc->n_small_tasks = err ? 0 : rtot.w;
+        cc->n_tiles = err ? 0 : (int)(((long long)rtot.z + P.tile_hits - 1) / P.tile_hits);
+        if (err) gor(&cc->error, err);
+        if (G(P.out_task_hoff) && !err) G(P.out_task_hoff)[P.n_tasks] = P.hit_base + htot;
     }
 }
 
@@ -649,17 +665,24 @@ __global__ __launch_bounds__(kBlock) void k_scan_write(const Params* __restrict_
     const Params& P = *Pp;
     if (G(P.ctr)->error & (kErrTooManyHits | kErrChunkCap)) return;
     const long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanItems;
+    // counts and hit energies of the thread's tasks are loaded up front; the
+    // per-particle data once per particle (consecutive tasks share it)
     int nv[kScanItems];
+    float ev_[kScanItems];
     int4 s = make_int4(0, 0, 0, 0);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const long long t = base + k;
         nv[k] = t < P.n_tasks ? G(P.task_n)[t] : 0;
+        ev_[k] = t < P.n_tasks ? G(P.task_ehit)[t] : 0.0f;
         s = add4(s, task_terms(P, nv[k]));
     }
     int4 tot;
     int4 run = add4(block_excl_scan4(s, tot), load_i4(reinterpret_cast<const int4*>(P.blk_offs), blockIdx.x));
     const int L = P.n_layers;
+    long long cur_gp = -1;
+    int4 rec1 = make_int4(0, 0, 0, 0);
+    int set_l0 = 0;
     for (int k = 0; k < kScanItems; ++k) {
         const long long t = base + k;
         if (t >= P.n_tasks) break;
@@ -678,14 +701,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_write(const Params* __restrict_
             // two 16-byte records per small task: (first small hit, task key,
             // Ehit bits, histogram) and (eta_p, phi_p, global event, particle
             // in event)
-            const Particle pt = load_particle(P.particles, gp);
-            const int H = G(P.part_set)[gp] * L + (key & 63);
+            if (gp != cur_gp) {
+                cur_gp = gp;
+                const Particle pt = load_particle(P.particles, gp);
+                const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)G(P.part_ev)[gp]);
+                rec1 = make_int4(__float_as_int(pt.eta), __float_as_int(pt.phi), (int)evg,
+                                 (int)G(P.part_p)[gp]);
+                set_l0 = G(P.part_set)[gp] * L;
+            }
             store_i4(P.small_rec, 2LL * run.w,
-                     make_int4(run.z, key, __float_as_int(G(P.task_ehit)[t]), H));
-            const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)G(P.part_ev)[gp]);
-            store_i4(P.small_rec, 2LL * run.w + 1,
-                     make_int4(__float_as_int(pt.eta), __float_as_int(pt.phi), (int)evg,
-                               (int)G(P.part_p)[gp]));
+                     make_int4(run.z, key, __float_as_int(ev_[k]), set_l0 + (key & 63)));
+            store_i4(P.small_rec, 2LL * run.w + 1, rec1);
             const int T = P.tile_hits;
             const int q = (run.z + T - 1) / T;
             if ((long long)q * T < (long long)run.z + n) G(P.tile_first)[q] = run.w;

@@ -58,6 +58,9 @@ constexpr double kLn2Hi = 6.93147180369123816490e-01;  // 32 trailing zero bits
 constexpr double kLn2Lo = 1.90821492927058770002e-10;
 constexpr double kInvLn2 = 1.44269504088896338700e+00;
 
+// The Horner steps of the series below are single-rounding fused
+// multiply-adds (v_fma_f64).
+//
 // log for finite normal x > 0: x = m 2^e with m in [sqrt(1/2), sqrt(2)),
 // log m = 2 atanh(s) with s = (m-1)/(m+1), odd series to s^21
 __device__ __noinline__ double dlog(double x)
@@ -72,16 +75,16 @@ __device__ __noinline__ double dlog(double x)
     const double s = (m - 1.0) / (m + 1.0);
     const double z = s * s;
     double q = 1.0 / 21.0;
-    q = q * z + 1.0 / 19.0;
-    q = q * z + 1.0 / 17.0;
-    q = q * z + 1.0 / 15.0;
-    q = q * z + 1.0 / 13.0;
-    q = q * z + 1.0 / 11.0;
-    q = q * z + 1.0 / 9.0;
-    q = q * z + 1.0 / 7.0;
-    q = q * z + 1.0 / 5.0;
-    q = q * z + 1.0 / 3.0;
-    q = q * z + 1.0;
+    q = __builtin_fma(q, z, 1.0 / 19.0);
+    q = __builtin_fma(q, z, 1.0 / 17.0);
+    q = __builtin_fma(q, z, 1.0 / 15.0);
+    q = __builtin_fma(q, z, 1.0 / 13.0);
+    q = __builtin_fma(q, z, 1.0 / 11.0);
+    q = __builtin_fma(q, z, 1.0 / 9.0);
+    q = __builtin_fma(q, z, 1.0 / 7.0);
+    q = __builtin_fma(q, z, 1.0 / 5.0);
+    q = __builtin_fma(q, z, 1.0 / 3.0);
+    q = __builtin_fma(q, z, 1.0);
     const double ed = (double)e;
     return ed * kLn2Hi + (ed * kLn2Lo + (2.0 * s) * q);
 }
@@ -94,19 +97,19 @@ __device__ __noinline__ double dexp(double x)
     const double k = floor(x * kInvLn2 + 0.5);
     const double r = (x - k * kLn2Hi) - k * kLn2Lo;
     double q = 1.0 / 6227020800.0;
-    q = q * r + 1.0 / 479001600.0;
-    q = q * r + 1.0 / 39916800.0;
-    q = q * r + 1.0 / 3628800.0;
-    q = q * r + 1.0 / 362880.0;
-    q = q * r + 1.0 / 40320.0;
-    q = q * r + 1.0 / 5040.0;
-    q = q * r + 1.0 / 720.0;
-    q = q * r + 1.0 / 120.0;
-    q = q * r + 1.0 / 24.0;
-    q = q * r + 1.0 / 6.0;
-    q = q * r + 0.5;
-    q = q * r + 1.0;
-    q = q * r + 1.0;
+    q = __builtin_fma(q, r, 1.0 / 479001600.0);
+    q = __builtin_fma(q, r, 1.0 / 39916800.0);
+    q = __builtin_fma(q, r, 1.0 / 3628800.0);
+    q = __builtin_fma(q, r, 1.0 / 362880.0);
+    q = __builtin_fma(q, r, 1.0 / 40320.0);
+    q = __builtin_fma(q, r, 1.0 / 5040.0);
+    q = __builtin_fma(q, r, 1.0 / 720.0);
+    q = __builtin_fma(q, r, 1.0 / 120.0);
+    q = __builtin_fma(q, r, 1.0 / 24.0);
+    q = __builtin_fma(q, r, 1.0 / 6.0);
+    q = __builtin_fma(q, r, 0.5);
+    q = __builtin_fma(q, r, 1.0);
+    q = __builtin_fma(q, r, 1.0);
     const int ki = (int)k;
     if (ki < -1000) {
         const double sc = __longlong_as_double((long long)(ki + 1000 + 1023) << 52);
@@ -126,25 +129,25 @@ __device__ __noinline__ double dcos_turns(double u)
     const int quad = ((int)qt) & 3;
     if ((quad & 1) == 0) {
         double c = 1.0 / 20922789888000.0;
-        c = c * z - 1.0 / 87178291200.0;
-        c = c * z + 1.0 / 479001600.0;
-        c = c * z - 1.0 / 3628800.0;
-        c = c * z + 1.0 / 40320.0;
-        c = c * z - 1.0 / 720.0;
-        c = c * z + 1.0 / 24.0;
-        c = c * z - 0.5;
-        c = c * z + 1.0;
+        c = __builtin_fma(c, z, -(1.0 / 87178291200.0));
+        c = __builtin_fma(c, z, 1.0 / 479001600.0);
+        c = __builtin_fma(c, z, -(1.0 / 3628800.0));
+        c = __builtin_fma(c, z, 1.0 / 40320.0);
+        c = __builtin_fma(c, z, -(1.0 / 720.0));
+        c = __builtin_fma(c, z, 1.0 / 24.0);
+        c = __builtin_fma(c, z, -(0.5));
+        c = __builtin_fma(c, z, 1.0);
         return quad == 0 ? c : -c;
     }
     double s = 1.0 / 355687428096000.0;
-    s = s * z - 1.0 / 1307674368000.0;
-    s = s * z + 1.0 / 6227020800.0;
-    s = s * z - 1.0 / 39916800.0;
-    s = s * z + 1.0 / 362880.0;
-    s = s * z - 1.0 / 5040.0;
-    s = s * z + 1.0 / 120.0;
-    s = s * z - 1.0 / 6.0;
-    s = s * z + 1.0;
+    s = __builtin_fma(s, z, -(1.0 / 1307674368000.0));
+    s = __builtin_fma(s, z, 1.0 / 6227020800.0);
+    s = __builtin_fma(s, z, -(1.0 / 39916800.0));
+    s = __builtin_fma(s, z, 1.0 / 362880.0);
+    s = __builtin_fma(s, z, -(1.0 / 5040.0));
+    s = __builtin_fma(s, z, 1.0 / 120.0);
+    s = __builtin_fma(s, z, -(1.0 / 6.0));
+    s = __builtin_fma(s, z, 1.0);
     s = t * s;
     return quad == 1 ? -s : s;
 }
