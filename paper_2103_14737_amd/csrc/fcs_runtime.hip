@@ -732,7 +732,8 @@ void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, int g
         hipLaunchKernelGGL(fcsk::k_seg_top, dim3(1), dim3(1024), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_seg_apply, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_seg_list, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
-        hipLaunchKernelGGL(fcsk::k_seg_emit, dim3(c->n_cu * 8), dim3(fcsk::kBlock), 0, s, dP);
+        // the emit pass is latency bound: 16 persistent workgroups per CU
+        hipLaunchKernelGGL(fcsk::k_seg_emit, dim3(c->n_cu * 16), dim3(fcsk::kBlock), 0, s, dP);
     }
 }
 
