@@ -3,15 +3,16 @@
 // Pipeline of one batch (all launches read one device-resident Params block,
 // so the sequence can be captured once in a hipGraph and replayed):
 //   k_setup        per (particle, layer): parametrization set, Dirichlet layer
-//                  energy, Poisson hit count, Ehit           (Listing 1)
-//   k_scan_reduce / k_scan_top / k_scan_write
+//                  energy, Poisson hit count, Ehit (Listing 1); per-block
+//                  sums for the task scan
+//   k_scan_top / k_scan_write
 //                  scans of the task hit counts -> work queue: chunks of
 //                  large tasks, packed tiles of small tasks
 //   k_hits         persistent: pulls work items from a ticket counter; per
 //                  hit Philox draw, inverse-CDF bin, placement, cell lookup,
 //                  deposit (sim_a of the CUDA Implementation section)
-//   k_seg_count / scan / k_seg_write
-//                  ordered gather of the hit cells as (cell_id, E) and
+//   k_seg_count / k_seg_reduce / k_seg_top / k_seg_apply / k_seg_list /
+//   k_seg_emit     ordered gather of the hit cells as (cell_id, E) and
 //                  sparse reset of the accumulator (sim_ct and clean)
 #pragma once
 
@@ -26,9 +27,9 @@ constexpr int kGuide = 1024;       // guide entries per histogram (top 10 bits o
 constexpr int kChunkMax = 32768;   // hits per chunk (per-cell counts are 16-bit)
 constexpr int kHashProbes = 16;
 constexpr uint32_t kEmpty = 0xffffffffu;
-constexpr int kTileMax = 512;             // max hits of one packed tile (one wave)
-constexpr int kScanItems = 8;             // items per thread in scans
+constexpr int kScanItems = 8;             // items per thread in the segment scans
 constexpr int kScanBlock = kBlock * kScanItems;
+constexpr int kTileMax = 512;             // max hits of one packed tile (one wave)
 constexpr int kQueues = 8;                // work-queue ranges (one ticket each)
 constexpr int kQueueStride = 64;          // ints between tickets: one 256-byte line each
 
@@ -138,8 +139,8 @@ struct Params {
     uint8_t* flags;      // [n_events * n_blk]
     long long* seg_cnt;  // [n_events * n_seg] (nonzero blocks << 32 | nonzero cells)
     long long* seg_off;  // [n_events * n_seg] exclusive prefix of seg_cnt
-    unsigned long long* blk_list;  // [n_events * n_seg * kSegBlocks] position << 32 | (event << blk_shift | block)
     long long* seg_blk;  // [n_seg_blocks]
+    unsigned long long* blk_list;  // [n_events * n_seg * kSegBlocks] position << 32 | (event << blk_shift | block)
     Counters* ctr;
     int32_t* queue;      // [kQueues * kQueueStride * 2]: tickets, then drained flags
     // outputs (device)
@@ -306,6 +307,7 @@ __device__ __forceinline__ int block_excl_scan1(int v, int& total)
     total = tot;
     return inc - v + off;
 }
+
 
 template <typename T>
 __device__ __forceinline__ T block_excl_scan_t(T v, T& total)
@@ -493,6 +495,14 @@ __global__ void k_validate(const Params* __restrict__ Pp)
 // ------------------------------------------- per-task setup (a1 - a3) ---
 // One thread per (particle, layer); the particles of a block share their
 // Gamma draws through LDS for the Dirichlet normalization.
+// (hits, chunks, small hits, small tasks) of a task with n hits
+__device__ __forceinline__ int4 task_terms(const Params& P, int n)
+{
+    const bool big = n >= P.big_thr;
+    return make_int4(n, big ? (n + P.chunk_hits - 1) / P.chunk_hits : 0, (!big && n > 0) ? n : 0,
+                     (!big && n > 0) ? 1 : 0);
+}
+
 __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
@@ -524,12 +534,11 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
     }
     g_s[tid] = g;
     __syncthreads();
-    if (!active) return;
     int n = 0;
     float ehit = 0.0f;
     double el = 0.0;
     const long long t = gp * L + l;
-    if (set >= 0) {
+    if (active && set >= 0) {
         double sum = 0.0;
         for (int k = 0; k < L; ++k) sum = sum + g_s[lp * L + k];
         el = (double)pt.e * (g / sum);
@@ -548,41 +557,27 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
         }
         ehit = n > 0 ? (float)(e_used / (double)n) : 0.0f;
     }
-    G(P.task_n)[t] = n;
-    G(P.task_ehit)[t] = ehit;
-    if (G(P.out_elayer)) G(P.out_elayer)[t] = (float)el;
-    if (G(P.out_counts)) G(P.out_counts)[t] = n;
-    if (l == 0) {
-        G(P.part_ev)[gp] = ev;
-        G(P.part_p)[gp] = pin;
-        G(P.part_set)[gp] = set;
+    if (active) {
+        G(P.task_n)[t] = n;
+        G(P.task_ehit)[t] = ehit;
+        if (G(P.out_elayer)) G(P.out_elayer)[t] = (float)el;
+        if (G(P.out_counts)) G(P.out_counts)[t] = n;
+        if (l == 0) {
+            G(P.part_ev)[gp] = ev;
+            G(P.part_p)[gp] = pin;
+            G(P.part_set)[gp] = set;
+        }
     }
+    // this block's sums of (hits, chunks, small hits, small tasks) for the
+    // task scan; the scan's blocks are the setup blocks
+    int4 tot;
+    (void)block_excl_scan4(active ? task_terms(P, n) : make_int4(0, 0, 0, 0), tot);
+    if (tid == 0) store_i4(reinterpret_cast<int4*>(P.blk_sums), blockIdx.x, tot);
 }
 
 // ----------------------------------------- task scans -> work queue (a11) ---
 // per task: x = hits, y = chunks of a large task, z = hits of a small task,
 // w = 1 for a small task with hits
-__device__ __forceinline__ int4 task_terms(const Params& P, int n)
-{
-    const bool big = n >= P.big_thr;
-    return make_int4(n, big ? (n + P.chunk_hits - 1) / P.chunk_hits : 0, (!big && n > 0) ? n : 0,
-                     (!big && n > 0) ? 1 : 0);
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const Params* __restrict__ Pp)
-{
-    const Params& P = *Pp;
-    const long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanItems;
-    int4 s = make_int4(0, 0, 0, 0);
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const long long t = base + k;
-        if (t < P.n_tasks) s = add4(s, task_terms(P, G(P.task_n)[t]));
-    }
-    int4 tot;
-    (void)block_excl_scan4(s, tot);
-    if (threadIdx.x == 0) store_i4(reinterpret_cast<int4*>(P.blk_sums), blockIdx.x, tot);
-}
 
 // one block: exclusive scan of the block sums (hits, chunks, small hits,
 // small tasks); totals into the counters.  A thread owns `per` consecutive
@@ -601,16 +596,23 @@ __global__ __launch_bounds__(1024) void k_scan_top(const Params* __restrict__ Pp
     const int b0 = tid * per;
     const int4* in = reinterpret_cast<const int4*>(P.blk_sums);
     int4* out = reinterpret_cast<int4*>(P.blk_offs);
+    // block sums read kRun at a time, the loads of a run in flight together
+    constexpr int kRun = 8;
+    int4 vv[kRun];
     long long h = 0;
     int c = 0, sh = 0, st = 0;
-    for (int k = 0; k < per; ++k) {
-        const int b = b0 + k;
-        if (b < nb) {
-            const int4 v = load_i4(in, b);
-            h += v.x;
-            c += v.y;
-            sh += v.z;
-            st += v.w;
+    for (int c0 = 0; c0 < per; c0 += kRun) {
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            const int b = b0 + c0 + k;
+            vv[k] = (c0 + k < per && b < nb) ? load_i4(in, b) : make_int4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            h += vv[k].x;
+            c += vv[k].y;
+            sh += vv[k].z;
+            st += vv[k].w;
         }
     }
     const long long hi = wave_incl_scan<long long>(h);
@@ -632,13 +634,20 @@ __global__ __launch_bounds__(1024) void k_scan_top(const Params* __restrict__ Pp
         htot += wh;
         rtot = add4(rtot, wr);
     }
-    for (int k = 0; k < per; ++k) {
-        const int b = b0 + k;
-        if (b < nb) {
-            const int4 v = load_i4(in, b);
-            store_i4(out, b, make_int4((int)ho, ro.y, ro.z, ro.w));
-            ho += v.x;
-            ro = add4(ro, v);
+    for (int c0 = 0; c0 < per; c0 += kRun) {
+        if (per > kRun) {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                const int b = b0 + c0 + k;
+                vv[k] = (c0 + k < per && b < nb) ? load_i4(in, b) : make_int4(0, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            const int b = b0 + c0 + k;
+            if (c0 + k < per && b < nb) store_i4(out, b, make_int4((int)ho, ro.y, ro.z, ro.w));
+            ho += vv[k].x;
+            ro = add4(ro, vv[k]);
         }
     }
     if (tid < 2 * kQueues) G(P.queue)[tid * kQueueStride] = 0;
@@ -660,63 +669,48 @@ __global__ __launch_bounds__(1024) void k_scan_top(const Params* __restrict__ Pp
     }
 }
 
+// one thread per task, over the setup blocks (particles kBlock / L at a
+// time): the task's place in the hit list, its chunks, its small-task
+// records and the first task of every tile it opens
 __global__ __launch_bounds__(kBlock) void k_scan_write(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
     if (G(P.ctr)->error & (kErrTooManyHits | kErrChunkCap)) return;
-    const long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanItems;
-    // counts and hit energies of the thread's tasks are loaded up front; the
-    // per-particle data once per particle (consecutive tasks share it)
-    int nv[kScanItems];
-    float ev_[kScanItems];
-    int4 s = make_int4(0, 0, 0, 0);
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const long long t = base + k;
-        nv[k] = t < P.n_tasks ? G(P.task_n)[t] : 0;
-        ev_[k] = t < P.n_tasks ? G(P.task_ehit)[t] : 0.0f;
-        s = add4(s, task_terms(P, nv[k]));
-    }
-    int4 tot;
-    int4 run = add4(block_excl_scan4(s, tot), load_i4(reinterpret_cast<const int4*>(P.blk_offs), blockIdx.x));
     const int L = P.n_layers;
-    long long cur_gp = -1;
-    int4 rec1 = make_int4(0, 0, 0, 0);
-    int set_l0 = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        const long long t = base + k;
-        if (t >= P.n_tasks) break;
-        const int n = nv[k];
-        const int4 d = task_terms(P, n);
-        if (P.want_hits) G(P.task_hoff)[t] = run.x;
-        if (G(P.out_task_hoff)) G(P.out_task_hoff)[t] = P.hit_base + run.x;
-        const long long gp = t / L;
-        const int key = (int)(gp * 64 + (t - gp * L));
-        for (int c = 0; c < d.y; ++c) {
-            const int first = c * P.chunk_hits;
-            const int cnt = min(P.chunk_hits, n - first);
-            store_i4(P.chunks, run.y + c, make_int4(key, first, cnt, 0));
-        }
-        if (d.w) {
-            // two 16-byte records per small task: (first small hit, task key,
-            // Ehit bits, histogram) and (eta_p, phi_p, global event, particle
-            // in event)
-            if (gp != cur_gp) {
-                cur_gp = gp;
-                const Particle pt = load_particle(P.particles, gp);
-                const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)G(P.part_ev)[gp]);
-                rec1 = make_int4(__float_as_int(pt.eta), __float_as_int(pt.phi), (int)evg,
-                                 (int)G(P.part_p)[gp]);
-                set_l0 = G(P.part_set)[gp] * L;
-            }
-            store_i4(P.small_rec, 2LL * run.w,
-                     make_int4(run.z, key, __float_as_int(ev_[k]), set_l0 + (key & 63)));
-            store_i4(P.small_rec, 2LL * run.w + 1, rec1);
-            const int T = P.tile_hits;
-            const int q = (run.z + T - 1) / T;
-            if ((long long)q * T < (long long)run.z + n) G(P.tile_first)[q] = run.w;
-        }
-        run = add4(run, d);
+    const int ppb = kBlock / L;
+    const int tid = threadIdx.x;
+    const long long t = (long long)blockIdx.x * ppb * L + tid;
+    const bool active = tid < ppb * L && t < P.n_tasks;
+    const int n = active ? G(P.task_n)[t] : 0;
+    const int4 d = task_terms(P, n);
+    int4 tot;
+    const int4 run = add4(block_excl_scan4(d, tot),
+                          load_i4(reinterpret_cast<const int4*>(P.blk_offs), blockIdx.x));
+    if (!active) return;
+    if (P.want_hits) G(P.task_hoff)[t] = run.x;
+    if (G(P.out_task_hoff)) G(P.out_task_hoff)[t] = P.hit_base + run.x;
+    const long long gp = t / L;
+    const int key = (int)(gp * 64 + (t - gp * L));
+    for (int c = 0; c < d.y; ++c) {
+        const int first = c * P.chunk_hits;
+        const int cnt = min(P.chunk_hits, n - first);
+        store_i4(P.chunks, run.y + c, make_int4(key, first, cnt, 0));
+    }
+    if (d.w) {
+        // two 16-byte records per small task: (first small hit, task key,
+        // Ehit bits, histogram) and (eta_p, phi_p, global event, particle
+        // in event)
+        const Particle pt = load_particle(P.particles, gp);
+        const int H = G(P.part_set)[gp] * L + (key & 63);
+        store_i4(P.small_rec, 2LL * run.w,
+                 make_int4(run.z, key, __float_as_int(G(P.task_ehit)[t]), H));
+        const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)G(P.part_ev)[gp]);
+        store_i4(P.small_rec, 2LL * run.w + 1,
+                 make_int4(__float_as_int(pt.eta), __float_as_int(pt.phi), (int)evg,
+                           (int)G(P.part_p)[gp]));
+        const int T = P.tile_hits;
+        const int q = (run.z + T - 1) / T;
+        if ((long long)q * T < (long long)run.z + n) G(P.tile_first)[q] = run.w;
     }
 }
 

@@ -569,7 +569,8 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     if ((sh.n_events << blk_shift) > 0xffffffffLL)
         return fail(c, FCS_E_INVALID_ARG, "%lld events in one batch: at most %lld for this geometry",
                     (long long)sh.n_events, 0xffffffffLL >> blk_shift);
-    const long long nsb = (nt + fcsk::kScanBlock - 1) / fcsk::kScanBlock;
+    // the task scan runs over the setup blocks (kBlock / L particles each)
+    const long long nsb = (N + fcsk::kBlock / L - 1) / (fcsk::kBlock / L);
     const long long nseg = E * n_seg;
     const long long nsegb = (nseg + fcsk::kScanBlock - 1) / fcsk::kScanBlock;
     if (c->chunk_cap < nt + 1024) c->chunk_cap = nt + 1024;
@@ -719,7 +720,6 @@ void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, int g
         const int ppb = fcsk::kBlock / P.n_layers;
         hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(P.n_particles, ppb)), dim3(fcsk::kBlock), 0,
                            s, dP);
-        hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
     }
@@ -1248,7 +1248,6 @@ int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* ev
                            dim3(256), 0, c->stream, dP);
     hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(in.N, fcsk::kBlock / c->n_layers)), dim3(fcsk::kBlock),
                        0, c->stream, dP);
-    hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, c->stream, dP);
     hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, c->stream, dP);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
@@ -1309,7 +1308,6 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
                            c->n_hist * 512, 0u);
         hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(in.N, fcsk::kBlock / c->n_layers)),
                            dim3(fcsk::kBlock), 0, s, dP);
-        hipLaunchKernelGGL(fcsk::k_scan_reduce, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_adjoint, dim3(c->n_cu * tu.wg_per_cu), dim3(fcsk::kBlock),
