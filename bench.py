@@ -88,12 +88,68 @@ def _time_steps(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) / steps, res
 
 
+def run_fwd_bwd(torch, sim, geo, par, dev, steps, warmup):
+    """Forward (dense cells through the autograd binding) + loss + backward
+    (the adjoint) on the 64-pion workload; hits of one forward per second."""
+    from paper_2103_14737_amd import workloads as W
+    from paper_2103_14737_amd.fcs import particles_to_device
+    wd = W.single_pion_diff()
+    dpd = particles_to_device(wd.particles, dev)
+    doffd = torch.from_numpy(wd.event_offsets).to(dev)
+    base = sim.simulate_events(dpd, doffd, wd.seed, outputs=("dense", "elayer"))
+    el = base["elayer"]
+    # targets: the same particles with perturbed, renormalized layer fractions
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(wd.seed)
+    e2 = el.reshape(-1, sim.n_layers).double()
+    pert = (e2 * (1 + 0.2 * torch.randn(e2.shape, generator=gen, device=dev,
+                                        dtype=torch.float64))).clamp_min(0)
+    pert = (pert * (e2.sum(1, keepdim=True) / pert.sum(1, keepdim=True))).float().reshape(-1)
+    target = sim.simulate_events(dpd, doffd, wd.seed, outputs=("dense",),
+                                 elayer_override=pert)["cells"]
+    from paper_2103_14737_amd.autograd import simulate_dense
+    el_leaf = el.detach().clone().requires_grad_()
+    wt_leaf = torch.from_numpy(par["weights"]).to(dev).requires_grad_()
+    times = {"fwd": 0.0, "bwd": 0.0}
+    nh = [int(base["stats"]["n_hits"])]
+
+    def step_fb():
+        # forward (cells and loss) and the adjoint through torch.autograd
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        el_leaf.grad = None
+        wt_leaf.grad = None
+        cells = simulate_dense(sim, dpd, doffd, wd.seed, el_leaf, wt_leaf)
+        loss = ((cells - target) ** 2).sum()
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        times["fwd"] += b - a
+        times["bwd"] += time.perf_counter() - b
+        return nh[0]
+
+    for _ in range(warmup):
+        step_fb()
+    times["fwd"] = times["bwd"] = 0.0
+    t_fb, _ = _time_steps(torch, step_fb, steps, 0)
+    res = {"workload": "single_pion_diff", "n_events": wd.n_events,
+           "hits_per_step": nh[0], "hits_per_s": nh[0] / t_fb,
+           "t_fwd_ms": times["fwd"] / steps * 1e3,
+           "t_bwd_ms": times["bwd"] / steps * 1e3}
+    print(f"bench: fwd+bwd {nh[0] / t_fb:.4g} hits/s", flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fwd-bwd-only", action="store_true",
+                    help="time only the forward + backward section and print its figures "
+                         "(for profiling; not the benchmark line)")
     ap.add_argument("--only-headline", action="store_true",
                     help="time only the headline batched workload (for profiling)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -126,6 +182,10 @@ def main():
     sim.load_geometry(geo)
     sim.load_parametrization(par)
     load_ms = (time.perf_counter() - t0) * 1e3
+
+    if args.fwd_bwd_only:
+        print(json.dumps(run_fwd_bwd(torch, sim, geo, par, dev, args.steps, args.warmup)), flush=True)
+        return 0
 
     def prepare(w, outputs=("compact",)):
         dp = particles_to_device(w.particles, dev)
@@ -249,52 +309,7 @@ def main():
         print(f"bench: per-event {t_pe * 1e3:.1f} ms/step -> batched is "
               f"{t_pe / t_step:.1f}x faster", flush=True)
 
-        # ---------------------------------------- forward + backward (64 pions)
-        wd = W.single_pion_diff()
-        dpd = particles_to_device(wd.particles, dev)
-        doffd = torch.from_numpy(wd.event_offsets).to(dev)
-        base = sim.simulate_events(dpd, doffd, wd.seed, outputs=("dense", "elayer"))
-        el = base["elayer"]
-        # targets: the same particles with perturbed, renormalized layer fractions
-        gen = torch.Generator(device=dev)
-        gen.manual_seed(wd.seed)
-        e2 = el.reshape(-1, sim.n_layers).double()
-        pert = (e2 * (1 + 0.2 * torch.randn(e2.shape, generator=gen, device=dev,
-                                            dtype=torch.float64))).clamp_min(0)
-        pert = (pert * (e2.sum(1, keepdim=True) / pert.sum(1, keepdim=True))).float().reshape(-1)
-        target = sim.simulate_events(dpd, doffd, wd.seed, outputs=("dense",),
-                                     elayer_override=pert)["cells"]
-        from paper_2103_14737_amd.autograd import simulate_dense
-        el_leaf = el.detach().clone().requires_grad_()
-        wt_leaf = torch.from_numpy(par["weights"]).to(dev).requires_grad_()
-        times = {"fwd": 0.0, "bwd": 0.0}
-        nh = [int(base["stats"]["n_hits"])]
-
-        def step_fb():
-            # forward (cells and loss) and the adjoint through torch.autograd
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            el_leaf.grad = None
-            wt_leaf.grad = None
-            cells = simulate_dense(sim, dpd, doffd, wd.seed, el_leaf, wt_leaf)
-            loss = ((cells - target) ** 2).sum()
-            torch.cuda.synchronize()
-            b = time.perf_counter()
-            loss.backward()
-            torch.cuda.synchronize()
-            times["fwd"] += b - a
-            times["bwd"] += time.perf_counter() - b
-            return nh[0]
-
-        for _ in range(args.warmup):
-            step_fb()
-        times["fwd"] = times["bwd"] = 0.0
-        t_fb, _ = _time_steps(torch, step_fb, args.steps, 0)
-        line["fwd_bwd"] = {"workload": "single_pion_diff", "n_events": wd.n_events,
-                           "hits_per_step": nh[0], "hits_per_s": nh[0] / t_fb,
-                           "t_fwd_ms": times["fwd"] / args.steps * 1e3,
-                           "t_bwd_ms": times["bwd"] / args.steps * 1e3}
-        print(f"bench: fwd+bwd {nh[0] / t_fb:.4g} hits/s", flush=True)
+        line["fwd_bwd"] = run_fwd_bwd(torch, sim, geo, par, dev, args.steps, args.warmup)
 
         # ---------------------------------------- multi-particle workloads
         others = {}

@@ -318,9 +318,12 @@ int fcs_query_sizes(fcs_ctx *ctx, const fcs_particle *particles,
  *                    A_hb = sum over hits of histogram h in bin b of
  *                    g[cell] * Ehit, S_h = sum_b A_hb, W_h = sum_b w_hb
  *                    (A_hb / w_hb is taken as 0 when w_hb = 0).
- * grad_elayer is f32 [N * n_layers], grad_weights f32 [n_histograms * 256];
- * both are device pointers (either may be NULL).  Inputs follow
- * opt->inputs_on_device.  Synchronous like fcs_simulate_events.
+ * grad_elayer is f32 [N * n_layers], grad_weights f32 [n_histograms * 256]
+ * and 16-byte aligned; both are device pointers (either may be NULL).
+ * Inputs follow opt->inputs_on_device.  Synchronous like
+ * fcs_simulate_events.  The context keeps FP64 accumulators for these sums
+ * (8 bytes per task and per histogram bin), zeroed when allocated and
+ * cleared again by each call.
  * ------------------------------------------------------------------------ */
 int fcs_backward(fcs_ctx *ctx, const fcs_particle *particles,
                  const int64_t *event_offsets, int64_t n_events,

@@ -39,8 +39,9 @@ class _SimulateDense(torch.autograd.Function):
         bkw = {k: v for k, v in ctx.kw.items()
                if k in ("event_index_base", "hit_energy_scale", "nhit_cap", "min_layer_energy")}
         ge, gw = ctx.sim.backward(ctx.particles, ctx.event_offsets, ctx.seed,
-                                  grad_cells.reshape(-1), elayer_override=elayer.detach(), **bkw)
-        return (ge if need_e else None, gw if need_w else None) + (None,) * 5
+                                  grad_cells.reshape(-1), elayer_override=elayer.detach(),
+                                  need_elayer=need_e, need_weights=need_w, **bkw)
+        return (ge, gw) + (None,) * 5
 
 
 def sampled_elayer(sim, particles, event_offsets, seed, **kw):

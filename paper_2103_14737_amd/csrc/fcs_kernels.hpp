@@ -162,6 +162,7 @@ struct Params {
     const float* grad_cells;
     double* acc_elayer;   // [n_tasks] FP64 sums of g over in-acceptance hits
     double* acc_bins;     // [n_hist * 256] FP64 sums of g * Ehit
+    uint8_t* hist_mark;   // [n_hist] 1 where acc_bins may hold sums (backward only)
     float* grad_elayer;
     float* grad_weights;
     long long n_hist;
@@ -200,6 +201,8 @@ __device__ __forceinline__ void gadd(FCS_AS_GLOBAL double* p, double v)
 // 16-byte records (particles, work items, scan partials) move as native int
 // vectors, which load and store from the global address space directly
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ Particle load_particle(const Particle* base, long long i)
 {
@@ -343,20 +346,6 @@ __device__ __forceinline__ long long block_sum_ll(long long v)
     return t;
 }
 
-
-__device__ __forceinline__ double block_sum_ll_d(double v)
-{
-    __shared__ double redd[kBlock / kWave];
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-    if (lane_id() == 0) redd[threadIdx.x / kWave] = v;
-    __syncthreads();
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) t += redd[w];
-    __syncthreads();
-    return t;
-}
 
 // ---------------------------------------------------- set selection (a1) ---
 __device__ __forceinline__ int select_set(const Params& P, int pdg, float e, float eta)
@@ -556,6 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
             e_used = ov >= 0.0f ? (double)ov : 0.0;
         }
         ehit = n > 0 ? (float)(e_used / (double)n) : 0.0f;
+        if (n > 0 && G(P.hist_mark)) G(P.hist_mark)[set * L + l] = 1;
     }
     if (active) {
         G(P.task_n)[t] = n;
@@ -1407,6 +1397,28 @@ __global__ __launch_bounds__(kBlock) void k_seg_list(const Params* __restrict__ 
     if (cells) w4p[lane] = v4i{0, 0, 0, 0};
 }
 
+// Calls whose only cell output is the caller's dense buffer skip the
+// compaction: this pass counts the nonzero cells from the per-block counts
+// (the nnz statistic) and clears those counts for the next call.
+__global__ __launch_bounds__(kBlock) void k_flags_reset(const Params* __restrict__ Pp)
+{
+    const Params& P = *Pp;
+    const long long n = P.n_events << (P.blk_shift - 4);  // 16-byte words
+    auto f = (FCS_AS_GLOBAL v4i*)G(P.flags);
+    long long s = 0;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        const v4i w = f[i];
+        if (w.x | w.y | w.z | w.w) {
+            s += byte_sum((uint32_t)w.x) + byte_sum((uint32_t)w.y) + byte_sum((uint32_t)w.z) +
+                 byte_sum((uint32_t)w.w);
+            f[i] = v4i{0, 0, 0, 0};
+        }
+    }
+    const long long tot = block_sum_ll(s);
+    if (threadIdx.x == 0 && tot) (void)gfetch_add(&G(P.ctr)->nnz_total, tot);
+}
+
 // emit pass: persistent waves take kEmitBatch listed blocks at a time; all
 // loads of a batch are range-checked buffer loads issued before their use
 __global__ __launch_bounds__(kBlock) void k_seg_emit(const Params* __restrict__ Pp)
@@ -1554,28 +1566,61 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
     }
 }
 
-// dL/dE_layer = (sum of g over the task's in-acceptance hits) / n
+// dL/dE_layer = (sum of g over the task's in-acceptance hits) / n.  The
+// accumulator is cleared once read, so the next call starts from zero.
 __global__ void k_adj_elayer(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= P.n_tasks) return;
     const int n = G(P.task_n)[t];
-    G(P.grad_elayer)[t] = n > 0 ? (float)(G(P.acc_elayer)[t] / (double)n) : 0.0f;
+    const double a = G(P.acc_elayer)[t];
+    if (G(P.grad_elayer)) G(P.grad_elayer)[t] = n > 0 ? (float)(a / (double)n) : 0.0f;
+    if (a != 0.0) G(P.acc_elayer)[t] = 0.0;
 }
 
-// dL/dw_b = A_b / w_b - S / W per histogram (one block per histogram)
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// dL/dw_b = A_b / w_b - S / W per histogram, one wave per histogram (four
+// bins a lane).  Histograms no task of the call drew from have A = 0 and a
+// zero gradient; the others are read, and their sums and mark cleared.
 __global__ __launch_bounds__(kBlock) void k_adj_weights(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
-    const long long H = blockIdx.x;
-    const int b = threadIdx.x;
-    const double w = (double)G(P.weights)[H * kBins + b];
-    const double A = G(P.acc_bins)[H * kBins + b];
-    const double W = block_sum_ll_d(w);
-    const double S = block_sum_ll_d(A);
-    const double lr = w > 0.0 ? A / w : 0.0;
-    G(P.grad_weights)[H * kBins + b] = (float)(lr - S / W);
+    const int lane = lane_id();
+    const long long waves = (long long)gridDim.x * kWavesPerBlock;
+    const auto gw = (FCS_AS_GLOBAL v4f*)G(P.grad_weights);
+    const auto wv = (const FCS_AS_GLOBAL v4f*)G(P.weights);
+    const auto av = (FCS_AS_GLOBAL v2d*)G(P.acc_bins);
+    for (long long H = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; H < P.n_hist;
+         H += waves) {
+        const long long i = H * (kBins / 4) + lane;  // this lane's four bins
+        if (!G(P.hist_mark)[H]) {
+            if (gw) gw[i] = v4f{0.f, 0.f, 0.f, 0.f};
+            continue;
+        }
+        const v4f w4 = wv[i];
+        const v2d a01 = av[2 * i], a23 = av[2 * i + 1];
+        const double W = wave_sum_d(((double)w4.x + (double)w4.y) + ((double)w4.z + (double)w4.w));
+        const double S = wave_sum_d((a01.x + a01.y) + (a23.x + a23.y));
+        const double q = S / W;
+        if (gw) {
+            v4f r;
+            r.x = (float)((w4.x > 0.f ? a01.x / (double)w4.x : 0.0) - q);
+            r.y = (float)((w4.y > 0.f ? a01.y / (double)w4.y : 0.0) - q);
+            r.z = (float)((w4.z > 0.f ? a23.x / (double)w4.z : 0.0) - q);
+            r.w = (float)((w4.w > 0.f ? a23.y / (double)w4.w : 0.0) - q);
+            gw[i] = r;
+        }
+        av[2 * i] = v2d{0.0, 0.0};
+        av[2 * i + 1] = v2d{0.0, 0.0};
+        if (lane == 0) G(P.hist_mark)[H] = 0;
+    }
 }
 
 }  // namespace fcsk

@@ -33,11 +33,11 @@ struct DevBuf {
 
 struct GraphKey {
     long long n_particles, n_events;
-    int dense, validate, grid, part;
+    int mode, validate, grid, part;
     bool operator<(const GraphKey& o) const
     {
-        return std::tie(n_particles, n_events, dense, validate, grid, part) <
-               std::tie(o.n_particles, o.n_events, o.dense, o.validate, o.grid, o.part);
+        return std::tie(n_particles, n_events, mode, validate, grid, part) <
+               std::tie(o.n_particles, o.n_events, o.mode, o.validate, o.grid, o.part);
     }
 };
 
@@ -80,7 +80,7 @@ struct fcs_ctx {
     DevBuf w_particles, w_evoff, w_override, w_task_n, w_task_ehit, w_part_ev, w_part_p,
         w_part_set, w_blk_sums, w_blk_offs, w_task_hoff, w_chunks, w_small_rec,
         w_tile_first, w_cells, w_flags, w_seg_cnt, w_seg_off, w_seg_blk, w_blk_list, w_queue, w_params,
-        w_acc_el, w_acc_bins;
+        w_acc_el, w_acc_bins, w_hist_mark;
     long long cells_events = 0;  // events the accumulator holds (kept zero)
     long long flag_events = 0;
     long long chunk_cap = 0;
@@ -295,7 +295,7 @@ void fcs_destroy(fcs_ctx* c)
                       &c->w_blk_sums, &c->w_blk_offs, &c->w_task_hoff, &c->w_chunks,
                       &c->w_small_rec, &c->w_tile_first, &c->w_cells, &c->g_layers, &c->g_regions,
                       &c->w_flags, &c->w_seg_cnt, &c->w_seg_off, &c->w_seg_blk, &c->w_blk_list, &c->w_queue,
-                      &c->w_params, &c->w_acc_el, &c->w_acc_bins, &c->o_cells, &c->o_ids,
+                      &c->w_params, &c->w_acc_el, &c->w_acc_bins, &c->w_hist_mark, &c->o_cells, &c->o_ids,
                       &c->o_e, &c->o_evoff, &c->o_heta, &c->o_hphi, &c->o_he, &c->o_hcell,
                       &c->o_thoff, &c->o_counts, &c->o_elayer, &c->w_async};
     for (DevBuf* b : bufs) release(c, *b);
@@ -706,9 +706,14 @@ size_t geo_lds_bytes(const Params& P) { return (size_t)(3 * P.n_layers + 2 * P.n
 // part: 0 = everything, 1 = up to the work queue, 2 = the hit kernel,
 // 3 = compaction and reset.
 enum Part { kAll = 0, kPre = 1, kHits = 2, kPost = 3 };
+// where the cell energies go: the private accumulator (compacted, then
+// cleared), the caller's dense buffer and the compacted list, or the
+// caller's dense buffer alone (no compaction; the block counts are cleared)
+enum CellMode { kPrivate = 0, kDenseCompact = 1, kDenseOnly = 2 };
 
-void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, int grid, int part)
+void enqueue_batch(fcs_ctx* c, const Params& P, int mode, bool validate, int grid, int part)
 {
+    const bool dense = mode != kPrivate;
     const Params* dP = (const Params*)c->w_params.p;
     hipStream_t s = c->stream;
     if (part == kAll || part == kPre) {
@@ -725,7 +730,12 @@ void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, int g
     }
     if (part == kAll || part == kHits)
         hipLaunchKernelGGL(fcsk::k_hits, dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
-    if (part == kAll || part == kPost) {
+    if ((part == kAll || part == kPost) && mode == kDenseOnly) {
+        const long long words = P.n_events << (P.blk_shift - 4);
+        hipLaunchKernelGGL(fcsk::k_flags_reset,
+                           dim3((unsigned)std::min<long long>(grid_for(words, fcsk::kBlock), (long long)c->n_cu * 8)),
+                           dim3(fcsk::kBlock), 0, s, dP);
+    } else if (part == kAll || part == kPost) {
         const unsigned nw = grid_for(P.n_events * P.n_seg, fcsk::kBlock / fcsk::kWave);
         hipLaunchKernelGGL(fcsk::k_seg_count, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_seg_reduce, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
@@ -738,7 +748,7 @@ void enqueue_batch(fcs_ctx* c, const Params& P, bool dense, bool validate, int g
 }
 
 // instantiate (once per batch shape) and launch the graph of one part
-int launch_graph(fcs_ctx* c, const Params& P, const GraphKey& key, bool dense, bool validate,
+int launch_graph(fcs_ctx* c, const Params& P, const GraphKey& key, int mode, bool validate,
                  int grid, int part)
 {
     auto it = c->graphs.find(key);
@@ -746,7 +756,7 @@ int launch_graph(fcs_ctx* c, const Params& P, const GraphKey& key, bool dense, b
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_batch(c, P, dense, validate, grid, part);
+        enqueue_batch(c, P, mode, validate, grid, part);
         HIPCHK(c, hipStreamEndCapture(c->stream, &g));
         const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -796,8 +806,8 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         std::memset(hc, 0, sizeof(Counters));
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
         if ((rc = ring_sent(c))) return rc;
-        const bool dense = dense_out != nullptr;
-        GraphKey key{sh.n_particles, sh.n_events, dense ? 1 : 0, validate ? 1 : 0, grid, kAll};
+        const int mode = !dense_out ? kPrivate : (P->out_ids ? kDenseCompact : kDenseOnly);
+        GraphKey key{sh.n_particles, sh.n_events, mode, validate ? 1 : 0, grid, kAll};
         hipEvent_t k0 = c->ev_k0, k1 = c->ev_k1;
         if (profile && async) {
             // a free event pair for this call; the oldest pending one is read
@@ -817,24 +827,24 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             ++c->prof_count;
         }
         if (use_graph && !profile) {
-            if ((rc = launch_graph(c, *P, key, dense, validate, grid, kAll))) return rc;
+            if ((rc = launch_graph(c, *P, key, mode, validate, grid, kAll))) return rc;
         } else {
             // profiled: the hit kernel is launched on its own between two event
             // records (graphs for the parts before and after it)
             if (use_graph) {
                 key.part = kPre;
-                if ((rc = launch_graph(c, *P, key, dense, validate, grid, kPre))) return rc;
+                if ((rc = launch_graph(c, *P, key, mode, validate, grid, kPre))) return rc;
             } else {
-                enqueue_batch(c, *P, dense, validate, grid, kPre);
+                enqueue_batch(c, *P, mode, validate, grid, kPre);
             }
             if (profile) HIPCHK(c, hipEventRecord(k0, c->stream));
-            enqueue_batch(c, *P, dense, validate, grid, kHits);
+            enqueue_batch(c, *P, mode, validate, grid, kHits);
             if (profile) HIPCHK(c, hipEventRecord(k1, c->stream));
             if (use_graph) {
                 key.part = kPost;
-                if ((rc = launch_graph(c, *P, key, dense, validate, grid, kPost))) return rc;
+                if ((rc = launch_graph(c, *P, key, mode, validate, grid, kPost))) return rc;
             } else {
-                enqueue_batch(c, *P, dense, validate, grid, kPost);
+                enqueue_batch(c, *P, mode, validate, grid, kPost);
             }
             HIPCHK(c, hipGetLastError());
         }
@@ -1267,6 +1277,8 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
 {
     if (!c) return FCS_E_INVALID_ARG;
     if (!grad_cells) return fail(c, FCS_E_INVALID_ARG, "grad_cells is NULL");
+    if ((uintptr_t)grad_weights & 15)
+        return fail(c, FCS_E_INVALID_ARG, "grad_weights must be 16-byte aligned");
     Tuning tu;
     int rc = o ? check_tuning(c, o, &tu) : fail(c, FCS_E_INVALID_ARG, "options are NULL");
     if (rc) return rc;
@@ -1278,9 +1290,17 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         HIPCHK(c, hipStreamSynchronize(c->stream));
         return FCS_OK;
     }
-    if ((rc = ensure(c, c->w_acc_el, (size_t)nt * 8)) ||
-        (rc = ensure(c, c->w_acc_bins, (size_t)c->n_hist * 256 * 8)))
+    // The accumulators are zeroed when allocated; the passes that read them
+    // (k_adj_elayer, k_adj_weights) clear what they read, so every call
+    // finds them at zero.
+    bool g_el = false, g_bins = false, g_mark = false;
+    if ((rc = ensure(c, c->w_acc_el, (size_t)nt * 8, &g_el)) ||
+        (rc = ensure(c, c->w_acc_bins, (size_t)c->n_hist * 256 * 8, &g_bins)) ||
+        (rc = ensure(c, c->w_hist_mark, (size_t)c->n_hist, &g_mark)))
         return rc;
+    if (g_el) HIPCHK(c, hipMemsetAsync(c->w_acc_el.p, 0, c->w_acc_el.bytes, c->stream));
+    if (g_bins) HIPCHK(c, hipMemsetAsync(c->w_acc_bins.p, 0, c->w_acc_bins.bytes, c->stream));
+    if (g_mark) HIPCHK(c, hipMemsetAsync(c->w_hist_mark.p, 0, c->w_hist_mark.bytes, c->stream));
     for (int attempt = 0; attempt < 2; ++attempt) {
         char* blk = ring_take(c);
         if (!blk) return fail(c, FCS_E_HIP, "hipEventSynchronize on a parameter block failed");
@@ -1293,6 +1313,7 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         P->grad_cells = grad_cells;
         P->acc_elayer = (double*)c->w_acc_el.p;
         P->acc_bins = (double*)c->w_acc_bins.p;
+        P->hist_mark = (uint8_t*)c->w_hist_mark.p;
         P->grad_elayer = grad_elayer;
         P->grad_weights = grad_weights;
         const Params* dP = (const Params*)c->w_params.p;
@@ -1303,19 +1324,19 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         if (in.validate_on_device)
             hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(in.N, (long long)n_events), 256)),
                                dim3(256), 0, s, dP);
-        hipLaunchKernelGGL(fcsk::k_fill_u32, dim3(1024), dim3(256), 0, s, (uint32_t*)c->w_acc_el.p, nt * 2, 0u);
-        hipLaunchKernelGGL(fcsk::k_fill_u32, dim3(2048), dim3(256), 0, s, (uint32_t*)c->w_acc_bins.p,
-                           c->n_hist * 512, 0u);
         hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(in.N, fcsk::kBlock / c->n_layers)),
                            dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_adjoint, dim3(c->n_cu * tu.wg_per_cu), dim3(fcsk::kBlock),
                            geo_lds_bytes(*P), s, dP);
-        if (grad_elayer)
-            hipLaunchKernelGGL(fcsk::k_adj_elayer, dim3(grid_for(nt, 256)), dim3(256), 0, s, dP);
-        if (grad_weights)
-            hipLaunchKernelGGL(fcsk::k_adj_weights, dim3((unsigned)c->n_hist), dim3(fcsk::kBlock), 0, s, dP);
+        // both passes run whatever gradients are asked for: they also clear
+        // the accumulators
+        hipLaunchKernelGGL(fcsk::k_adj_elayer, dim3(grid_for(nt, 256)), dim3(256), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_adj_weights,
+                           dim3(grid_for(std::min<long long>(c->n_hist, (long long)c->n_cu * 32),
+                                         fcsk::kBlock / fcsk::kWave)),
+                           dim3(fcsk::kBlock), 0, s, dP);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
                                  hipMemcpyDeviceToHost, s));

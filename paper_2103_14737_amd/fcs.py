@@ -375,9 +375,10 @@ class Simulator:
     def backward(self, particles, event_offsets, seed, grad_cells, *, event_index_base=0,
                  hit_energy_scale=100.0, nhit_cap=20000, min_layer_energy=1e-6,
                  elayer_override=None, grad_elayer=None, grad_weights=None, chunk_hits=0,
-                 big_task_hits=0, tile_hits=0, wg_per_cu=0):
+                 big_task_hits=0, tile_hits=0, wg_per_cu=0, need_elayer=True, need_weights=True):
         """fcs_backward on device tensors: returns (grad_elayer [N*L],
-        grad_weights [n_hist*256]) as torch CUDA float32 tensors."""
+        grad_weights [n_hist*256]) as torch CUDA float32 tensors; a gradient
+        with need_* False is not computed and returned as None."""
         import torch
         p, off, ov, dev, stream, n_events = self._inputs(particles, event_offsets, elayer_override)
         assert dev and _is_torch(grad_cells) and grad_cells.is_cuda
@@ -386,9 +387,13 @@ class Simulator:
                           min_layer_energy, chunk_hits, big_task_hits, tile_hits, wg_per_cu,
                           False, dev, ov, stream, n_particles=N)
         g = grad_cells.contiguous().float()
-        if grad_elayer is None:
+        if not need_elayer:
+            grad_elayer = None
+        elif grad_elayer is None:
             grad_elayer = torch.empty(N * self.n_layers, dtype=torch.float32, device=g.device)
-        if grad_weights is None:
+        if not need_weights:
+            grad_weights = None
+        elif grad_weights is None:
             grad_weights = torch.empty(self.n_hist * 256, dtype=torch.float32, device=g.device)
         self._check(self._L.fcs_backward(self._h, _ptr(p), _ptr(off), n_events, C.byref(o),
                                          _ptr(g), _ptr(grad_elayer), _ptr(grad_weights)))

@@ -359,3 +359,43 @@ def test_autograd_function(sim, oracle_lib, geom_full, param_full, geo, par, tor
         assert np.count_nonzero(b) > 0
         # same kernel, same incoming gradient: FP64 atomic order only
         assert np.all(np.abs(a - b) <= 1e-6 * np.abs(b) + 1e-9 * np.abs(b).max())
+
+
+def test_dense_only_then_compact(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+    """A dense-only call skips the compaction: its nonzero-cell count still
+    matches the oracle, and a compacted call after it starts clean."""
+    torch = torch_cuda
+    w = W.subset_events(W.single_particle_sweep(), 0, 20)
+    dp, doff = _dev(w, torch)
+    ref = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed)
+    r = sim.simulate_events(dp, doff, w.seed, outputs=("dense",))
+    torch.cuda.synchronize()
+    assert r["stats"]["n_cells_nonzero"] == ref["n_cells_nonzero"]
+    dense = _np(r["cells"])
+    assert np.count_nonzero(dense) == ref["n_cells_nonzero"]
+    w2 = W.subset_events(W.hard_scatter(), 0, 2)
+    r2, ref2 = run_both(sim, oracle_lib, geom_full, param_full, geo, w2, torch)
+    check_parity(r2, ref2, geo, label="compact after dense-only")
+    r3 = sim.simulate_events(dp, doff, w.seed, outputs=("dense", "compact"))
+    check_parity(r3, ref, geo, hits=False, counts=False, label="dense+compact after dense-only")
+
+
+def test_backward_repeats_and_partial_gradients(sim, geo, torch_cuda):
+    """The adjoint's accumulators are cleared by the passes that read them:
+    repeated calls, and calls asking for one gradient only, agree."""
+    torch = torch_cuda
+    w = W.subset_events(W.single_pion_diff(), 0, 8)
+    dp, doff = _dev(w, torch)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    g = torch.randn(w.n_events * geo["n_cells"], generator=gen, device="cuda")
+    e1, w1 = sim.backward(dp, doff, w.seed, g)
+    e2, _ = sim.backward(dp, doff, w.seed, g, need_weights=False)
+    _, w3 = sim.backward(dp, doff, w.seed, g, need_elayer=False)
+    e4, w4 = sim.backward(dp, doff, w.seed, g)
+    torch.cuda.synchronize()
+    for a, b in ((e1, e2), (e1, e4), (w1, w3), (w1, w4)):
+        a, b = _np(a).astype(np.float64), _np(b).astype(np.float64)
+        assert np.count_nonzero(a) > 0
+        # FP64 atomic order only
+        assert np.all(np.abs(a - b) <= 1e-6 * np.abs(a) + 1e-9 * np.abs(a).max())
