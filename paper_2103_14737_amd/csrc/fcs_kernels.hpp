@@ -869,6 +869,13 @@ static_assert(kListCap * 2 <= kWaveSlots * 4 && kListCap * 2 <= kBins * 8,
 static_assert(kGuide / 16 == kWave && kBins / 4 == kWave, "one 16-byte record per lane");
 static_assert(kChunkMax < 65536, "per-cell chunk counts are 16-bit");
 static_assert(kWaveSlots == 512, "hash_bits caps the table at 2^9 slots");
+// per-step (event, cell) table of the tile path: 64-bit keys in the wave's
+// guide area, FP32 sums in its histogram area (both reloaded per chunk)
+constexpr int kTileBits = 7;
+constexpr int kTileSlots = 1 << kTileBits;
+static_assert(kTileSlots * 8 <= kGuide && kTileSlots * 4 <= kBins * 4 && kTileSlots >= 2 * kWave,
+              "the tile table borrows a wave's guide and histogram");
+constexpr unsigned long long kEmpty64 = ~0ull;
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -877,14 +884,6 @@ __device__ __forceinline__ void wave_sync()
 }
 
 __device__ __forceinline__ int wave_broadcast_first(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// sum over the lanes of the wave (every lane gets the total)
-__device__ __forceinline__ float wave_sum(float v)
-{
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
 
 // Owners of the hits of a tile of small tasks, for one wave: every task that
 // starts inside the tile marks its first hit with its index relative to the
@@ -1114,6 +1113,8 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     uint16_t* owners = reinterpret_cast<uint16_t*>(hkey);  // tiles only
     float* cum = w_cum[wv];
     const uint8_t* guide = reinterpret_cast<const uint8_t*>(w_guide16[wv]);
+    unsigned long long* tkey = reinterpret_cast<unsigned long long*>(w_guide16[wv]);  // tiles only
+    float* tval = w_cum[wv];                                                           // tiles only
 
     const auto ctr = G(P.ctr);
     if (ctr->error & (kErrTooManyHits | kErrChunkCap)) return;
@@ -1187,19 +1188,37 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                 if (valid && P.want_hits)
                     write_hit(P, (long long)G(P.task_hoff)[sh.t] + sh.i, h, sh.ehit);
                 n_out += (valid && h.cell < 0) ? 1 : 0;
-                bool pending = valid && h.cell >= 0;
-                for (int round = 0; round < 2; ++round) {
-                    const unsigned long long act = __ballot(pending);
-                    if (!act) break;
-                    const int leader = __ffsll((long long)act) - 1;
-                    const int lc = __builtin_amdgcn_readlane(h.cell, leader);
-                    const int le = __builtin_amdgcn_readlane(sh.ev, leader);
-                    const bool same = pending && h.cell == lc && sh.ev == le;
-                    const float tot = wave_sum(same ? sh.ehit : 0.0f);
-                    if (lane == leader) deposit(P, le, lc, tot);
-                    pending = pending && !same;
+                // The step's hits are summed per (event, cell) in the wave's
+                // LDS table; the lane that claims a slot deposits its sum, so
+                // each (event, cell) of the step costs one device atomic.
+                tkey[lane] = kEmpty64;
+                tkey[lane + kWave] = kEmpty64;
+                tval[lane] = 0.0f;
+                tval[lane + kWave] = 0.0f;
+                wave_sync();
+                bool owner = false;
+                int slot = 0;
+                if (valid && h.cell >= 0) {
+                    const unsigned long long key =
+                        ((unsigned long long)(uint32_t)sh.ev << 32) | (uint32_t)h.cell;
+                    slot = (int)((((uint32_t)h.cell * 0x9E3779B1u) ^ ((uint32_t)sh.ev * 0x85EBCA77u)) >>
+                                 (32 - kTileBits));
+                    // at most kWave keys in kTileSlots >= 2 kWave slots: a
+                    // free or matching slot is always found
+                    for (int pr = 0; pr < kTileSlots; ++pr) {
+                        const unsigned long long o = atomicCAS(&tkey[slot], kEmpty64, key);
+                        if (o == kEmpty64) {
+                            owner = true;
+                            break;
+                        }
+                        if (o == key) break;
+                        slot = (slot + 1) & (kTileSlots - 1);
+                    }
+                    atomicAdd(&tval[slot], sh.ehit);
                 }
-                if (pending) deposit(P, sh.ev, h.cell, sh.ehit);
+                wave_sync();
+                if (owner) deposit(P, sh.ev, h.cell, tval[slot]);
+                wave_sync();
             }
             wave_sync();
             // the owner list borrowed the hash keys: empty them again
