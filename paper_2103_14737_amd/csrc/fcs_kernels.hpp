@@ -958,18 +958,49 @@ __device__ __forceinline__ SmallHit small_hit(const Params& P, int j, int hit)
 // nonzero cells (one byte per block, packed four to a word): the adder that
 // finds the cell at zero counts it.  Energies are positive, so exactly one
 // adder sees zero.
-__device__ __forceinline__ void deposit(const Params& P, long long ev, int cell, float v)
+__device__ __forceinline__ float deposit_add(const Params& P, long long ev, int cell, float v)
 {
-    if (!(v > 0.0f)) return;  // zero-energy hits leave the cell untouched
     const auto cp = G(P.cells) + ev * P.n_cells + cell;
     float old;
     [[clang::atomic(ignore_denormal_mode)]] {
         old = __hip_atomic_fetch_add(cp, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (old == 0.0f) {
-        const long long b = ev * P.n_blk + (cell >> 6);
-        (void)gfetch_add((FCS_AS_GLOBAL uint32_t*)(G(P.flags) + (b & ~3LL)), 1u << (8 * (b & 3)));
+    return old;
+}
+
+// the count word of (event, cell) and the increment of the cell's block in it
+__device__ __forceinline__ FCS_AS_GLOBAL uint32_t* count_word(const Params& P, long long ev, int cell)
+{
+    const long long b = ev * P.n_blk + (cell >> 6);
+    return (FCS_AS_GLOBAL uint32_t*)(G(P.flags) + (b & ~3LL));
+}
+__device__ __forceinline__ uint32_t count_inc(int cell) { return 1u << (8 * ((cell >> 6) & 3)); }
+
+__device__ __forceinline__ void deposit(const Params& P, long long ev, int cell, float v)
+{
+    if (!(v > 0.0f)) return;  // zero-energy hits leave the cell untouched
+    if (deposit_add(P, ev, cell, v) == 0.0f) (void)gfetch_add(count_word(P, ev, cell), count_inc(cell));
+}
+
+// Claim or find the slot of `key` in a wave's tile table (linear probing);
+// true for the lane that claimed it.  A step inserts at most kWave keys into
+// kTileSlots >= 2 kWave slots, so a free or matching slot is always found.
+__device__ __forceinline__ bool tile_slot(unsigned long long* tkey, unsigned long long key, uint32_t h,
+                                          int& slot)
+{
+    slot = (int)(h >> (32 - kTileBits));
+    for (int pr = 0; pr < kTileSlots; ++pr) {
+        const unsigned long long o = atomicCAS(&tkey[slot], kEmpty64, key);
+        if (o == kEmpty64) return true;
+        if (o == key) return false;
+        slot = (slot + 1) & (kTileSlots - 1);
     }
+    return false;
+}
+
+__device__ __forceinline__ uint32_t tile_hash(uint32_t a, uint32_t b)
+{
+    return (a * 0x9E3779B1u) ^ (b * 0x85EBCA77u);
 }
 
 // add `cnt` hits of `key` to a wave's LDS hash table (linear probing over
@@ -1115,6 +1146,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     const uint8_t* guide = reinterpret_cast<const uint8_t*>(w_guide16[wv]);
     unsigned long long* tkey = reinterpret_cast<unsigned long long*>(w_guide16[wv]);  // tiles only
     float* tval = w_cum[wv];                                                           // tiles only
+    uint32_t* tinc = reinterpret_cast<uint32_t*>(w_cum[wv]);                           // tiles only
 
     const auto ctr = G(P.ctr);
     if (ctr->error & (kErrTooManyHits | kErrChunkCap)) return;
@@ -1199,25 +1231,29 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                 bool owner = false;
                 int slot = 0;
                 if (valid && h.cell >= 0) {
-                    const unsigned long long key =
-                        ((unsigned long long)(uint32_t)sh.ev << 32) | (uint32_t)h.cell;
-                    slot = (int)((((uint32_t)h.cell * 0x9E3779B1u) ^ ((uint32_t)sh.ev * 0x85EBCA77u)) >>
-                                 (32 - kTileBits));
-                    // at most kWave keys in kTileSlots >= 2 kWave slots: a
-                    // free or matching slot is always found
-                    for (int pr = 0; pr < kTileSlots; ++pr) {
-                        const unsigned long long o = atomicCAS(&tkey[slot], kEmpty64, key);
-                        if (o == kEmpty64) {
-                            owner = true;
-                            break;
-                        }
-                        if (o == key) break;
-                        slot = (slot + 1) & (kTileSlots - 1);
-                    }
+                    owner = tile_slot(tkey, ((unsigned long long)(uint32_t)sh.ev << 32) | (uint32_t)h.cell,
+                                      tile_hash((uint32_t)h.cell, (uint32_t)sh.ev), slot);
                     atomicAdd(&tval[slot], sh.ehit);
                 }
                 wave_sync();
-                if (owner) deposit(P, sh.ev, h.cell, tval[slot]);
+                const float v = owner ? tval[slot] : 0.0f;
+                const bool fresh = v > 0.0f && deposit_add(P, sh.ev, h.cell, v) == 0.0f;
+                // the step's new cells are counted per count word (four
+                // blocks) in the same table: one device atomic per word
+                wave_sync();
+                tkey[lane] = kEmpty64;
+                tkey[lane + kWave] = kEmpty64;
+                tinc[lane] = 0u;
+                tinc[lane + kWave] = 0u;
+                wave_sync();
+                bool wowner = false;
+                if (fresh) {
+                    wowner = tile_slot(tkey, ((unsigned long long)(uint32_t)sh.ev << 32) | ((uint32_t)h.cell >> 8),
+                                       tile_hash((uint32_t)h.cell >> 8, (uint32_t)sh.ev), slot);
+                    atomicAdd(&tinc[slot], count_inc(h.cell));
+                }
+                wave_sync();
+                if (wowner) (void)gfetch_add(count_word(P, sh.ev, h.cell), tinc[slot]);
                 wave_sync();
             }
             wave_sync();
