@@ -120,6 +120,7 @@ struct Params {
     int32_t clean_cells;  // reset the accumulator while compacting
     int32_t chunk_cap;
     int32_t n_scan_blocks;
+    int32_t n_scan_groups;
     int32_t n_seg_blocks;
     // workspace
     int32_t* task_n;
@@ -128,7 +129,10 @@ struct Params {
     uint32_t* part_p;
     int32_t* part_set;
     int32_t* blk_sums;   // [n_scan_blocks * 4]
-    int32_t* blk_offs;   // [n_scan_blocks * 4]
+    int32_t* blk_offs;   // [n_scan_blocks * 4] prefixes within the block's scan group
+    long long* grp_hits; // [n_scan_groups] hits of each scan group
+    int32_t* grp_rest;   // [n_scan_groups * 4] (-, chunks, small hits, small tasks) of each group
+    int32_t* grp_offs;   // [n_scan_groups * 4] exclusive prefixes of the groups
     int32_t* task_hoff;  // [n_tasks] when want_hits
     int4* chunks;        // [chunk_cap] (task key, first hit, count, -)
     int4* small_rec;     // [2 * n_tasks] records of the small tasks
@@ -496,6 +500,11 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
     __shared__ double g_s[kBlock];
+    __shared__ double s_mu[kBlock];
+    __shared__ uint32_t s_pin[kBlock], s_evg[kBlock];
+    __shared__ int s_n[kBlock];
+    __shared__ uint16_t s_list[kBlock];
+    __shared__ int s_cnt[2];
     const int L = P.n_layers;
     const int ppb = kBlock / L;
     const int tid = threadIdx.x;
@@ -522,22 +531,45 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
         }
     }
     g_s[tid] = g;
+    if (tid < 2) s_cnt[tid] = 0;
     __syncthreads();
-    int n = 0;
-    float ehit = 0.0f;
     double el = 0.0;
     const long long t = gp * L + l;
+    // Poisson draws grouped by sampler branch: the block's inversion tasks
+    // (mu < 10) fill the task list from the front, the others from the back,
+    // so that each wave but one runs a single branch
+    int cls = -1;
     if (active && set >= 0) {
         double sum = 0.0;
         for (int k = 0; k < L; ++k) sum = sum + g_s[lp * L + k];
         el = (double)pt.e * (g / sum);
         if (el >= P.min_e && el > 0.0) {
             const double mu = el / (double)P.scale;
-            long long k = poisson_draw(mu, P.key0, P.key1, (uint32_t)l, pin, evg);
+            s_mu[tid] = mu;
+            s_pin[tid] = pin;
+            s_evg[tid] = evg;
+            cls = mu < 10.0 ? 0 : 1;
+            if (cls == 0) s_list[atomicAdd(&s_cnt[0], 1)] = (uint16_t)tid;
+            else s_list[kBlock - 1 - atomicAdd(&s_cnt[1], 1)] = (uint16_t)tid;
+        }
+    }
+    __syncthreads();
+    {
+        const int c0 = s_cnt[0], c1 = s_cnt[1];
+        if (tid < c0 + c1) {
+            const int task = tid < c0 ? s_list[tid] : s_list[kBlock - 1 - (tid - c0)];
+            long long k = poisson_draw(s_mu[task], P.key0, P.key1, (uint32_t)(task % L), s_pin[task],
+                                       s_evg[task]);
             if (k < 1) k = 1;
             if (k > P.cap) k = P.cap;
-            n = (int)k;
+            s_n[task] = (int)k;
         }
+    }
+    __syncthreads();
+    int n = 0;
+    float ehit = 0.0f;
+    if (cls >= 0) n = s_n[tid];
+    if (active && set >= 0) {
         double e_used = el;
         if (G(P.elayer_override)) {
             const float ov = G(P.elayer_override)[t];
@@ -569,51 +601,36 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
 // per task: x = hits, y = chunks of a large task, z = hits of a small task,
 // w = 1 for a small task with hits
 
-// one block: exclusive scan of the block sums (hits, chunks, small hits,
-// small tasks); totals into the counters.  A thread owns `per` consecutive
-// block sums, so the whole scan takes one pass with two barriers.  Hits are
-// summed in 64 bits (more than 2^31 - 1 hits in a batch is an error, found
-// here); the other components are bounded by the task count.
-__global__ __launch_bounds__(1024) void k_scan_top(const Params* __restrict__ Pp)
+// The task scan runs over the setup blocks' sums in two levels.  Groups of
+// kGroupItems block sums are scanned by one 1024-thread block each (loads and
+// stores coalesced, staged through LDS); one block then scans the group
+// totals.  Hits are summed in 64 bits (more than 2^31 - 1 hits in a batch is
+// an error, found in the top pass); the other components are bounded by the
+// task count.
+constexpr int kScanThreads = 1024;
+constexpr int kGroupPer = 2;                              // block sums per thread
+constexpr int kGroupItems = kScanThreads * kGroupPer;     // block sums per group
+
+// exclusive scan over a 1024-thread block of (hits, rest): returns the
+// thread's exclusive prefix and the block totals
+__device__ __forceinline__ void scan1024(long long h, int4 r, long long& ho, int4& ro, long long& htot,
+                                         int4& rtot)
 {
-    const Params& P = *Pp;
-    constexpr int kT = 1024, kW = kT / kWave;
+    constexpr int kW = kScanThreads / kWave;
     __shared__ long long w_hits[kW];
     __shared__ int4 w_rest[kW];
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    const int nb = P.n_scan_blocks;
-    const int per = (nb + kT - 1) / kT;
-    const int b0 = tid * per;
-    const int4* in = reinterpret_cast<const int4*>(P.blk_sums);
-    int4* out = reinterpret_cast<int4*>(P.blk_offs);
-    // block sums read kRun at a time, the loads of a run in flight together
-    constexpr int kRun = 8;
-    int4 vv[kRun];
-    long long h = 0;
-    int c = 0, sh = 0, st = 0;
-    for (int c0 = 0; c0 < per; c0 += kRun) {
-#pragma unroll
-        for (int k = 0; k < kRun; ++k) {
-            const int b = b0 + c0 + k;
-            vv[k] = (c0 + k < per && b < nb) ? load_i4(in, b) : make_int4(0, 0, 0, 0);
-        }
-#pragma unroll
-        for (int k = 0; k < kRun; ++k) {
-            h += vv[k].x;
-            c += vv[k].y;
-            sh += vv[k].z;
-            st += vv[k].w;
-        }
-    }
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
     const long long hi = wave_incl_scan<long long>(h);
-    const int4 ri = wave_incl_scan4(make_int4(0, c, sh, st));
+    const int4 ri = wave_incl_scan4(r);
     if (lane == kWave - 1) {
         w_hits[wave] = hi;
         w_rest[wave] = ri;
     }
     __syncthreads();
-    long long ho = hi - h, htot = 0;
-    int4 ro = make_int4(0, ri.y - c, ri.z - sh, ri.w - st), rtot = make_int4(0, 0, 0, 0);
+    ho = hi - h;
+    ro = sub4(ri, r);
+    htot = 0;
+    rtot = make_int4(0, 0, 0, 0);
     for (int w = 0; w < kW; ++w) {
         const long long wh = w_hits[w];
         const int4 wr = w_rest[w];
@@ -624,22 +641,15 @@ __global__ __launch_bounds__(1024) void k_scan_top(const Params* __restrict__ Pp
         htot += wh;
         rtot = add4(rtot, wr);
     }
-    for (int c0 = 0; c0 < per; c0 += kRun) {
-        if (per > kRun) {
-#pragma unroll
-            for (int k = 0; k < kRun; ++k) {
-                const int b = b0 + c0 + k;
-                vv[k] = (c0 + k < per && b < nb) ? load_i4(in, b) : make_int4(0, 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kRun; ++k) {
-            const int b = b0 + c0 + k;
-            if (c0 + k < per && b < nb) store_i4(out, b, make_int4((int)ho, ro.y, ro.z, ro.w));
-            ho += vv[k].x;
-            ro = add4(ro, vv[k]);
-        }
-    }
+    __syncthreads();
+}
+
+// batch totals of the task scan into the counters (errors for too many hits
+// or too many chunks) and the work-queue tickets reset; called by every
+// thread of the block that finishes the scan
+__device__ __forceinline__ void scan_totals(const Params& P, long long htot, int4 rtot)
+{
+    const int tid = threadIdx.x;
     if (tid < 2 * kQueues) G(P.queue)[tid * kQueueStride] = 0;
     if (tid == 0) {
         auto cc = G(P.ctr);
@@ -659,6 +669,95 @@ __global__ __launch_bounds__(1024) void k_scan_top(const Params* __restrict__ Pp
     }
 }
 
+// one block per group: exclusive prefixes of the group's block sums (hits
+// in 32 bits, valid whenever the batch total is) and the group's totals;
+// with a single group it also finishes the scan
+__global__ __launch_bounds__(kScanThreads) void k_scan_group(const Params* __restrict__ Pp)
+{
+    const Params& P = *Pp;
+    __shared__ int4 s_v[kGroupItems];
+    const int tid = threadIdx.x;
+    const long long base = (long long)blockIdx.x * kGroupItems;
+    const long long nb = P.n_scan_blocks;
+    const int4* in = reinterpret_cast<const int4*>(P.blk_sums);
+    int4* out = reinterpret_cast<int4*>(P.blk_offs);
+#pragma unroll
+    for (int k = 0; k < kGroupPer; ++k) {
+        const long long b = base + k * kScanThreads + tid;
+        s_v[k * kScanThreads + tid] = b < nb ? load_i4(in, b) : make_int4(0, 0, 0, 0);
+    }
+    __syncthreads();
+    int4 v[kGroupPer];
+    long long h = 0;
+    int4 r = make_int4(0, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < kGroupPer; ++k) {
+        v[k] = s_v[tid * kGroupPer + k];
+        h += v[k].x;
+        r = add4(r, make_int4(0, v[k].y, v[k].z, v[k].w));
+    }
+    long long ho, htot;
+    int4 ro, rtot;
+    scan1024(h, r, ho, ro, htot, rtot);
+#pragma unroll
+    for (int k = 0; k < kGroupPer; ++k) {
+        s_v[tid * kGroupPer + k] = make_int4((int)ho, ro.y, ro.z, ro.w);
+        ho += v[k].x;
+        ro = add4(ro, make_int4(0, v[k].y, v[k].z, v[k].w));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kGroupPer; ++k) {
+        const long long b = base + k * kScanThreads + tid;
+        if (b < nb) store_i4(out, b, s_v[k * kScanThreads + tid]);
+    }
+    if (tid == 0) {
+        G(P.grp_hits)[blockIdx.x] = htot;
+        store_i4(reinterpret_cast<int4*>(P.grp_rest), blockIdx.x, rtot);
+    }
+    // a batch of one group needs no top pass
+    if (P.n_scan_groups == 1) {
+        if (tid == 0) store_i4(reinterpret_cast<int4*>(P.grp_offs), 0, make_int4(0, 0, 0, 0));
+        scan_totals(P, htot, rtot);
+    }
+}
+
+// one block: exclusive scan of the group totals into the group offsets;
+// batch totals into the counters, work-queue tickets reset
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(const Params* __restrict__ Pp)
+{
+    const Params& P = *Pp;
+    const int tid = threadIdx.x;
+    const int ng = P.n_scan_groups;
+    const int per = (ng + kScanThreads - 1) / kScanThreads;
+    const int g0 = tid * per;
+    const int4* rest = reinterpret_cast<const int4*>(P.grp_rest);
+    int4* out = reinterpret_cast<int4*>(P.grp_offs);
+    long long h = 0;
+    int4 r = make_int4(0, 0, 0, 0);
+    for (int k = 0; k < per; ++k) {
+        const int g = g0 + k;
+        if (g < ng) {
+            h += G(P.grp_hits)[g];
+            const int4 q = load_i4(rest, g);
+            r = add4(r, make_int4(0, q.y, q.z, q.w));
+        }
+    }
+    long long ho, htot;
+    int4 ro, rtot;
+    scan1024(h, r, ho, ro, htot, rtot);
+    for (int k = 0; k < per; ++k) {
+        const int g = g0 + k;
+        if (g < ng) {
+            store_i4(out, g, make_int4((int)ho, ro.y, ro.z, ro.w));
+            ho += G(P.grp_hits)[g];
+            const int4 q = load_i4(rest, g);
+            ro = add4(ro, make_int4(0, q.y, q.z, q.w));
+        }
+    }
+    scan_totals(P, htot, rtot);
+}
+
 // one thread per task, over the setup blocks (particles kBlock / L at a
 // time): the task's place in the hit list, its chunks, its small-task
 // records and the first task of every tile it opens
@@ -674,8 +773,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_write(const Params* __restrict_
     const int n = active ? G(P.task_n)[t] : 0;
     const int4 d = task_terms(P, n);
     int4 tot;
-    const int4 run = add4(block_excl_scan4(d, tot),
-                          load_i4(reinterpret_cast<const int4*>(P.blk_offs), blockIdx.x));
+    const int4 run = add4(add4(block_excl_scan4(d, tot),
+                               load_i4(reinterpret_cast<const int4*>(P.blk_offs), blockIdx.x)),
+                          load_i4(reinterpret_cast<const int4*>(P.grp_offs), blockIdx.x / kGroupItems));
     if (!active) return;
     if (P.want_hits) G(P.task_hoff)[t] = run.x;
     if (G(P.out_task_hoff)) G(P.out_task_hoff)[t] = P.hit_base + run.x;

@@ -219,6 +219,7 @@ __device__ __noinline__ long long poisson_draw(double mu, uint32_t k0, uint32_t 
     const double a = -0.059 + 0.02483 * b;
     const double invalpha = 1.1239 + 1.1328 / (b - 3.4);
     const double vr = 0.9277 - 3.6224 / (b - 2.0);
+    const double log_ia = dlog(invalpha);
     for (uint32_t j = 0; j < 32; ++j) {
         const U4 x = philox4x32_10(j, layer | (kTagPoisson << 8), part, ev, k0, k1);
         for (int h = 0; h < 2; ++h) {
@@ -230,7 +231,7 @@ __device__ __noinline__ long long poisson_draw(double mu, uint32_t k0, uint32_t 
             const double kd = floor((((2.0 * a) / us + b) * U + mu) + 0.43);
             if (us >= 0.07 && V <= vr) return (long long)kd;
             if (kd < 0.0 || (us < 0.013 && V > us)) continue;
-            const double lhs = (dlog(V) + dlog(invalpha)) - dlog(a / (us * us) + b);
+            const double lhs = (dlog(V) + log_ia) - dlog(a / (us * us) + b);
             const double rhs = (-mu + kd * loglam) - dlnfact((long long)kd);
             if (lhs <= rhs) return (long long)kd;
         }

@@ -78,7 +78,7 @@ struct fcs_ctx {
 
     // workspace
     DevBuf w_particles, w_evoff, w_override, w_task_n, w_task_ehit, w_part_ev, w_part_p,
-        w_part_set, w_blk_sums, w_blk_offs, w_task_hoff, w_chunks, w_small_rec,
+        w_part_set, w_blk_sums, w_blk_offs, w_grp, w_task_hoff, w_chunks, w_small_rec,
         w_tile_first, w_cells, w_flags, w_seg_cnt, w_seg_off, w_seg_blk, w_blk_list, w_queue, w_params,
         w_acc_el, w_acc_bins, w_hist_mark;
     long long cells_events = 0;  // events the accumulator holds (kept zero)
@@ -292,7 +292,7 @@ void fcs_destroy(fcs_ctx* c)
                       &c->p_e_edges, &c->p_eta_edges, &c->p_alpha, &c->p_weights, &c->p_cum,
                       &c->p_guide, &c->w_particles, &c->w_evoff, &c->w_override, &c->w_task_n,
                       &c->w_task_ehit, &c->w_part_ev, &c->w_part_p, &c->w_part_set,
-                      &c->w_blk_sums, &c->w_blk_offs, &c->w_task_hoff, &c->w_chunks,
+                      &c->w_blk_sums, &c->w_blk_offs, &c->w_grp, &c->w_task_hoff, &c->w_chunks,
                       &c->w_small_rec, &c->w_tile_first, &c->w_cells, &c->g_layers, &c->g_regions,
                       &c->w_flags, &c->w_seg_cnt, &c->w_seg_off, &c->w_seg_blk, &c->w_blk_list, &c->w_queue,
                       &c->w_params, &c->w_acc_el, &c->w_acc_bins, &c->w_hist_mark, &c->o_cells, &c->o_ids,
@@ -571,6 +571,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
                     (long long)sh.n_events, 0xffffffffLL >> blk_shift);
     // the task scan runs over the setup blocks (kBlock / L particles each)
     const long long nsb = (N + fcsk::kBlock / L - 1) / (fcsk::kBlock / L);
+    const long long nsg = (nsb + fcsk::kGroupItems - 1) / fcsk::kGroupItems;
     const long long nseg = E * n_seg;
     const long long nsegb = (nseg + fcsk::kScanBlock - 1) / fcsk::kScanBlock;
     if (c->chunk_cap < nt + 1024) c->chunk_cap = nt + 1024;
@@ -584,7 +585,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     if ((rc = ensure(c, c->w_task_n, nt * 4)) || (rc = ensure(c, c->w_task_ehit, nt * 4)) ||
         (rc = ensure(c, c->w_part_ev, N * 4)) || (rc = ensure(c, c->w_part_p, N * 4)) ||
         (rc = ensure(c, c->w_part_set, N * 4)) || (rc = ensure(c, c->w_blk_sums, nsb * 16)) ||
-        (rc = ensure(c, c->w_blk_offs, nsb * 16)) ||
+        (rc = ensure(c, c->w_blk_offs, nsb * 16)) || (rc = ensure(c, c->w_grp, nsg * 40)) ||
         (rc = ensure(c, c->w_task_hoff, want_hits ? nt * 4 : 4)) ||
         (rc = ensure(c, c->w_chunks, (size_t)c->chunk_cap * 16)) ||
         (rc = ensure(c, c->w_small_rec, (size_t)nt * 32)) ||
@@ -657,6 +658,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->clean_cells = dense_out ? 0 : 1;
     P->chunk_cap = (int)std::min<long long>(c->chunk_cap, 2147483647LL);
     P->n_scan_blocks = (int)nsb;
+    P->n_scan_groups = (int)nsg;
     P->n_seg_blocks = (int)nsegb;
     P->task_n = (int32_t*)c->w_task_n.p;
     P->task_ehit = (float*)c->w_task_ehit.p;
@@ -665,6 +667,10 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->part_set = (int32_t*)c->w_part_set.p;
     P->blk_sums = (int32_t*)c->w_blk_sums.p;
     P->blk_offs = (int32_t*)c->w_blk_offs.p;
+    // group records: rest and offsets (16 bytes each, aligned), then hits
+    P->grp_rest = (int32_t*)c->w_grp.p;
+    P->grp_offs = (int32_t*)((char*)c->w_grp.p + nsg * 16);
+    P->grp_hits = (long long*)((char*)c->w_grp.p + nsg * 32);
     P->task_hoff = (int32_t*)c->w_task_hoff.p;
     P->chunks = (int4*)c->w_chunks.p;
     P->small_rec = (int4*)c->w_small_rec.p;
@@ -725,7 +731,9 @@ void enqueue_batch(fcs_ctx* c, const Params& P, int mode, bool validate, int gri
         const int ppb = fcsk::kBlock / P.n_layers;
         hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(P.n_particles, ppb)), dim3(fcsk::kBlock), 0,
                            s, dP);
-        hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_scan_group, dim3(P.n_scan_groups), dim3(fcsk::kScanThreads), 0, s, dP);
+        if (P.n_scan_groups > 1)
+            hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(fcsk::kScanThreads), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
     }
     if (part == kAll || part == kHits)
@@ -1258,7 +1266,9 @@ int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* ev
                            dim3(256), 0, c->stream, dP);
     hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(in.N, fcsk::kBlock / c->n_layers)), dim3(fcsk::kBlock),
                        0, c->stream, dP);
-    hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, c->stream, dP);
+    hipLaunchKernelGGL(fcsk::k_scan_group, dim3(P->n_scan_groups), dim3(fcsk::kScanThreads), 0, c->stream, dP);
+    if (P->n_scan_groups > 1)
+        hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(fcsk::kScanThreads), 0, c->stream, dP);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
                              hipMemcpyDeviceToHost, c->stream));
@@ -1326,7 +1336,9 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
                                dim3(256), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(in.N, fcsk::kBlock / c->n_layers)),
                            dim3(fcsk::kBlock), 0, s, dP);
-        hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(1024), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_scan_group, dim3(P->n_scan_groups), dim3(fcsk::kScanThreads), 0, s, dP);
+        if (P->n_scan_groups > 1)
+            hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(fcsk::kScanThreads), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_adjoint, dim3(c->n_cu * tu.wg_per_cu), dim3(fcsk::kBlock),
                            geo_lds_bytes(*P), s, dP);
