@@ -61,17 +61,18 @@ def kernel_source_hash():
 
 def measured_traffic(workload, tuning):
     """HBM bytes per launch of the hit kernel from the committed counter
-    summary, if it was taken on the current kernel sources, this workload and
-    this tuning; else None."""
+    summaries: the entry taken on the current kernel sources, this workload
+    and this tuning, if there is one; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            entries = json.load(f).get("entries", [])
+    except (OSError, ValueError, AttributeError):
         return None
-    if (t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload
-            or t.get("tuning") != tuning):
-        return None
-    return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
+    h = kernel_source_hash()
+    for t in entries:
+        if t.get("source_hash") == h and t.get("workload") == workload and t.get("tuning") == tuning:
+            return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
+    return None
 
 
 def _sync(torch):
