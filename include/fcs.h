@@ -321,7 +321,11 @@ int fcs_query_sizes(fcs_ctx *ctx, const fcs_particle *particles,
  * grad_elayer is f32 [N * n_layers], grad_weights f32 [n_histograms * 256]
  * and 16-byte aligned; both are device pointers (either may be NULL).
  * Inputs follow opt->inputs_on_device.  Synchronous like
- * fcs_simulate_events.  The context keeps FP64 accumulators for these sums
+ * fcs_simulate_events, unless opt->async_launch (device inputs and
+ * opt->n_particles required): then the call returns once its work is
+ * enqueued, opt->stream (if set) waits for the gradients, and errors are
+ * reported by the next fcs_synchronize (adjoint calls are not counted in its
+ * statistics).  The context keeps FP64 accumulators for these sums
  * (8 bytes per task and per histogram bin), zeroed when allocated and
  * cleared again by each call.
  * ------------------------------------------------------------------------ */

@@ -14,6 +14,11 @@ cell are held fixed (they are recomputed from their Philox counters), so
 `load_parametrization` (f32 [n_histograms * 256]); it carries the gradient and
 its values are not read by the forward pass.  Both passes run in the HIP
 library; this module only marshals arguments.
+
+With `async_launch=True` both passes return once their work is enqueued on
+the library's stream (torch's current stream waits for their outputs), so
+consecutive training steps need no host round trip; errors are then raised
+by `sim.synchronize()`.
 """
 from __future__ import annotations
 
@@ -37,7 +42,8 @@ class _SimulateDense(torch.autograd.Function):
         if not (need_e or need_w):
             return (None,) * 7
         bkw = {k: v for k, v in ctx.kw.items()
-               if k in ("event_index_base", "hit_energy_scale", "nhit_cap", "min_layer_energy")}
+               if k in ("event_index_base", "hit_energy_scale", "nhit_cap", "min_layer_energy",
+                        "async_launch")}
         ge, gw = ctx.sim.backward(ctx.particles, ctx.event_offsets, ctx.seed,
                                   grad_cells.reshape(-1), elayer_override=elayer.detach(),
                                   need_elayer=need_e, need_weights=need_w, **bkw)
@@ -55,7 +61,8 @@ def simulate_dense(sim, particles, event_offsets, seed, elayer, weights=None, **
     """Dense cell energies [n_events, n_cells] (device f32) as a differentiable
     function of `elayer` (and of `weights`, when given).  `particles` and
     `event_offsets` must be device tensors; `kw` takes event_index_base,
-    hit_energy_scale, nhit_cap, min_layer_energy and the launch tuning."""
+    hit_energy_scale, nhit_cap, min_layer_energy, async_launch and the launch
+    tuning."""
     if not (torch.is_tensor(elayer) and elayer.is_cuda and elayer.dtype == torch.float32):
         raise TypeError("elayer must be a float32 CUDA tensor")
     if weights is None:

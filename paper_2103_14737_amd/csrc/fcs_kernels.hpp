@@ -1369,7 +1369,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
 // ---------------------------------------------------- asynchronous calls ---
 // one thread: fold the call's counters and capacity checks into the
 // context's running totals (stream order serializes the calls)
-__global__ void k_async_tail(const Params* __restrict__ Pp, AsyncAcc* __restrict__ acc)
+__global__ void k_async_tail(const Params* __restrict__ Pp, AsyncAcc* __restrict__ acc, int count_call)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const Params& P = *Pp;
@@ -1378,10 +1378,12 @@ __global__ void k_async_tail(const Params* __restrict__ Pp, AsyncAcc* __restrict
     if (G(P.out_ids) && c->nnz_total > P.out_cap) err |= kErrCellCap;
     if (P.want_hits && c->hits_total > P.hit_cap) err |= kErrHitCap;
     const auto a = G(acc);
-    a->n_calls += 1;
-    a->hits += c->hits_total;
-    a->hits_out += c->hits_out;
-    a->nnz += c->nnz_total;
+    if (count_call) {  // simulation calls; adjoint calls fold their errors only
+        a->n_calls += 1;
+        a->hits += c->hits_total;
+        a->hits_out += c->hits_out;
+        a->nnz += c->nnz_total;
+    }
     a->error |= err;
 }
 

@@ -858,7 +858,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         }
         if (async) {
             hipLaunchKernelGGL(fcsk::k_async_tail, dim3(1), dim3(64), 0, c->stream,
-                               (const Params*)c->w_params.p, (fcsk::AsyncAcc*)c->w_async.p);
+                               (const Params*)c->w_params.p, (fcsk::AsyncAcc*)c->w_async.p, 1);
             HIPCHK(c, hipGetLastError());
             return FCS_OK;
         }
@@ -1292,11 +1292,22 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
     Tuning tu;
     int rc = o ? check_tuning(c, o, &tu) : fail(c, FCS_E_INVALID_ARG, "options are NULL");
     if (rc) return rc;
+    const bool async = o->async_launch != 0;
+    if (async && (!o->inputs_on_device || o->n_particles <= 0))
+        return fail(c, FCS_E_INVALID_ARG, "async_launch needs device inputs and n_particles");
     Inputs in;
     if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, false, &in))) return rc;
     const long long nt = in.N * c->n_layers;
+    // an asynchronous call returns once enqueued; the caller's stream waits
+    // for its gradients, errors are reported by fcs_synchronize
+    auto finish_async = [&]() -> int {
+        HIPCHK(c, hipEventRecord(c->ev_done, c->stream));
+        if (o->stream) HIPCHK(c, hipStreamWaitEvent((hipStream_t)o->stream, c->ev_done, 0));
+        return FCS_OK;
+    };
     if (in.N == 0) {
         if (grad_weights) HIPCHK(c, hipMemsetAsync(grad_weights, 0, (size_t)c->n_hist * 256 * 4, c->stream));
+        if (async) return finish_async();
         HIPCHK(c, hipStreamSynchronize(c->stream));
         return FCS_OK;
     }
@@ -1318,7 +1329,7 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         Counters* hc = (Counters*)(blk + kCtrOffset);
         Shape sh{in.N, 0, n_events, 0, 0, 0};
         if ((rc = prepare(c, o, tu, sh, in.d_particles, in.d_evoff, in.d_override, nullptr, nullptr,
-                          false, false, P)))
+                          false, async, P)))
             return rc;
         P->grad_cells = grad_cells;
         P->acc_elayer = (double*)c->w_acc_el.p;
@@ -1349,6 +1360,12 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
                            dim3(grid_for(std::min<long long>(c->n_hist, (long long)c->n_cu * 32),
                                          fcsk::kBlock / fcsk::kWave)),
                            dim3(fcsk::kBlock), 0, s, dP);
+        if (async) {
+            hipLaunchKernelGGL(fcsk::k_async_tail, dim3(1), dim3(64), 0, s, dP,
+                               (fcsk::AsyncAcc*)c->w_async.p, 0);
+            HIPCHK(c, hipGetLastError());
+            return finish_async();
+        }
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
                                  hipMemcpyDeviceToHost, s));

@@ -375,17 +375,20 @@ class Simulator:
     def backward(self, particles, event_offsets, seed, grad_cells, *, event_index_base=0,
                  hit_energy_scale=100.0, nhit_cap=20000, min_layer_energy=1e-6,
                  elayer_override=None, grad_elayer=None, grad_weights=None, chunk_hits=0,
-                 big_task_hits=0, tile_hits=0, wg_per_cu=0, need_elayer=True, need_weights=True):
+                 big_task_hits=0, tile_hits=0, wg_per_cu=0, need_elayer=True, need_weights=True,
+                 async_launch=False):
         """fcs_backward on device tensors: returns (grad_elayer [N*L],
         grad_weights [n_hist*256]) as torch CUDA float32 tensors; a gradient
-        with need_* False is not computed and returned as None."""
+        with need_* False is not computed and returned as None.  With
+        async_launch the call returns once enqueued (torch's current stream
+        waits for the gradients); errors are raised by synchronize()."""
         import torch
         p, off, ov, dev, stream, n_events = self._inputs(particles, event_offsets, elayer_override)
         assert dev and _is_torch(grad_cells) and grad_cells.is_cuda
         N = int(p.shape[0])
         o = self._options(seed, event_index_base, "batched", (), hit_energy_scale, nhit_cap,
                           min_layer_energy, chunk_hits, big_task_hits, tile_hits, wg_per_cu,
-                          False, dev, ov, stream, n_particles=N)
+                          False, dev, ov, stream, n_particles=N, async_launch=async_launch)
         g = grad_cells.contiguous().float()
         if not need_elayer:
             grad_elayer = None

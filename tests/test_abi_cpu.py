@@ -179,3 +179,20 @@ def test_async_argument_checks(F, dry):
     off = np.ascontiguousarray(w.event_offsets)
     rc = F.lib().fcs_simulate_events(dry._h, p.ctypes.data, off.ctypes.data, 5, C.byref(o), C.byref(so))
     assert rc == F.FCS_E_INVALID_ARG
+
+
+def test_async_backward_argument_checks(F, dry):
+    import ctypes as C
+    dry.load_geometry(W.make_geometry())
+    dry.load_parametrization(W.make_param())
+    w = W.single_particle_sweep(n_events=5)
+    o = F.FcsSimOptions()
+    F.lib().fcs_default_options(C.byref(o))
+    o.async_launch = 1  # host inputs: refused before any device work
+    p = np.ascontiguousarray(w.particles)
+    off = np.ascontiguousarray(w.event_offsets)
+    g = np.zeros(5 * 191338, np.float32)
+    rc = F.lib().fcs_backward(dry._h, p.ctypes.data, off.ctypes.data, 5, C.byref(o), g.ctypes.data,
+                              None, None)
+    assert rc == F.FCS_E_INVALID_ARG
+    assert "async_launch" in F.lib().fcs_last_error(dry._h).decode()
