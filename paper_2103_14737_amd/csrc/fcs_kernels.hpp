@@ -850,7 +850,8 @@ __device__ __forceinline__ int lookup_cell(const GeoLds& g, const LayerRec& lr, 
     int ip = (int)floorf((phi - f_of(f.z)) * f_of(f.w));
     ie = min(max(ie, 0), iv.x - 1);
     ip = min(max(ip, 0), iv.y - 1);
-    return iv.z + ie * iv.y + ip;
+    // 0 <= ie * nphi < n_cells <= 2^28: a full-rate 24-bit multiply
+    return iv.z + (int)__umul24((unsigned)ie, (unsigned)iv.y) + ip;
 }
 
 // stage the geometry tables into LDS (call with every thread, then sync)
@@ -866,12 +867,21 @@ __device__ __forceinline__ GeoLds stage_geometry(const Params& P, v4i* s_geo)
 }
 
 // first bin with cum > u; the guide narrows the search to [g[j], g[j+1]]
-template <typename CumT, typename GuideT>
+// (g[kGuide] = kBins - 1).  kPadded: the guide holds that last entry, as
+// the per-wave LDS copies do; else both reads stay inside the histogram's
+// kGuide entries and the last one is selected.
+template <bool kPadded, typename CumT, typename GuideT>
 __device__ __forceinline__ int find_bin(CumT cum, GuideT guide, uint32_t x0, float u)
 {
     const int j = (int)(x0 >> 22);  // u0 = (x0 >> 8) 2^-24 lies in [j, j+1) / kGuide
     int lo = guide[j];
-    int hi = j < kGuide - 1 ? (int)guide[j + 1] : kBins - 1;
+    int hi;
+    if constexpr (kPadded) {
+        hi = guide[j + 1];
+    } else {
+        const int g1 = guide[j < kGuide - 1 ? j + 1 : j];
+        hi = j < kGuide - 1 ? g1 : kBins - 1;
+    }
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (cum[mid] > u) hi = mid;
@@ -887,18 +897,20 @@ struct HitOut {
 
 // one hit: counter (i, layer | 3 << 8, particle in event, global event)
 // -> three 24-bit uniforms -> (r, alpha) bin -> position in the bin ->
-// (eta, phi) -> cell
-template <typename CumT, typename GuideT>
+// (eta, phi) -> cell.  kTask: the wave's hits belong to one task (layer,
+// particle and event uniform; padded guide in LDS).
+template <bool kTask, typename CumT, typename GuideT>
 __device__ __forceinline__ HitOut simulate_hit(const GeoLds& g, const LayerRec& lr, CumT cum,
                                                GuideT guide, float dr, uint32_t k0, uint32_t k1,
                                                uint32_t i, uint32_t l, uint32_t pin, uint32_t evg,
                                                float eta_p, float phi_p)
 {
     const float inv_r = f_of(lr.a.z);
-    const U4 x = philox4x32_10(i, l | (kTagHit << 8), pin, evg, k0, k1);
+    const U4 x = kTask ? philox4x32_10_uniform_ctr(i, l | (kTagHit << 8), pin, evg, k0, k1)
+                       : philox4x32_10(i, l | (kTagHit << 8), pin, evg, k0, k1);
     const float u0 = unit24(x.x), u1 = unit24(x.y), u2 = unit24(x.z);
     HitOut h;
-    h.bin = find_bin(cum, guide, x.x, u0);
+    h.bin = find_bin<kTask>(cum, guide, x.x, u0);
     const int ir = h.bin >> 3, ia = h.bin & 7;
     const float r = __builtin_fmaf(u1, dr, (float)ir * dr);  // lower edge + u1 * dr, one rounding
     float c, s;
@@ -1235,7 +1247,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     __shared__ uint32_t w_key[kWavesPerBlock][kWaveSlots];
     __shared__ uint32_t w_cnt2[kWavesPerBlock][kWaveSlots / 2];
     __shared__ float w_cum[kWavesPerBlock][kBins];
-    __shared__ v4i w_guide16[kWavesPerBlock][kGuide / 16];
+    __shared__ v4i w_guide16[kWavesPerBlock][kGuide / 16 + 1];  // + the pad entry
 
     const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
@@ -1261,6 +1273,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     const GeoLds geo = stage_geometry(P, s_geo);
     for (int s = lane; s < kWaveSlots; s += kWave) hkey[s] = kEmpty;
     for (int s = lane; s < kWaveSlots / 2; s += kWave) hcnt2[s] = 0;
+    if (lane == 0) reinterpret_cast<uint8_t*>(w_guide16[wv])[kGuide] = kBins - 1;  // the pad entry
     __syncthreads();
 
     WaveQueue queue = make_queue(n_items, active_wg);
@@ -1278,7 +1291,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
             const int hbits = hash_bits(ck.count);
             const long long hbase = P.want_hits ? (long long)G(P.task_hoff)[ck.t] : 0;
             for (int i = ck.first + lane; i < ck.first + ck.count; i += kWave) {
-                const HitOut h = simulate_hit(geo, lrec, cum, guide, dr, k0, k1, (uint32_t)i,
+                const HitOut h = simulate_hit<true>(geo, lrec, cum, guide, dr, k0, k1, (uint32_t)i,
                                               (uint32_t)ck.l, ck.pin, ck.evg, ck.eta_p, ck.phi_p);
                 if (P.want_hits) write_hit(P, hbase + i, h, ck.ehit);
                 n_out += h.cell < 0 ? 1 : 0;
@@ -1312,7 +1325,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                 const bool valid = k < hcount;
                 const int kk = valid ? k : hcount - 1;
                 const SmallHit sh = small_hit(P, s0 + owners[kk], h0 + kk);
-                const HitOut h = simulate_hit(geo, layer_rec(geo, sh.l),
+                const HitOut h = simulate_hit<false>(geo, layer_rec(geo, sh.l),
                                               G(P.cum) + (long long)sh.H * kBins,
                                               G(P.guide) + (long long)sh.H * kGuide, dr, k0, k1,
                                               (uint32_t)sh.i, (uint32_t)sh.l, sh.pin, sh.evg,
@@ -1647,7 +1660,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
     extern __shared__ v4i s_geo[];
     __shared__ double w_bin[kWavesPerBlock][kBins];
     __shared__ float w_cum[kWavesPerBlock][kBins];
-    __shared__ v4i w_guide16[kWavesPerBlock][kGuide / 16];
+    __shared__ v4i w_guide16[kWavesPerBlock][kGuide / 16 + 1];  // + the pad entry
 
     const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
@@ -1666,6 +1679,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
     const uint32_t k0 = P.key0, k1 = P.key1;
     const GeoLds geo = stage_geometry(P, s_geo);
     for (int b = lane; b < kBins; b += kWave) bins[b] = 0.0;
+    if (lane == 0) reinterpret_cast<uint8_t*>(w_guide16[wv])[kGuide] = kBins - 1;  // the pad entry
     __syncthreads();
 
     WaveQueue queue = make_queue(n_items, active_wg);
@@ -1681,7 +1695,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
             const auto g = G(P.grad_cells) + (long long)ck.ev * C;
             double gsum = 0.0;
             for (int i = ck.first + lane; i < ck.first + ck.count; i += kWave) {
-                const HitOut h = simulate_hit(geo, lrec, cum, guide, dr, k0, k1, (uint32_t)i,
+                const HitOut h = simulate_hit<true>(geo, lrec, cum, guide, dr, k0, k1, (uint32_t)i,
                                               (uint32_t)ck.l, ck.pin, ck.evg, ck.eta_p, ck.phi_p);
                 if (h.cell < 0) continue;
                 const double gc = (double)g[h.cell];
@@ -1705,7 +1719,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
             wave_tile_owners(P, ctr, item - n_chunks, owners, s0, h0, hcount);
             for (int k = lane; k < hcount; k += kWave) {
                 const SmallHit sh = small_hit(P, s0 + owners[k], h0 + k);
-                const HitOut h = simulate_hit(geo, layer_rec(geo, sh.l),
+                const HitOut h = simulate_hit<false>(geo, layer_rec(geo, sh.l),
                                               G(P.cum) + (long long)sh.H * kBins,
                                               G(P.guide) + (long long)sh.H * kGuide, dr, k0, k1,
                                               (uint32_t)sh.i, (uint32_t)sh.l, sh.pin, sh.evg,

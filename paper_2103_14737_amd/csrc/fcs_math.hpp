@@ -43,6 +43,43 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     return U4{c0, c1, c2, c3};
 }
 
+// The same function for counters whose words 1-3 are wave-uniform (the hits
+// of one task): in the first three rounds two of a round's three xor inputs
+// are uniform, and they are combined first so that the scalar unit does that
+// part; xor is associative, so the words are the same.
+__device__ __forceinline__ U4 philox4x32_10_uniform_ctr(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                        uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t pb = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t hi_a = (uint32_t)(pa >> 32), lo_a = (uint32_t)pa;
+        const uint32_t hi_b = (uint32_t)(pb >> 32), lo_b = (uint32_t)pb;
+        uint32_t y0, y2;
+        if (r == 0) {         // c1, c2, c3 uniform: y0 uniform
+            y0 = hi_b ^ (c1 ^ k0);
+            y2 = hi_a ^ (c3 ^ k1);
+        } else if (r == 1) {  // c0, c1 uniform
+            y0 = hi_b ^ (c1 ^ k0);
+            y2 = c3 ^ (hi_a ^ k1);
+        } else if (r == 2) {  // c3 uniform
+            y0 = __builtin_amdgcn_bitop3_b32(hi_b, c1, k0, 0x96);
+            y2 = hi_a ^ (c3 ^ k1);
+        } else {
+            y0 = __builtin_amdgcn_bitop3_b32(hi_b, c1, k0, 0x96);
+            y2 = __builtin_amdgcn_bitop3_b32(hi_a, c3, k1, 0x96);
+        }
+        c0 = y0;
+        c1 = lo_b;
+        c2 = y2;
+        c3 = lo_a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
 // Counter words: (draw index, layer | stream tag << 8, particle in event,
 // global event index).  Stream tags: 1 layer-energy Gamma, 2 hit-count
 // Poisson, 3 per-hit draws.
