@@ -5,15 +5,16 @@
 //   k_setup        per (particle, layer): parametrization set, Dirichlet layer
 //                  energy, Poisson hit count, Ehit (Listing 1); per-block
 //                  sums for the task scan
-//   k_scan_top / k_scan_write
+//   k_scan_group / k_scan_top / k_scan_write
 //                  scans of the task hit counts -> work queue: chunks of
 //                  large tasks, packed tiles of small tasks
 //   k_hits         persistent: pulls work items from a ticket counter; per
 //                  hit Philox draw, inverse-CDF bin, placement, cell lookup,
 //                  deposit (sim_a of the CUDA Implementation section)
-//   k_seg_count / k_seg_reduce / k_seg_top / k_seg_apply / k_seg_list /
-//   k_seg_emit     ordered gather of the hit cells as (cell_id, E) and
-//                  sparse reset of the accumulator (sim_ct and clean)
+//   k_seg_count / k_seg_top / k_seg_list / k_seg_emit
+//                  ordered gather of the hit cells as (cell_id, E) and
+//                  sparse reset of the accumulator (sim_ct and clean);
+//                  k_flags_reset instead for calls with a dense output only
 #pragma once
 
 #include "fcs_math.hpp"
@@ -27,8 +28,7 @@ constexpr int kGuide = 1024;       // guide entries per histogram (top 10 bits o
 constexpr int kChunkMax = 32768;   // hits per chunk (per-cell counts are 16-bit)
 constexpr int kHashProbes = 16;
 constexpr uint32_t kEmpty = 0xffffffffu;
-constexpr int kScanItems = 8;             // items per thread in the segment scans
-constexpr int kScanBlock = kBlock * kScanItems;
+constexpr int kSegPerWave = 8;            // segments counted by one wave
 constexpr int kTileMax = 512;             // max hits of one packed tile (one wave)
 constexpr int kQueues = 8;                // work-queue ranges (one ticket each)
 constexpr int kQueueStride = 64;          // ints between tickets: one 256-byte line each
@@ -121,7 +121,7 @@ struct Params {
     int32_t chunk_cap;
     int32_t n_scan_blocks;
     int32_t n_scan_groups;
-    int32_t n_seg_blocks;
+    int32_t n_seg_groups;  // groups of kSegGroup segments
     // workspace
     int32_t* task_n;
     float* task_ehit;
@@ -141,9 +141,9 @@ struct Params {
     int32_t* tile_first; // [n_tasks + 1]
     float* cells;        // [n_events * n_cells] accumulator
     uint8_t* flags;      // [n_events * n_blk]
-    long long* seg_cnt;  // [n_events * n_seg] (nonzero blocks << 32 | nonzero cells)
-    long long* seg_off;  // [n_events * n_seg] exclusive prefix of seg_cnt
-    long long* seg_blk;  // [n_seg_blocks]
+    long long* seg_off;  // [n_events * n_seg] (nonzero blocks << 32 | nonzero cells) before the
+                         // segment, within its group of kSegGroup
+    long long* seg_blk;  // [n_seg_groups] group totals, then their exclusive prefixes
     unsigned long long* blk_list;  // [n_events * n_seg * kSegBlocks] position << 32 | (event << blk_shift | block)
     Counters* ctr;
     int32_t* queue;      // [kQueues * kQueueStride * 2]: tickets, then drained flags
@@ -1452,35 +1452,52 @@ __device__ __forceinline__ const FCS_AS_GLOBAL v4i* seg_counts(const Params& P, 
     return (const FCS_AS_GLOBAL v4i*)(G(P.flags) + (e << P.blk_shift) + (long long)seg * kSegBlocks);
 }
 
+// Count pass: a workgroup per group of kSegGroup segments, kSegPerWave per
+// wave (their loads in flight together).  Per segment the nonzero cells (low
+// 32 bits) and nonzero blocks (high 32 bits); the segments' exclusive
+// prefixes within the group go to seg_off and the group's total to seg_blk.
+constexpr int kSegGroup = kSegPerWave * kWavesPerBlock;
 __global__ __launch_bounds__(kBlock) void k_seg_count(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
-    const long long gw = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    if (gw >= P.n_events * P.n_seg) return;
-    const long long e = gw / P.n_seg;
-    const int seg = (int)(gw - e * P.n_seg);
-    const v4i w = seg_counts(P, e, seg)[lane_id()];
-    const uint32_t x = (uint32_t)w.x, y = (uint32_t)w.y, z = (uint32_t)w.z, q = (uint32_t)w.w;
-    long long s = (long long)(byte_sum(x) + byte_sum(y) + byte_sum(z) + byte_sum(q)) +
-                  ((long long)(byte_nonzero(x) + byte_nonzero(y) + byte_nonzero(z) + byte_nonzero(q)) << 32);
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
-    if (lane_id() == 0) G(P.seg_cnt)[gw] = s;
-}
-
-__global__ __launch_bounds__(kBlock) void k_seg_reduce(const Params* __restrict__ Pp)
-{
-    const Params& P = *Pp;
+    __shared__ long long s_c[kSegGroup];
     const long long n = P.n_events * P.n_seg;
-    const long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanItems;
-    long long s = 0;
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) s += G(P.seg_cnt)[base + k];
-    long long tot;
-    (void)block_excl_scan_t<long long>(s, tot);
-    if (threadIdx.x == 0) G(P.seg_blk)[blockIdx.x] = tot;
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const long long g0 = (long long)blockIdx.x * kSegGroup;
+    const long long w0 = g0 + wave * kSegPerWave;
+    v4i w[kSegPerWave];
+#pragma unroll
+    for (int k = 0; k < kSegPerWave; ++k) {
+        const long long gw = w0 + k;
+        w[k] = v4i{0, 0, 0, 0};
+        if (gw < n) {
+            const long long e = gw / P.n_seg;
+            w[k] = seg_counts(P, e, (int)(gw - e * P.n_seg))[lane];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kSegPerWave; ++k) {
+        const uint32_t x = (uint32_t)w[k].x, y = (uint32_t)w[k].y, z = (uint32_t)w[k].z,
+                       q = (uint32_t)w[k].w;
+        // at most 65,536 cells and 1,024 blocks per segment: both fit one word
+        uint32_t c = (uint32_t)(byte_sum(x) + byte_sum(y) + byte_sum(z) + byte_sum(q)) +
+                     ((uint32_t)(byte_nonzero(x) + byte_nonzero(y) + byte_nonzero(z) + byte_nonzero(q))
+                      << 17);
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, kWave);
+        if (lane == 0) s_c[wave * kSegPerWave + k] = (long long)(c & 0x1ffffu) + ((long long)(c >> 17) << 32);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        const long long v = lane < kSegGroup ? s_c[lane] : 0;
+        const long long inc = wave_incl_scan<long long>(v);
+        if (lane < kSegGroup && g0 + lane < n) G(P.seg_off)[g0 + lane] = inc - v;
+        if (lane == kSegGroup - 1) G(P.seg_blk)[blockIdx.x] = inc;
+    }
 }
 
+// one block: exclusive scan of the group totals; batch totals (nonzero cells,
+// listed blocks) into the counters
 __global__ __launch_bounds__(1024) void k_seg_top(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
@@ -1489,7 +1506,7 @@ __global__ __launch_bounds__(1024) void k_seg_top(const Params* __restrict__ Pp)
     const int tid = threadIdx.x;
     if (tid == 0) carry = 0;
     __syncthreads();
-    const int nb = P.n_seg_blocks;
+    const int nb = P.n_seg_groups;
     for (int b0 = 0; b0 < nb; b0 += 1024) {
         const int b = b0 + tid;
         const long long v = b < nb ? G(P.seg_blk)[b] : 0;
@@ -1514,25 +1531,6 @@ __global__ __launch_bounds__(1024) void k_seg_top(const Params* __restrict__ Pp)
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_seg_apply(const Params* __restrict__ Pp)
-{
-    const Params& P = *Pp;
-    const long long n = P.n_events * P.n_seg;
-    const long long base = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanItems;
-    long long v[kScanItems];
-    long long s = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < n ? G(P.seg_cnt)[base + k] : 0;
-        s += v[k];
-    }
-    long long tot;
-    long long run = block_excl_scan_t<long long>(s, tot) + G(P.seg_blk)[blockIdx.x];
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) G(P.seg_off)[base + k] = run;
-        run += v[k];
-    }
-}
-
 // list pass: a wave per segment writes an entry per nonzero block (global
 // block id, output position of its first nonzero cell) and resets the counts
 __global__ __launch_bounds__(kBlock) void k_seg_list(const Params* __restrict__ Pp)
@@ -1549,7 +1547,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_list(const Params* __restrict__ 
     const int cells = byte_sum(words[0]) + byte_sum(words[1]) + byte_sum(words[2]) + byte_sum(words[3]);
     const int blocks = byte_nonzero(words[0]) + byte_nonzero(words[1]) + byte_nonzero(words[2]) +
                        byte_nonzero(words[3]);
-    const long long so = G(P.seg_off)[gw];
+    const long long so = G(P.seg_off)[gw] + G(P.seg_blk)[gw / kSegGroup];
     int pos = (int)(so & 0xffffffffLL) + wave_incl_scan(cells) - cells;
     long long at = (so >> 32) + wave_incl_scan(blocks) - blocks;
     if (seg == 0 && lane == 0 && G(P.out_ev_off)) G(P.out_ev_off)[e] = P.out_base + (so & 0xffffffffLL);

@@ -79,7 +79,7 @@ struct fcs_ctx {
     // workspace
     DevBuf w_particles, w_evoff, w_override, w_task_n, w_task_ehit, w_part_ev, w_part_p,
         w_part_set, w_blk_sums, w_blk_offs, w_grp, w_task_hoff, w_chunks, w_small_rec,
-        w_tile_first, w_cells, w_flags, w_seg_cnt, w_seg_off, w_seg_blk, w_blk_list, w_queue, w_params,
+        w_tile_first, w_cells, w_flags, w_seg_off, w_seg_blk, w_blk_list, w_queue, w_params,
         w_acc_el, w_acc_bins, w_hist_mark;
     long long cells_events = 0;  // events the accumulator holds (kept zero)
     long long flag_events = 0;
@@ -294,7 +294,7 @@ void fcs_destroy(fcs_ctx* c)
                       &c->w_task_ehit, &c->w_part_ev, &c->w_part_p, &c->w_part_set,
                       &c->w_blk_sums, &c->w_blk_offs, &c->w_grp, &c->w_task_hoff, &c->w_chunks,
                       &c->w_small_rec, &c->w_tile_first, &c->w_cells, &c->g_layers, &c->g_regions,
-                      &c->w_flags, &c->w_seg_cnt, &c->w_seg_off, &c->w_seg_blk, &c->w_blk_list, &c->w_queue,
+                      &c->w_flags, &c->w_seg_off, &c->w_seg_blk, &c->w_blk_list, &c->w_queue,
                       &c->w_params, &c->w_acc_el, &c->w_acc_bins, &c->w_hist_mark, &c->o_cells, &c->o_ids,
                       &c->o_e, &c->o_evoff, &c->o_heta, &c->o_hphi, &c->o_he, &c->o_hcell,
                       &c->o_thoff, &c->o_counts, &c->o_elayer, &c->w_async};
@@ -573,7 +573,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     const long long nsb = (N + fcsk::kBlock / L - 1) / (fcsk::kBlock / L);
     const long long nsg = (nsb + fcsk::kGroupItems - 1) / fcsk::kGroupItems;
     const long long nseg = E * n_seg;
-    const long long nsegb = (nseg + fcsk::kScanBlock - 1) / fcsk::kScanBlock;
+    const long long nsegb = (nseg + fcsk::kSegGroup - 1) / fcsk::kSegGroup;
     if (c->chunk_cap < nt + 1024) c->chunk_cap = nt + 1024;
     // an asynchronous call cannot retry with a larger chunk list: reserve
     // the most chunks the hit cap allows
@@ -590,7 +590,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
         (rc = ensure(c, c->w_chunks, (size_t)c->chunk_cap * 16)) ||
         (rc = ensure(c, c->w_small_rec, (size_t)nt * 32)) ||
         (rc = ensure(c, c->w_tile_first, (nt + 1) * 4)) ||
-        (rc = ensure(c, c->w_seg_cnt, nseg * 8)) || (rc = ensure(c, c->w_seg_off, nseg * 8)) ||
+        (rc = ensure(c, c->w_seg_off, nseg * 8)) ||
         (rc = ensure(c, c->w_seg_blk, nsegb * 8)) ||
         (rc = ensure(c, c->w_blk_list, (size_t)nseg * fcsk::kSegBlocks * 8)))
         return rc;
@@ -659,7 +659,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->chunk_cap = (int)std::min<long long>(c->chunk_cap, 2147483647LL);
     P->n_scan_blocks = (int)nsb;
     P->n_scan_groups = (int)nsg;
-    P->n_seg_blocks = (int)nsegb;
+    P->n_seg_groups = (int)nsegb;
     P->task_n = (int32_t*)c->w_task_n.p;
     P->task_ehit = (float*)c->w_task_ehit.p;
     P->part_ev = (int32_t*)c->w_part_ev.p;
@@ -679,7 +679,6 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->tile_first = (int32_t*)c->w_tile_first.p;
     P->cells = dense_out ? dense_out : (float*)c->w_cells.p;
     P->flags = (uint8_t*)c->w_flags.p;
-    P->seg_cnt = (long long*)c->w_seg_cnt.p;
     P->seg_off = (long long*)c->w_seg_off.p;
     P->seg_blk = (long long*)c->w_seg_blk.p;
     P->blk_list = (unsigned long long*)c->w_blk_list.p;
@@ -745,10 +744,8 @@ void enqueue_batch(fcs_ctx* c, const Params& P, int mode, bool validate, int gri
                            dim3(fcsk::kBlock), 0, s, dP);
     } else if (part == kAll || part == kPost) {
         const unsigned nw = grid_for(P.n_events * P.n_seg, fcsk::kBlock / fcsk::kWave);
-        hipLaunchKernelGGL(fcsk::k_seg_count, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
-        hipLaunchKernelGGL(fcsk::k_seg_reduce, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_seg_count, dim3(P.n_seg_groups), dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_seg_top, dim3(1), dim3(1024), 0, s, dP);
-        hipLaunchKernelGGL(fcsk::k_seg_apply, dim3(P.n_seg_blocks), dim3(fcsk::kBlock), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_seg_list, dim3(nw), dim3(fcsk::kBlock), 0, s, dP);
         // the emit pass is latency bound: 16 persistent workgroups per CU
         hipLaunchKernelGGL(fcsk::k_seg_emit, dim3(c->n_cu * 16), dim3(fcsk::kBlock), 0, s, dP);
