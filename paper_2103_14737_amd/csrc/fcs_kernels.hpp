@@ -121,6 +121,7 @@ struct Params {
     int32_t chunk_cap;
     int32_t n_scan_blocks;
     int32_t n_scan_groups;
+    int32_t setup_sub;     // scan blocks per setup workgroup
     int32_t n_seg_groups;  // groups of kSegGroup segments
     // workspace
     int32_t* task_n;
@@ -486,8 +487,9 @@ __global__ void k_validate(const Params* __restrict__ Pp)
 }
 
 // ------------------------------------------- per-task setup (a1 - a3) ---
-// One thread per (particle, layer); the particles of a block share their
-// Gamma draws through LDS for the Dirichlet normalization.
+// Per (particle, layer) task: the Gamma draw, the Dirichlet normalization
+// over the particle's layers (in LDS), the Poisson hit count and Ehit.
+//
 // (hits, chunks, small hits, small tasks) of a task with n hits
 __device__ __forceinline__ int4 task_terms(const Params& P, int n)
 {
@@ -496,7 +498,10 @@ __device__ __forceinline__ int4 task_terms(const Params& P, int n)
                      (!big && n > 0) ? 1 : 0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
+// Batches too small to give every CU several workgroups of several scan
+// blocks: one thread per task, one scan block (kBlock / L particles) per
+// workgroup.
+__global__ __launch_bounds__(kBlock) void k_setup_one(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
     __shared__ double g_s[kBlock];
@@ -526,8 +531,15 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
         evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
         set = select_set(P, pt.pdg, pt.e, pt.eta);
         if (set >= 0) {
-            const int t = set / (P.n_ebins * P.n_etabins);
-            g = gamma_draw((double)G(P.alpha)[t * L + l], P.key0, P.key1, (uint32_t)l, pin, evg);
+            const int ty = set / (P.n_ebins * P.n_etabins);
+            const double alpha = (double)G(P.alpha)[ty * L + l];
+            const double a = alpha < 1.0 ? alpha + 1.0 : alpha;
+            const double d = a - 1.0 / 3.0;
+            const double c = 1.0 / sqrt(9.0 * d);
+            uint32_t j = 0, w = 0;
+            while (!gamma_try(d, c, j, P.key0, P.key1, (uint32_t)l, pin, evg, &g, &w) && ++j < 64) {
+            }
+            g = j < 64 ? gamma_boost(g, alpha, w) : d;
         }
     }
     g_s[tid] = g;
@@ -591,10 +603,201 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
         }
     }
     // this block's sums of (hits, chunks, small hits, small tasks) for the
-    // task scan; the scan's blocks are the setup blocks
+    // task scan (one scan block per workgroup)
     int4 tot;
     (void)block_excl_scan4(active ? task_terms(P, n) : make_int4(0, 0, 0, 0), tot);
     if (tid == 0) store_i4(reinterpret_cast<int4*>(P.blk_sums), blockIdx.x, tot);
+}
+
+// A setup workgroup takes `setup_sub` scan blocks of kBlock / L particles
+// (at most kSetupPartCap particles, kSetupTaskCap tasks).  Each lane works
+// through the tasks tid, tid + kBlock, ... one Gamma attempt per step, so a
+// wave waits for its slowest lane's total number of attempts rather than for
+// the slowest draw of every task in turn.
+constexpr int kSetupSubMax = 4;
+constexpr int kSetupTaskCap = kSetupSubMax * kBlock;
+constexpr int kSetupPartCap = kBlock;
+
+// the next task of a lane with a set from t on (tasks of particles without
+// a set get g = 0), and its Gamma constants
+__device__ __forceinline__ void gamma_next(const Params& P, const int* s_set, double* s_g, int L,
+                                           int nt, int& t, double& alpha, double& d, double& c,
+                                           uint32_t& j)
+{
+    while (t < nt && s_set[t / L] < 0) {
+        s_g[t] = 0.0;
+        t += kBlock;
+    }
+    if (t < nt) {
+        const int ty = s_set[t / L] / (P.n_ebins * P.n_etabins);
+        alpha = (double)G(P.alpha)[ty * L + t % L];
+        const double a = alpha < 1.0 ? alpha + 1.0 : alpha;
+        d = a - 1.0 / 3.0;
+        c = 1.0 / sqrt(9.0 * d);
+        j = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
+{
+    const Params& P = *Pp;
+    __shared__ double s_g[kSetupTaskCap];       // Gamma draws, then layer energies
+    __shared__ double s_mu[kSetupTaskCap];      // Poisson means
+    uint32_t* s_w = reinterpret_cast<uint32_t*>(s_mu);  // before them: the boost words
+    __shared__ int s_n[kSetupTaskCap];          // hit counts
+    __shared__ uint16_t s_list[kSetupTaskCap];  // tasks by Poisson branch
+    __shared__ uint32_t s_pin[kSetupPartCap], s_evg[kSetupPartCap];
+    __shared__ int s_set[kSetupPartCap];
+    __shared__ float s_e[kSetupPartCap];
+    __shared__ int s_cnt[2];
+    const int L = P.n_layers;
+    const int ppb = kBlock / L;
+    const int sub = P.setup_sub;
+    const int tid = threadIdx.x;
+    const long long p0 = (long long)blockIdx.x * ppb * sub;
+    const int np = (int)min((long long)(ppb * sub), P.n_particles - p0);
+    const int nt = np * L;
+    // after a failed input check (bad offsets, particles) no task gets hits:
+    // particles outside the offsets must not reach an event index
+    const bool bad = (G(P.ctr)->error & (kErrPdg | kErrParticle | kErrOffsets)) != 0;
+    for (int lp = tid; lp < np; lp += kBlock) {
+        const long long gp = p0 + lp;
+        Particle pt = {0, 0.f, 0.f, 0.f};
+        int set = -1, ev = 0;
+        uint32_t pin = 0, evg = 0;
+        if (!bad) {
+            pt = load_particle(P.particles, gp);
+            ev = find_event(G(P.ev_off), P.n_events, P.part_base + gp);
+            pin = (uint32_t)(P.part_base + gp - G(P.ev_off)[ev]);
+            evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
+            set = select_set(P, pt.pdg, pt.e, pt.eta);
+        }
+        s_set[lp] = set;
+        s_pin[lp] = pin;
+        s_evg[lp] = evg;
+        s_e[lp] = pt.e;
+        G(P.part_ev)[gp] = ev;
+        G(P.part_p)[gp] = pin;
+        G(P.part_set)[gp] = set;
+    }
+    if (tid < 2) s_cnt[tid] = 0;
+    __syncthreads();
+    {
+        int t = tid;
+        double alpha = 0.0, d = 0.0, c = 0.0;
+        uint32_t j = 0;
+        gamma_next(P, s_set, s_g, L, nt, t, alpha, d, c, j);
+        while (__ballot(t < nt) != 0) {
+            if (t < nt) {
+                double g = 0.0;
+                uint32_t w = 0;
+                const int lp = t / L;
+                bool done = gamma_try(d, c, j, P.key0, P.key1, (uint32_t)(t % L), s_pin[lp], s_evg[lp],
+                                      &g, &w);
+                const bool fallback = !done && ++j == 64;
+                if (done || fallback) {
+                    // the boost of alpha < 1 waits for the pass below, so that
+                    // a wave runs it once for all its lanes
+                    s_g[t] = fallback ? d : g;
+                    s_w[t] = w;
+                    s_n[t] = fallback ? 1 : 0;
+                    t += kBlock;
+                    gamma_next(P, s_set, s_g, L, nt, t, alpha, d, c, j);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSetupSubMax; ++k) {
+        const int t = tid + k * kBlock;
+        if (t < nt && s_set[t / L] >= 0 && s_n[t] == 0) {
+            const double alpha = (double)G(P.alpha)[(s_set[t / L] / (P.n_ebins * P.n_etabins)) * L + t % L];
+            s_g[t] = gamma_boost(s_g[t], alpha, s_w[t]);
+        }
+    }
+    __syncthreads();
+    // layer energies (each task sums its particle's draws in layer order);
+    // Poisson draws grouped by sampler branch: inversion tasks (mu < 10)
+    // fill the list from the front, the others from the back
+    double el_t[kSetupSubMax];
+#pragma unroll
+    for (int k = 0; k < kSetupSubMax; ++k) {
+        const int t = tid + k * kBlock;
+        el_t[k] = 0.0;
+        if (t >= nt) continue;
+        const int lp = t / L;
+        if (s_set[lp] >= 0) {
+            double sum = 0.0;
+            for (int q = 0; q < L; ++q) sum = sum + s_g[lp * L + q];
+            const double el = (double)s_e[lp] * (s_g[t] / sum);
+            el_t[k] = el;
+            if (el >= P.min_e && el > 0.0) {
+                const double mu = el / (double)P.scale;
+                s_mu[t] = mu;
+                if (mu < 10.0) s_list[atomicAdd(&s_cnt[0], 1)] = (uint16_t)t;
+                else s_list[kSetupTaskCap - 1 - atomicAdd(&s_cnt[1], 1)] = (uint16_t)t;
+            }
+        }
+        s_n[t] = 0;
+    }
+    __syncthreads();  // every sum has read the draws: they make way for the layer energies
+#pragma unroll
+    for (int k = 0; k < kSetupSubMax; ++k)
+        if (tid + k * kBlock < nt) s_g[tid + k * kBlock] = el_t[k];
+    {
+        const int c0 = s_cnt[0], c1 = s_cnt[1];
+        for (int i = tid; i < c0 + c1; i += kBlock) {
+            const int t = i < c0 ? s_list[i] : s_list[kSetupTaskCap - 1 - (i - c0)];
+            const int lp = t / L;
+            long long k = poisson_draw(s_mu[t], P.key0, P.key1, (uint32_t)(t % L), s_pin[lp], s_evg[lp]);
+            if (k < 1) k = 1;
+            if (k > P.cap) k = P.cap;
+            s_n[t] = (int)k;
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < nt; t += kBlock) {
+        const int lp = t / L, l = t - lp * L;
+        const long long gt = (p0 + lp) * L + l;
+        const int n = s_n[t];
+        const double el = s_g[t];
+        const int set = s_set[lp];
+        float ehit = 0.0f;
+        if (set >= 0) {
+            double e_used = el;
+            if (G(P.elayer_override)) {
+                const float ov = G(P.elayer_override)[gt];
+                if (!(ov >= 0.0f) || !isfinite(ov)) gor(&G(P.ctr)->error, (int)kErrOverride);
+                e_used = ov >= 0.0f ? (double)ov : 0.0;
+            }
+            ehit = n > 0 ? (float)(e_used / (double)n) : 0.0f;
+            if (n > 0 && G(P.hist_mark)) G(P.hist_mark)[set * L + l] = 1;
+        }
+        G(P.task_n)[gt] = n;
+        G(P.task_ehit)[gt] = ehit;
+        if (G(P.out_elayer)) G(P.out_elayer)[gt] = (float)el;
+        if (G(P.out_counts)) G(P.out_counts)[gt] = n;
+    }
+    // the task scan's sums of (hits, chunks, small hits, small tasks), one
+    // wave per scan block of this workgroup
+    const int lane = lane_id();
+    for (int sb = tid / kWave; sb < sub; sb += kBlock / kWave) {
+        int4 acc = make_int4(0, 0, 0, 0);
+        for (int q = lane; q < ppb * L; q += kWave) {
+            const int t = sb * ppb * L + q;
+            if (t < nt) acc = add4(acc, task_terms(P, s_n[t]));
+        }
+#pragma unroll
+        for (int dd = kWave / 2; dd > 0; dd >>= 1) {
+            acc.x += __shfl_xor(acc.x, dd, kWave);
+            acc.y += __shfl_xor(acc.y, dd, kWave);
+            acc.z += __shfl_xor(acc.z, dd, kWave);
+            acc.w += __shfl_xor(acc.w, dd, kWave);
+        }
+        const long long b = (long long)blockIdx.x * sub + sb;
+        if (lane == 0 && b < P.n_scan_blocks) store_i4(reinterpret_cast<int4*>(P.blk_sums), b, acc);
+    }
 }
 
 // ----------------------------------------- task scans -> work queue (a11) ---

@@ -205,30 +205,35 @@ __device__ __noinline__ double dlnfact(long long k)
 }
 
 // ------------------------------------------------------------ samplers ---
-// Gamma(alpha, 1): Marsaglia-Tsang squeeze on a Box-Muller normal; for
-// alpha < 1 the draw for alpha + 1 is scaled by u^(1/alpha).
-// Attempt j uses counter (j, layer | 1 << 8, particle, event).
-__device__ __noinline__ double gamma_draw(double alpha, uint32_t k0, uint32_t k1, uint32_t layer,
-                                          uint32_t part, uint32_t ev)
+// Gamma(alpha, 1): Marsaglia-Tsang acceptance test on a Box-Muller normal;
+// for alpha < 1 the draw for alpha + 1 is scaled by u^(1/alpha).
+//
+// Attempt j (Philox counter (j, layer | 1 << 8, particle, event)) of the
+// Marsaglia-Tsang method for Gamma(a), with d = a - 1/3 and c = 1/sqrt(9d):
+// true and d v when the draw is accepted; *w is the draw's fourth word (the
+// uniform of the alpha < 1 boost).  A task takes attempts j = 0, 1, ... up to
+// 64 and then falls back to d.
+__device__ __forceinline__ bool gamma_try(double d, double c, uint32_t j, uint32_t k0, uint32_t k1,
+                                          uint32_t layer, uint32_t part, uint32_t ev, double* g,
+                                          uint32_t* w)
 {
-    const double a = alpha < 1.0 ? alpha + 1.0 : alpha;
-    const double d = a - 1.0 / 3.0;
-    const double c = 1.0 / sqrt(9.0 * d);
-    for (uint32_t j = 0; j < 64; ++j) {
-        const U4 x = philox4x32_10(j, layer | (kTagGamma << 8), part, ev, k0, k1);
-        const double z = sqrt(-2.0 * dlog(unit_open(x.x))) * dcos_turns(unit_open(x.y));
-        const double t = 1.0 + c * z;
-        if (!(t > 0.0)) continue;
-        const double v = (t * t) * t;
-        const double lhs = dlog(unit_open(x.z));
-        const double rhs = ((((0.5 * z) * z) + d) - d * v) + d * dlog(v);
-        if (lhs < rhs) {
-            double g = d * v;
-            if (alpha < 1.0) g = g * dexp(dlog(unit_open(x.w)) / alpha);
-            return g;
-        }
-    }
-    return d;
+    const U4 x = philox4x32_10(j, layer | (kTagGamma << 8), part, ev, k0, k1);
+    const double z = sqrt(-2.0 * dlog(unit_open(x.x))) * dcos_turns(unit_open(x.y));
+    const double t = 1.0 + c * z;
+    if (!(t > 0.0)) return false;
+    const double v = (t * t) * t;
+    const double lhs = dlog(unit_open(x.z));
+    const double rhs = ((((0.5 * z) * z) + d) - d * v) + d * dlog(v);
+    if (!(lhs < rhs)) return false;
+    *g = d * v;
+    *w = x.w;
+    return true;
+}
+
+// the boost of an accepted draw for alpha < 1: Gamma(alpha) = Gamma(alpha + 1) u^(1/alpha)
+__device__ __forceinline__ double gamma_boost(double g, double alpha, uint32_t w)
+{
+    return alpha < 1.0 ? g * dexp(dlog(unit_open(w)) / alpha) : g;
 }
 
 // Poisson(mu): sequential inversion below mu = 10, transformed rejection

@@ -551,6 +551,29 @@ int check_tuning(fcs_ctx* c, const fcs_sim_options* o, Tuning* t)
 }
 
 // Fill the Params block for one launch sequence over a range of events.
+
+// scan blocks (kBlock / L particles each) per setup workgroup: as many as
+// fit (longer task lists per lane), while the batch still gives about four
+// workgroups per CU
+int setup_sub(long long N, int L, int n_cu)
+{
+    const long long ppb = fcsk::kBlock / L;
+    const long long fill = N / (ppb * 4LL * n_cu);
+    const long long cap = std::min<long long>(fcsk::kSetupSubMax, std::max<long long>(1, fcsk::kSetupPartCap / ppb));
+    return (int)std::max<long long>(1, std::min(cap, fill));
+}
+// the setup launch of a batch of N particles: one scan block per workgroup
+// (k_setup_one), or setup_sub of them (k_setup)
+void launch_setup(hipStream_t s, const Params* dP, long long N, int L, int n_cu)
+{
+    const int sub = setup_sub(N, L, n_cu);
+    if (sub == 1)
+        hipLaunchKernelGGL(fcsk::k_setup_one, dim3(grid_for(N, fcsk::kBlock / L)), dim3(fcsk::kBlock), 0, s, dP);
+    else
+        hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(N, (fcsk::kBlock / L) * sub)), dim3(fcsk::kBlock), 0, s,
+                           dP);
+}
+
 // `dense_out` (device) is the caller's dense cell buffer or NULL.
 int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
             const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
@@ -659,6 +682,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->chunk_cap = (int)std::min<long long>(c->chunk_cap, 2147483647LL);
     P->n_scan_blocks = (int)nsb;
     P->n_scan_groups = (int)nsg;
+    P->setup_sub = setup_sub(N, L, c->n_cu);
     P->n_seg_groups = (int)nsegb;
     P->task_n = (int32_t*)c->w_task_n.p;
     P->task_ehit = (float*)c->w_task_ehit.p;
@@ -727,9 +751,7 @@ void enqueue_batch(fcs_ctx* c, const Params& P, int mode, bool validate, int gri
                                dim3(grid_for(std::max(P.n_particles, P.n_events), 256)), dim3(256),
                                0, s, dP);
         if (dense) hipLaunchKernelGGL(fcsk::k_fill_dense, dim3(2048), dim3(256), 0, s, dP);
-        const int ppb = fcsk::kBlock / P.n_layers;
-        hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(P.n_particles, ppb)), dim3(fcsk::kBlock), 0,
-                           s, dP);
+        launch_setup(s, dP, P.n_particles, P.n_layers, c->n_cu);
         hipLaunchKernelGGL(fcsk::k_scan_group, dim3(P.n_scan_groups), dim3(fcsk::kScanThreads), 0, s, dP);
         if (P.n_scan_groups > 1)
             hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(fcsk::kScanThreads), 0, s, dP);
@@ -1261,8 +1283,7 @@ int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* ev
     if (in.validate_on_device)
         hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(in.N, (long long)n_events), 256)),
                            dim3(256), 0, c->stream, dP);
-    hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(in.N, fcsk::kBlock / c->n_layers)), dim3(fcsk::kBlock),
-                       0, c->stream, dP);
+    launch_setup(c->stream, dP, in.N, c->n_layers, c->n_cu);
     hipLaunchKernelGGL(fcsk::k_scan_group, dim3(P->n_scan_groups), dim3(fcsk::kScanThreads), 0, c->stream, dP);
     if (P->n_scan_groups > 1)
         hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(fcsk::kScanThreads), 0, c->stream, dP);
@@ -1342,8 +1363,7 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         if (in.validate_on_device)
             hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(in.N, (long long)n_events), 256)),
                                dim3(256), 0, s, dP);
-        hipLaunchKernelGGL(fcsk::k_setup, dim3(grid_for(in.N, fcsk::kBlock / c->n_layers)),
-                           dim3(fcsk::kBlock), 0, s, dP);
+        launch_setup(s, dP, in.N, c->n_layers, c->n_cu);
         hipLaunchKernelGGL(fcsk::k_scan_group, dim3(P->n_scan_groups), dim3(fcsk::kScanThreads), 0, s, dP);
         if (P->n_scan_groups > 1)
             hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(fcsk::kScanThreads), 0, s, dP);

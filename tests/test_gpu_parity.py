@@ -261,6 +261,15 @@ def test_full_hard_scatter(sim, oracle_lib, geom_full, param_full, geo, torch_cu
     check_parity(r, ref, geo, hits=False, label="hard scatter 100 events (full)")
 
 
+@pytest.mark.parametrize("n_events", [20, 28])
+def test_setup_groupings(sim, oracle_lib, geom_full, param_full, geo, torch_cuda, n_events):
+    """Hard-scatter slices whose particle counts give the setup two and three
+    scan blocks per workgroup (the full batch gives four, small ones one)."""
+    w = W.subset_events(W.hard_scatter(), 0, n_events)
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, hits=False)
+    check_parity(r, ref, geo, hits=False, label=f"hard scatter {n_events} events ({len(w.particles)} particles)")
+
+
 def test_full_pileup_sampled_events(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
     full = W.pileup()
     dp, doff = _dev(full, torch_cuda)
