@@ -147,6 +147,7 @@ struct Params {
     long long* seg_blk;  // [n_seg_groups] group totals, then their exclusive prefixes
     unsigned long long* blk_list;  // [n_events * n_seg * kSegBlocks] position << 32 | (event << blk_shift | block)
     Counters* ctr;
+    AsyncAcc* fold_acc;   // asynchronous calls with compaction: k_seg_top folds the totals here
     int32_t* queue;      // [kQueues * kQueueStride * 2]: tickets, then drained flags
     // outputs (device)
     float* out_elayer;
@@ -1585,10 +1586,8 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
 // ---------------------------------------------------- asynchronous calls ---
 // one thread: fold the call's counters and capacity checks into the
 // context's running totals (stream order serializes the calls)
-__global__ void k_async_tail(const Params* __restrict__ Pp, AsyncAcc* __restrict__ acc, int count_call)
+__device__ __forceinline__ void fold_async(const Params& P, AsyncAcc* acc, bool count_call)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const Params& P = *Pp;
     const auto c = G(P.ctr);
     int err = c->error;
     if (G(P.out_ids) && c->nnz_total > P.out_cap) err |= kErrCellCap;
@@ -1601,6 +1600,12 @@ __global__ void k_async_tail(const Params* __restrict__ Pp, AsyncAcc* __restrict
         a->nnz += c->nnz_total;
     }
     a->error |= err;
+}
+
+__global__ void k_async_tail(const Params* __restrict__ Pp, AsyncAcc* __restrict__ acc, int count_call)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    fold_async(*Pp, acc, count_call != 0);
 }
 
 // ---------------------------------------------- range-checked loads ---
@@ -1731,6 +1736,9 @@ __global__ __launch_bounds__(1024) void k_seg_top(const Params* __restrict__ Pp)
         G(P.ctr)->nnz_total = nnz;
         G(P.ctr)->n_blk_list = carry >> 32;
         if (G(P.out_ev_off)) G(P.out_ev_off)[P.n_events] = P.out_base + nnz;
+        // every counter and error bit of the call is final here (the passes
+        // after this one set none)
+        if (P.fold_acc) fold_async(P, P.fold_acc, true);
     }
 }
 

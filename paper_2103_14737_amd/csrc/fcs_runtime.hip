@@ -830,10 +830,13 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         int rc = prepare(c, o, tu, sh, d_particles, d_evoff, d_override, dense_out, dout, want_hits,
                          async, P);
         if (rc) return rc;
+        const int mode = !dense_out ? kPrivate : (P->out_ids ? kDenseCompact : kDenseOnly);
+        // asynchronous calls fold their totals into the context's running
+        // totals: in the segment top pass, or after a dense-only call
+        P->fold_acc = (async && mode != kDenseOnly) ? (fcsk::AsyncAcc*)c->w_async.p : nullptr;
         std::memset(hc, 0, sizeof(Counters));
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
         if ((rc = ring_sent(c))) return rc;
-        const int mode = !dense_out ? kPrivate : (P->out_ids ? kDenseCompact : kDenseOnly);
         GraphKey key{sh.n_particles, sh.n_events, mode, validate ? 1 : 0, grid, kAll};
         hipEvent_t k0 = c->ev_k0, k1 = c->ev_k1;
         if (profile && async) {
@@ -876,8 +879,9 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             HIPCHK(c, hipGetLastError());
         }
         if (async) {
-            hipLaunchKernelGGL(fcsk::k_async_tail, dim3(1), dim3(64), 0, c->stream,
-                               (const Params*)c->w_params.p, (fcsk::AsyncAcc*)c->w_async.p, 1);
+            if (mode == kDenseOnly)
+                hipLaunchKernelGGL(fcsk::k_async_tail, dim3(1), dim3(64), 0, c->stream,
+                                   (const Params*)c->w_params.p, (fcsk::AsyncAcc*)c->w_async.p, 1);
             HIPCHK(c, hipGetLastError());
             return FCS_OK;
         }
