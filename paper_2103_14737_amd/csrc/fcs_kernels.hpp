@@ -122,6 +122,7 @@ struct Params {
     int32_t n_scan_blocks;
     int32_t n_scan_groups;
     int32_t setup_sub;     // scan blocks per setup workgroup
+    int32_t validate;      // check device-resident inputs in the setup
     int32_t n_seg_groups;  // groups of kSegGroup segments
     // workspace
     int32_t* task_n;
@@ -464,26 +465,31 @@ __global__ void k_build_guide(const float* __restrict__ cum, uint8_t* __restrict
     guide[i] = (uint8_t)lo;
 }
 
-__global__ void k_validate(const Params* __restrict__ Pp)
+// Input checks of device-resident inputs, made by the setup kernels: each
+// particle by the thread that loads it, the offsets grid-stride.  A failed
+// check sets an error bit that the call reports; the batch still runs (every
+// index stays in range: events come from a clamped search, hit counts are
+// capped) and its outputs are unspecified.
+__device__ __forceinline__ int particle_errors(const Particle& pt)
 {
-    const Params& P = *Pp;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int err = 0;
-    if (i < P.n_particles) {
-        const Particle pt = load_particle(P.particles, i);
-        const int a = pt.pdg < 0 ? -pt.pdg : pt.pdg;
-        if (a != 11 && a != 22 && a != 211) err |= kErrPdg;
-        if (!(pt.e > 0.0f) || !isfinite(pt.e) || !isfinite(pt.eta) || !isfinite(pt.phi) ||
-            fabsf(pt.phi) > 3.2f)
-            err |= kErrParticle;
-    }
-    if (i < P.n_events) {
+    const int a = pt.pdg < 0 ? -pt.pdg : pt.pdg;
+    if (a != 11 && a != 22 && a != 211) err |= kErrPdg;
+    if (!(pt.e > 0.0f) || !isfinite(pt.e) || !isfinite(pt.eta) || !isfinite(pt.phi) || fabsf(pt.phi) > 3.2f)
+        err |= kErrParticle;
+    return err;
+}
+
+__device__ __forceinline__ void check_offsets(const Params& P)
+{
+    const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    int err = 0;
+    for (long long i = i0; i < P.n_events; i += stride)
         if (G(P.ev_off)[i] > G(P.ev_off)[i + 1]) err |= kErrOffsets;
-    }
-    if (i == 0) {
-        if (G(P.ev_off)[0] != P.part_base || G(P.ev_off)[P.n_events] != P.part_base + P.n_particles)
-            err |= kErrOffsets;
-    }
+    if (i0 == 0 &&
+        (G(P.ev_off)[0] != P.part_base || G(P.ev_off)[P.n_events] != P.part_base + P.n_particles))
+        err |= kErrOffsets;
     if (err) gor(&G(P.ctr)->error, err);
 }
 
@@ -518,15 +524,17 @@ __global__ __launch_bounds__(kBlock) void k_setup_one(const Params* __restrict__
     const int l = tid - lp * L;
     const long long gp = (long long)blockIdx.x * ppb + lp;
     const bool active = lp < ppb && gp < P.n_particles;
-    // after a failed input check (bad offsets, particles) no task gets hits:
-    // particles outside the offsets must not reach an event index
-    const bool bad = (G(P.ctr)->error & (kErrPdg | kErrParticle | kErrOffsets)) != 0;
+    if (P.validate) check_offsets(P);
     Particle pt = {0, 0.f, 0.f, 0.f};
     int set = -1, ev = 0;
     uint32_t pin = 0, evg = 0;
     double g = 0.0;
-    if (active && !bad) {
+    if (active) {
         pt = load_particle(P.particles, gp);
+        if (P.validate && l == 0) {
+            const int err = particle_errors(pt);
+            if (err) gor(&G(P.ctr)->error, err);
+        }
         ev = find_event(G(P.ev_off), P.n_events, P.part_base + gp);
         pin = (uint32_t)(P.part_base + gp - G(P.ev_off)[ev]);
         evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
@@ -658,21 +666,18 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
     const long long p0 = (long long)blockIdx.x * ppb * sub;
     const int np = (int)min((long long)(ppb * sub), P.n_particles - p0);
     const int nt = np * L;
-    // after a failed input check (bad offsets, particles) no task gets hits:
-    // particles outside the offsets must not reach an event index
-    const bool bad = (G(P.ctr)->error & (kErrPdg | kErrParticle | kErrOffsets)) != 0;
+    if (P.validate) check_offsets(P);
     for (int lp = tid; lp < np; lp += kBlock) {
         const long long gp = p0 + lp;
-        Particle pt = {0, 0.f, 0.f, 0.f};
-        int set = -1, ev = 0;
-        uint32_t pin = 0, evg = 0;
-        if (!bad) {
-            pt = load_particle(P.particles, gp);
-            ev = find_event(G(P.ev_off), P.n_events, P.part_base + gp);
-            pin = (uint32_t)(P.part_base + gp - G(P.ev_off)[ev]);
-            evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
-            set = select_set(P, pt.pdg, pt.e, pt.eta);
+        const Particle pt = load_particle(P.particles, gp);
+        if (P.validate) {
+            const int err = particle_errors(pt);
+            if (err) gor(&G(P.ctr)->error, err);
         }
+        const int ev = find_event(G(P.ev_off), P.n_events, P.part_base + gp);
+        const uint32_t pin = (uint32_t)(P.part_base + gp - G(P.ev_off)[ev]);
+        const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
+        const int set = select_set(P, pt.pdg, pt.e, pt.eta);
         s_set[lp] = set;
         s_pin[lp] = pin;
         s_evg[lp] = evg;

@@ -33,11 +33,11 @@ struct DevBuf {
 
 struct GraphKey {
     long long n_particles, n_events;
-    int mode, validate, grid, part;
+    int mode, grid, part;
     bool operator<(const GraphKey& o) const
     {
-        return std::tie(n_particles, n_events, mode, validate, grid, part) <
-               std::tie(o.n_particles, o.n_events, o.mode, o.validate, o.grid, o.part);
+        return std::tie(n_particles, n_events, mode, grid, part) <
+               std::tie(o.n_particles, o.n_events, o.mode, o.grid, o.part);
     }
 };
 
@@ -740,16 +740,12 @@ enum Part { kAll = 0, kPre = 1, kHits = 2, kPost = 3 };
 // caller's dense buffer alone (no compaction; the block counts are cleared)
 enum CellMode { kPrivate = 0, kDenseCompact = 1, kDenseOnly = 2 };
 
-void enqueue_batch(fcs_ctx* c, const Params& P, int mode, bool validate, int grid, int part)
+void enqueue_batch(fcs_ctx* c, const Params& P, int mode, int grid, int part)
 {
     const bool dense = mode != kPrivate;
     const Params* dP = (const Params*)c->w_params.p;
     hipStream_t s = c->stream;
     if (part == kAll || part == kPre) {
-        if (validate)
-            hipLaunchKernelGGL(fcsk::k_validate,
-                               dim3(grid_for(std::max(P.n_particles, P.n_events), 256)), dim3(256),
-                               0, s, dP);
         if (dense) hipLaunchKernelGGL(fcsk::k_fill_dense, dim3(2048), dim3(256), 0, s, dP);
         launch_setup(s, dP, P.n_particles, P.n_layers, c->n_cu);
         hipLaunchKernelGGL(fcsk::k_scan_group, dim3(P.n_scan_groups), dim3(fcsk::kScanThreads), 0, s, dP);
@@ -775,15 +771,14 @@ void enqueue_batch(fcs_ctx* c, const Params& P, int mode, bool validate, int gri
 }
 
 // instantiate (once per batch shape) and launch the graph of one part
-int launch_graph(fcs_ctx* c, const Params& P, const GraphKey& key, int mode, bool validate,
-                 int grid, int part)
+int launch_graph(fcs_ctx* c, const Params& P, const GraphKey& key, int mode, int grid, int part)
 {
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_batch(c, P, mode, validate, grid, part);
+        enqueue_batch(c, P, mode, grid, part);
         HIPCHK(c, hipStreamEndCapture(c->stream, &g));
         const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -834,10 +829,11 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         // asynchronous calls fold their totals into the context's running
         // totals: in the segment top pass, or after a dense-only call
         P->fold_acc = (async && mode != kDenseOnly) ? (fcsk::AsyncAcc*)c->w_async.p : nullptr;
+        P->validate = validate ? 1 : 0;
         std::memset(hc, 0, sizeof(Counters));
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
         if ((rc = ring_sent(c))) return rc;
-        GraphKey key{sh.n_particles, sh.n_events, mode, validate ? 1 : 0, grid, kAll};
+        GraphKey key{sh.n_particles, sh.n_events, mode, grid, kAll};
         hipEvent_t k0 = c->ev_k0, k1 = c->ev_k1;
         if (profile && async) {
             // a free event pair for this call; the oldest pending one is read
@@ -857,24 +853,24 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             ++c->prof_count;
         }
         if (use_graph && !profile) {
-            if ((rc = launch_graph(c, *P, key, mode, validate, grid, kAll))) return rc;
+            if ((rc = launch_graph(c, *P, key, mode, grid, kAll))) return rc;
         } else {
             // profiled: the hit kernel is launched on its own between two event
             // records (graphs for the parts before and after it)
             if (use_graph) {
                 key.part = kPre;
-                if ((rc = launch_graph(c, *P, key, mode, validate, grid, kPre))) return rc;
+                if ((rc = launch_graph(c, *P, key, mode, grid, kPre))) return rc;
             } else {
-                enqueue_batch(c, *P, mode, validate, grid, kPre);
+                enqueue_batch(c, *P, mode, grid, kPre);
             }
             if (profile) HIPCHK(c, hipEventRecord(k0, c->stream));
-            enqueue_batch(c, *P, mode, validate, grid, kHits);
+            enqueue_batch(c, *P, mode, grid, kHits);
             if (profile) HIPCHK(c, hipEventRecord(k1, c->stream));
             if (use_graph) {
                 key.part = kPost;
-                if ((rc = launch_graph(c, *P, key, mode, validate, grid, kPost))) return rc;
+                if ((rc = launch_graph(c, *P, key, mode, grid, kPost))) return rc;
             } else {
-                enqueue_batch(c, *P, mode, validate, grid, kPost);
+                enqueue_batch(c, *P, mode, grid, kPost);
             }
             HIPCHK(c, hipGetLastError());
         }
@@ -999,6 +995,11 @@ int stage_inputs(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
                                      hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
             in->N = in->h_off[n_events];
+            if (in->h_off[0] != 0)
+                return fail(c, FCS_E_INVALID_ARG, "event_offsets[0] = %lld, must be 0", (long long)in->h_off[0]);
+            for (int64_t e = 0; e < n_events; ++e)
+                if (in->h_off[e + 1] < in->h_off[e])
+                    return fail(c, FCS_E_INVALID_ARG, "event_offsets decreases at event %lld", (long long)e);
             if (o->n_particles > 0 && o->n_particles != in->N)
                 return fail(c, FCS_E_INVALID_ARG, "n_particles = %lld but event_offsets[n_events] = %lld",
                             (long long)o->n_particles, in->N);
@@ -1280,13 +1281,11 @@ int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* ev
     if ((rc = prepare(c, o, tu, sh, in.d_particles, in.d_evoff, nullptr, nullptr, nullptr, false,
                       false, P)))
         return rc;
+    P->validate = in.validate_on_device ? 1 : 0;
     const Params* dP = (const Params*)c->w_params.p;
     std::memset(hc, 0, sizeof(Counters));
     HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
     if ((rc = ring_sent(c))) return rc;
-    if (in.validate_on_device)
-        hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(in.N, (long long)n_events), 256)),
-                           dim3(256), 0, c->stream, dP);
     launch_setup(c->stream, dP, in.N, c->n_layers, c->n_cu);
     hipLaunchKernelGGL(fcsk::k_scan_group, dim3(P->n_scan_groups), dim3(fcsk::kScanThreads), 0, c->stream, dP);
     if (P->n_scan_groups > 1)
@@ -1353,6 +1352,7 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         if ((rc = prepare(c, o, tu, sh, in.d_particles, in.d_evoff, in.d_override, nullptr, nullptr,
                           false, async, P)))
             return rc;
+        P->validate = in.validate_on_device ? 1 : 0;
         P->grad_cells = grad_cells;
         P->acc_elayer = (double*)c->w_acc_el.p;
         P->acc_bins = (double*)c->w_acc_bins.p;
@@ -1364,9 +1364,6 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         std::memset(hc, 0, sizeof(Counters));
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, s));
         if ((rc = ring_sent(c))) return rc;
-        if (in.validate_on_device)
-            hipLaunchKernelGGL(fcsk::k_validate, dim3(grid_for(std::max(in.N, (long long)n_events), 256)),
-                               dim3(256), 0, s, dP);
         launch_setup(s, dP, in.N, c->n_layers, c->n_cu);
         hipLaunchKernelGGL(fcsk::k_scan_group, dim3(P->n_scan_groups), dim3(fcsk::kScanThreads), 0, s, dP);
         if (P->n_scan_groups > 1)

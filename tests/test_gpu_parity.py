@@ -232,6 +232,27 @@ def test_capacity_and_errors(sim, geo, torch_cuda):
         _np(r1["cell_e"]), _np(r2["cell_e"]), rtol=REL, atol=ABS)
 
 
+@pytest.mark.parametrize("mode", ["batched", "per_event"])
+def test_bad_device_offsets_rejected(sim, geo, torch_cuda, mode):
+    """Decreasing event offsets on the device: the call reports
+    FCS_E_INVALID_ARG (checked by the setup kernels in batched mode, on the
+    host copy in per-event mode) and the context stays clean."""
+    from paper_2103_14737_amd.fcs import FCS_E_INVALID_ARG, FcsError
+    torch = torch_cuda
+    w = W.subset_events(W.hard_scatter(), 0, 3)
+    dp, doff = _dev(w, torch)
+    off = w.event_offsets.copy()
+    off[1], off[2] = off[2], off[1]
+    with pytest.raises(FcsError) as e:
+        sim.simulate_events(dp, torch.from_numpy(off).cuda(), w.seed, mode=mode, cell_capacity=10 ** 7)
+    assert e.value.code == FCS_E_INVALID_ARG and ("offsets" in str(e.value))
+    r1 = sim.simulate_events(dp, doff, w.seed)
+    r2 = sim.simulate_events(dp, doff, w.seed, mode=mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(_np(r1["cell_ids"]), _np(r2["cell_ids"]))
+    assert np.allclose(_np(r1["cell_e"]), _np(r2["cell_e"]), rtol=REL, atol=ABS)
+
+
 def test_modes_and_graph_replay_agree(sim, geo, torch_cuda):
     w = W.subset_events(W.hard_scatter(), 20, 4)
     dp, doff = _dev(w, torch_cuda)
