@@ -299,45 +299,6 @@ __device__ __forceinline__ int4 block_excl_scan4(int4 v, int4& total)
     return add4(sub4(inc, v), off);
 }
 
-__device__ __forceinline__ int block_excl_scan1(int v, int& total)
-{
-    __shared__ int wsum1[kBlock / kWave];
-    const int wave = threadIdx.x / kWave;
-    const int inc = wave_incl_scan(v);
-    if (lane_id() == kWave - 1) wsum1[wave] = inc;
-    __syncthreads();
-    int off = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) {
-        const int s = wsum1[w];
-        if (w < wave) off += s;
-        tot += s;
-    }
-    __syncthreads();
-    total = tot;
-    return inc - v + off;
-}
-
-
-template <typename T>
-__device__ __forceinline__ T block_excl_scan_t(T v, T& total)
-{
-    __shared__ T wsum_t[kBlock / kWave];
-    const int wave = threadIdx.x / kWave;
-    const T inc = wave_incl_scan(v);
-    if (lane_id() == kWave - 1) wsum_t[wave] = inc;
-    __syncthreads();
-    T off = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) {
-        const T s = wsum_t[w];
-        if (w < wave) off += s;
-        tot += s;
-    }
-    __syncthreads();
-    total = tot;
-    return inc - v + off;
-}
 
 __device__ __forceinline__ long long block_sum_ll(long long v)
 {
@@ -406,23 +367,6 @@ __global__ void k_fill_dense(const Params* __restrict__ Pp)
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
         p[i] = 0.0f;
-}
-
-__global__ void k_reset_counters(const Params* __restrict__ Pp)
-{
-    for (int i = threadIdx.x; i < 2 * kQueues; i += blockDim.x) G(Pp->queue)[i * kQueueStride] = 0;
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        Counters* c = Pp->ctr;
-        c->hits_total = 0;
-        c->hits_out = 0;
-        c->nnz_total = 0;
-        c->n_chunks = 0;
-        c->n_small_hits = 0;
-        c->n_small_tasks = 0;
-        c->n_tiles = 0;
-        c->error = 0;
-        c->need_chunks = 0;
-    }
 }
 
 // ---------------------------------------------- parametrization tables ---
@@ -1204,7 +1148,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ int wave_broadcast_first(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Owners of the hits of a tile of small tasks, for one wave: every task that
 // starts inside the tile marks its first hit with its index relative to the
