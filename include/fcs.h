@@ -216,6 +216,16 @@ typedef struct {
                                    Errors, statistics and hit-kernel times
                                    of async calls are collected by
                                    fcs_synchronize.                         */
+    int32_t reuse_forward_queue; /* fcs_backward only: 1 = the caller states
+                                   that the particles, offsets and layer
+                                   energies hold what they held in the
+                                   batched fcs_simulate_events call that
+                                   last built the context's work queue.  If
+                                   that call took these same device
+                                   pointers, options and tuning, and no call
+                                   has rebuilt the queue since, the adjoint
+                                   reuses it (no setup, no scans); otherwise
+                                   the flag has no effect.                  */
 } fcs_sim_options;
 
 /* Fill *opt with the defaults: seed 0, batched, compact output, 100 MeV per

@@ -43,10 +43,13 @@ class _SimulateDense(torch.autograd.Function):
             return (None,) * 7
         bkw = {k: v for k, v in ctx.kw.items()
                if k in ("event_index_base", "hit_energy_scale", "nhit_cap", "min_layer_energy",
-                        "async_launch")}
+                        "async_launch", "chunk_hits", "big_task_hits", "tile_hits", "wg_per_cu")}
+        # the forward's work queue is reused when no other call has rebuilt it
+        # since (the library checks inputs, options and tuning)
         ge, gw = ctx.sim.backward(ctx.particles, ctx.event_offsets, ctx.seed,
                                   grad_cells.reshape(-1), elayer_override=elayer.detach(),
-                                  need_elayer=need_e, need_weights=need_w, **bkw)
+                                  need_elayer=need_e, need_weights=need_w,
+                                  reuse_forward_queue=True, **bkw)
         return (ge, gw) + (None,) * 5
 
 

@@ -169,7 +169,7 @@ struct Params {
     const float* grad_cells;
     double* acc_elayer;   // [n_tasks] FP64 sums of g over in-acceptance hits
     double* acc_bins;     // [n_hist * 256] FP64 sums of g * Ehit
-    uint8_t* hist_mark;   // [n_hist] 1 where acc_bins may hold sums (backward only)
+    uint8_t* hist_mark;   // [n_hist] 1 where acc_bins may hold sums (set by the adjoint)
     float* grad_elayer;
     float* grad_weights;
     long long n_hist;
@@ -542,7 +542,6 @@ __global__ __launch_bounds__(kBlock) void k_setup_one(const Params* __restrict__
             e_used = ov >= 0.0f ? (double)ov : 0.0;
         }
         ehit = n > 0 ? (float)(e_used / (double)n) : 0.0f;
-        if (n > 0 && G(P.hist_mark)) G(P.hist_mark)[set * L + l] = 1;
     }
     if (active) {
         G(P.task_n)[t] = n;
@@ -722,7 +721,6 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
                 e_used = ov >= 0.0f ? (double)ov : 0.0;
             }
             ehit = n > 0 ? (float)(e_used / (double)n) : 0.0f;
-            if (n > 0 && G(P.hist_mark)) G(P.hist_mark)[set * L + l] = 1;
         }
         G(P.task_n)[gt] = n;
         G(P.task_ehit)[gt] = ehit;
@@ -1863,13 +1861,16 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
             for (int d = kWave / 2; d > 0; d >>= 1) gsum += __shfl_xor(gsum, d, kWave);
             if (lane == 0 && gsum != 0.0) gadd(G(P.acc_elayer) + ck.t, gsum);
             wave_sync();
+            bool any = false;
             for (int b = lane; b < kBins; b += kWave) {
                 const double v = bins[b];
                 if (v != 0.0) {
                     gadd(G(P.acc_bins) + hb + b, v);
                     bins[b] = 0.0;
+                    any = true;
                 }
             }
+            if (any) G(P.hist_mark)[ck.H] = 1;  // the weight pass reads this histogram
             wave_sync();
         } else {
             int s0, h0, hcount;
@@ -1885,6 +1886,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
                 const double gc = (double)G(P.grad_cells)[(long long)sh.ev * C + h.cell];
                 gadd(G(P.acc_elayer) + sh.t, gc);
                 gadd(G(P.acc_bins) + (long long)sh.H * kBins + h.bin, gc * (double)sh.ehit);
+                G(P.hist_mark)[sh.H] = 1;
             }
             wave_sync();
             // the owner list borrowed the bin sums: zero them again

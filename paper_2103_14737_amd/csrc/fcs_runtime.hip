@@ -105,6 +105,29 @@ struct fcs_ctx {
     int prof_head = 0, prof_count = 0;
     double async_kernel_ms = 0.0;
     std::map<GraphKey, hipGraphExec_t> graphs;
+    // the work queue in the workspace: the device inputs and options it was
+    // built from and its parameter block; an adjoint call with
+    // reuse_forward_queue and the same inputs skips the setup and the scans.
+    // Any call that rebuilds or may overwrite the workspace clears q_valid.
+    struct QueueKey {
+        const void *particles, *evoff, *override_;
+        long long n_events, n_particles, ev_base;
+        unsigned long long seed;
+        float scale;
+        int cap;
+        double min_e;
+        int chunk, big, tile;
+        bool operator==(const QueueKey& o) const
+        {
+            return std::tie(particles, evoff, override_, n_events, n_particles, ev_base, seed, scale, cap,
+                            min_e, chunk, big, tile) ==
+                   std::tie(o.particles, o.evoff, o.override_, o.n_events, o.n_particles, o.ev_base, o.seed,
+                            o.scale, o.cap, o.min_e, o.chunk, o.big, o.tile);
+        }
+    };
+    bool q_valid = false;
+    QueueKey q_key{};
+    Params q_params{};
 };
 
 namespace {
@@ -287,6 +310,7 @@ void fcs_destroy(fcs_ctx* c)
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
+    c->q_valid = false;
     DevBuf* bufs[] = {&c->g_eta_lo, &c->g_eta_hi, &c->g_inv_deta, &c->g_inv_dphi, &c->g_phi_lo,
                       &c->g_neta, &c->g_nphi, &c->g_offset, &c->g_inv_r, &c->g_cell_id,
                       &c->p_e_edges, &c->p_eta_edges, &c->p_alpha, &c->p_weights, &c->p_cum,
@@ -440,6 +464,7 @@ int fcs_load_geometry(fcs_ctx* c, const fcs_geometry* g)
         c->cells_events = 0;
         c->flag_events = 0;
         drop_graphs(c);
+        c->q_valid = false;
     }
     if (c->has_param && c->n_layers != L) c->has_param = false;
     return FCS_OK;
@@ -548,6 +573,27 @@ int check_tuning(fcs_ctx* c, const fcs_sim_options* o, Tuning* t)
     if (t->wg_per_cu < 1 || t->wg_per_cu > 32)
         return fail(c, FCS_E_INVALID_ARG, "wg_per_cu = %d outside [1, 32]", t->wg_per_cu);
     return FCS_OK;
+}
+
+// the inputs and options a work queue is built from (device inputs)
+fcs_ctx::QueueKey queue_key(const fcs_sim_options* o, const Tuning& tu, const void* particles,
+                            const void* evoff, long long n_events, long long N, long long ev_base)
+{
+    fcs_ctx::QueueKey k{};
+    k.particles = particles;
+    k.evoff = evoff;
+    k.override_ = o->elayer_override;
+    k.n_events = n_events;
+    k.n_particles = N;
+    k.ev_base = ev_base;
+    k.seed = o->seed;
+    k.scale = o->hit_energy_scale_mev;
+    k.cap = o->nhit_cap;
+    k.min_e = o->min_layer_energy_mev;
+    k.chunk = tu.chunk;
+    k.big = tu.big;
+    k.tile = tu.tile;
+    return k;
 }
 
 // Fill the Params block for one launch sequence over a range of events.
@@ -817,6 +863,10 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
     if (small_launch)
         grid = (int)std::min<long long>(grid, std::max<long long>(16, (sh.n_particles * c->n_layers + 3) / 4));
     std::memset(res, 0, sizeof *res);
+    c->q_valid = false;
+    // a batched call over device inputs leaves a work queue an adjoint call
+    // may reuse
+    const bool keep = !small_launch && o->inputs_on_device;
     for (int attempt = 0; attempt < 2; ++attempt) {
         char* blk = ring_take(c);
         if (!blk) return fail(c, FCS_E_HIP, "hipEventSynchronize on a parameter block failed");
@@ -879,6 +929,11 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
                 hipLaunchKernelGGL(fcsk::k_async_tail, dim3(1), dim3(64), 0, c->stream,
                                    (const Params*)c->w_params.p, (fcsk::AsyncAcc*)c->w_async.p, 1);
             HIPCHK(c, hipGetLastError());
+            if (keep) {
+                c->q_key = queue_key(o, tu, d_particles, d_evoff, sh.n_events, sh.n_particles, P->ev_base);
+                c->q_params = *P;
+                c->q_valid = true;
+            }
             return FCS_OK;
         }
         HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
@@ -894,7 +949,13 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             HIPCHK(c, hipEventElapsedTime(&ms, k0, k1));
             *kernel_ms += ms;
         }
-        return counters_error(c, *res);
+        const int rc2 = counters_error(c, *res);
+        if (rc2 == FCS_OK && keep) {
+            c->q_key = queue_key(o, tu, d_particles, d_evoff, sh.n_events, sh.n_particles, P->ev_base);
+            c->q_params = *P;
+            c->q_valid = true;
+        }
+        return rc2;
     }
     return fail(c, FCS_E_HIP, "work queue sizing did not converge");
 }
@@ -1282,6 +1343,7 @@ int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* ev
                       false, P)))
         return rc;
     P->validate = in.validate_on_device ? 1 : 0;
+    c->q_valid = false;  // the setup below overwrites the workspace's task arrays
     const Params* dP = (const Params*)c->w_params.p;
     std::memset(hc, 0, sizeof(Counters));
     HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
@@ -1343,6 +1405,61 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
     if (g_el) HIPCHK(c, hipMemsetAsync(c->w_acc_el.p, 0, c->w_acc_el.bytes, c->stream));
     if (g_bins) HIPCHK(c, hipMemsetAsync(c->w_acc_bins.p, 0, c->w_acc_bins.bytes, c->stream));
     if (g_mark) HIPCHK(c, hipMemsetAsync(c->w_hist_mark.p, 0, c->w_hist_mark.bytes, c->stream));
+    const Params* dP = (const Params*)c->w_params.p;
+    hipStream_t s = c->stream;
+    auto grads_to = [&](Params* P) {
+        P->grad_cells = grad_cells;
+        P->acc_elayer = (double*)c->w_acc_el.p;
+        P->acc_bins = (double*)c->w_acc_bins.p;
+        P->hist_mark = (uint8_t*)c->w_hist_mark.p;
+        P->grad_elayer = grad_elayer;
+        P->grad_weights = grad_weights;
+    };
+    // the adjoint passes; the last two run whatever gradients are asked for:
+    // they also clear the accumulators
+    auto launch_adjoint = [&](const Params& P) -> int {
+        hipLaunchKernelGGL(fcsk::k_adjoint, dim3(c->n_cu * tu.wg_per_cu), dim3(fcsk::kBlock),
+                           geo_lds_bytes(P), s, dP);
+        hipLaunchKernelGGL(fcsk::k_adj_elayer, dim3(grid_for(nt, 256)), dim3(256), 0, s, dP);
+        hipLaunchKernelGGL(fcsk::k_adj_weights,
+                           dim3(grid_for(std::min<long long>(c->n_hist, (long long)c->n_cu * 32),
+                                         fcsk::kBlock / fcsk::kWave)),
+                           dim3(fcsk::kBlock), 0, s, dP);
+        if (async)
+            hipLaunchKernelGGL(fcsk::k_async_tail, dim3(1), dim3(64), 0, s, dP,
+                               (fcsk::AsyncAcc*)c->w_async.p, 0);
+        HIPCHK(c, hipGetLastError());
+        return FCS_OK;
+    };
+    const fcs_ctx::QueueKey key = queue_key(o, tu, in.d_particles, in.d_evoff, n_events, in.N,
+                                            (long long)o->event_index_base);
+    // The forward call's work queue, when asked for and still in the
+    // workspace for these device inputs: only the adjoint passes run, on the
+    // forward's parameter block; the forward's counters (the queue's sizes)
+    // stay on the device and the queue's tickets are reset.
+    if (o->reuse_forward_queue && o->inputs_on_device && c->q_valid && c->q_key == key) {
+        char* blk = ring_take(c);
+        if (!blk) return fail(c, FCS_E_HIP, "hipEventSynchronize on a parameter block failed");
+        Params* P = (Params*)blk;
+        Counters* hc = (Counters*)(blk + kCtrOffset);
+        *P = c->q_params;
+        P->validate = 0;
+        P->fold_acc = nullptr;
+        grads_to(P);
+        HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, sizeof(Params), hipMemcpyHostToDevice, s));
+        if ((rc = ring_sent(c))) return rc;
+        hipLaunchKernelGGL(fcsk::k_fill_u32, dim3(1), dim3(256), 0, s, (uint32_t*)c->w_queue.p,
+                           (long long)(2 * fcsk::kQueues * fcsk::kQueueStride), 0u);
+        if ((rc = launch_adjoint(*P))) return rc;
+        if (async) return finish_async();
+        HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
+                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        const Counters k = *hc;
+        if (!(k.error & fcsk::kErrChunkCap)) return counters_error(c, k);
+        // the forward's chunk list had overflowed: rebuild below
+    }
+    c->q_valid = false;  // the setup below rebuilds the workspace
     for (int attempt = 0; attempt < 2; ++attempt) {
         char* blk = ring_take(c);
         if (!blk) return fail(c, FCS_E_HIP, "hipEventSynchronize on a parameter block failed");
@@ -1353,14 +1470,7 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
                           false, async, P)))
             return rc;
         P->validate = in.validate_on_device ? 1 : 0;
-        P->grad_cells = grad_cells;
-        P->acc_elayer = (double*)c->w_acc_el.p;
-        P->acc_bins = (double*)c->w_acc_bins.p;
-        P->hist_mark = (uint8_t*)c->w_hist_mark.p;
-        P->grad_elayer = grad_elayer;
-        P->grad_weights = grad_weights;
-        const Params* dP = (const Params*)c->w_params.p;
-        hipStream_t s = c->stream;
+        grads_to(P);
         std::memset(hc, 0, sizeof(Counters));
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, s));
         if ((rc = ring_sent(c))) return rc;
@@ -1369,22 +1479,8 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         if (P->n_scan_groups > 1)
             hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(fcsk::kScanThreads), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P->n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
-        hipLaunchKernelGGL(fcsk::k_adjoint, dim3(c->n_cu * tu.wg_per_cu), dim3(fcsk::kBlock),
-                           geo_lds_bytes(*P), s, dP);
-        // both passes run whatever gradients are asked for: they also clear
-        // the accumulators
-        hipLaunchKernelGGL(fcsk::k_adj_elayer, dim3(grid_for(nt, 256)), dim3(256), 0, s, dP);
-        hipLaunchKernelGGL(fcsk::k_adj_weights,
-                           dim3(grid_for(std::min<long long>(c->n_hist, (long long)c->n_cu * 32),
-                                         fcsk::kBlock / fcsk::kWave)),
-                           dim3(fcsk::kBlock), 0, s, dP);
-        if (async) {
-            hipLaunchKernelGGL(fcsk::k_async_tail, dim3(1), dim3(64), 0, s, dP,
-                               (fcsk::AsyncAcc*)c->w_async.p, 0);
-            HIPCHK(c, hipGetLastError());
-            return finish_async();
-        }
-        HIPCHK(c, hipGetLastError());
+        if ((rc = launch_adjoint(*P))) return rc;
+        if (async) return finish_async();
         HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
                                  hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));

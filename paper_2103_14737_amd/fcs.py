@@ -75,7 +75,8 @@ class FcsSimOptions(C.Structure):
                 ("tile_hits", C.c_int32), ("wg_per_cu", C.c_int32), ("use_graph", C.c_int32),
                 ("inputs_on_device", C.c_int32), ("outputs_on_device", C.c_int32),
                 ("profile", C.c_int32), ("elayer_override", _vp), ("stream", _vp),
-                ("n_particles", C.c_int64), ("async_launch", C.c_int32)]
+                ("n_particles", C.c_int64), ("async_launch", C.c_int32),
+                ("reuse_forward_queue", C.c_int32)]
 
 
 class FcsSimOutput(C.Structure):
@@ -376,12 +377,15 @@ class Simulator:
                  hit_energy_scale=100.0, nhit_cap=20000, min_layer_energy=1e-6,
                  elayer_override=None, grad_elayer=None, grad_weights=None, chunk_hits=0,
                  big_task_hits=0, tile_hits=0, wg_per_cu=0, need_elayer=True, need_weights=True,
-                 async_launch=False):
+                 async_launch=False, reuse_forward_queue=False):
         """fcs_backward on device tensors: returns (grad_elayer [N*L],
         grad_weights [n_hist*256]) as torch CUDA float32 tensors; a gradient
         with need_* False is not computed and returned as None.  With
         async_launch the call returns once enqueued (torch's current stream
-        waits for the gradients); errors are raised by synchronize()."""
+        waits for the gradients); errors are raised by synchronize().
+        reuse_forward_queue: the inputs are those of the last batched
+        simulate_events call on these device tensors, unchanged; its work
+        queue is reused when the library can match the call."""
         import torch
         p, off, ov, dev, stream, n_events = self._inputs(particles, event_offsets, elayer_override)
         assert dev and _is_torch(grad_cells) and grad_cells.is_cuda
@@ -389,6 +393,7 @@ class Simulator:
         o = self._options(seed, event_index_base, "batched", (), hit_energy_scale, nhit_cap,
                           min_layer_energy, chunk_hits, big_task_hits, tile_hits, wg_per_cu,
                           False, dev, ov, stream, n_particles=N, async_launch=async_launch)
+        o.reuse_forward_queue = 1 if reuse_forward_queue else 0
         g = grad_cells.contiguous().float()
         if not need_elayer:
             grad_elayer = None

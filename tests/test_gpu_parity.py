@@ -464,3 +464,49 @@ def test_backward_repeats_and_partial_gradients(sim, geo, torch_cuda):
         assert np.count_nonzero(a) > 0
         # FP64 atomic order only
         assert np.all(np.abs(a - b) <= 1e-6 * np.abs(a) + 1e-9 * np.abs(a).max())
+
+
+def test_backward_reuses_the_forward_queue_only_when_it_matches(sim, geo, torch_cuda):
+    """reuse_forward_queue: right after the forward call the adjoint runs on
+    its work queue; after another call rebuilt the queue (other inputs), or
+    with other options, the flag falls back to a full adjoint.  Every variant
+    gives the gradients of the plain call."""
+    torch = torch_cuda
+    w = W.subset_events(W.single_pion_diff(), 0, 12)
+    dp, doff = _dev(w, torch)
+    other = W.subset_events(W.single_pion_diff(), 12, 5)
+    dpo, doffo = _dev(other, torch)
+    el = sim.simulate_events(dp, doff, w.seed, outputs=("elayer",))["elayer"]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    g = torch.randn(w.n_events * geo["n_cells"], generator=gen, device="cuda")
+    ref_e, ref_w = sim.backward(dp, doff, w.seed, g, elayer_override=el)
+
+    def fwd():
+        sim.simulate_events(dp, doff, w.seed, outputs=("dense",), elayer_override=el)
+
+    variants = []
+    fwd()
+    variants.append(sim.backward(dp, doff, w.seed, g, elayer_override=el, reuse_forward_queue=True))
+    variants.append(sim.backward(dp, doff, w.seed, g, elayer_override=el, reuse_forward_queue=True))
+    fwd()
+    sim.simulate_events(dpo, doffo, other.seed, outputs=("dense",))
+    variants.append(sim.backward(dp, doff, w.seed, g, elayer_override=el, reuse_forward_queue=True))
+    fwd()
+    variants.append(sim.backward(dp, doff, w.seed, g, elayer_override=el, reuse_forward_queue=True,
+                                 hit_energy_scale=150.0))
+    fwd()
+    variants.append(sim.backward(dp, doff, w.seed, g, elayer_override=el, reuse_forward_queue=True,
+                                 async_launch=True))
+    sim.synchronize()
+    torch.cuda.synchronize()
+    a_e, a_w = _np(ref_e).astype(np.float64), _np(ref_w).astype(np.float64)
+    assert np.count_nonzero(a_e) > 0 and np.count_nonzero(a_w) > 0
+    for i, (e, wg) in enumerate(variants):
+        if i == 3:
+            # a different hit energy scale: different counts, different gradients
+            assert not np.allclose(_np(e), a_e)
+            continue
+        for a, b in ((a_e, e), (a_w, wg)):
+            b = _np(b).astype(np.float64)
+            assert np.all(np.abs(a - b) <= 1e-6 * np.abs(a) + 1e-9 * np.abs(a).max()), i
