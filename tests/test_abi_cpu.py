@@ -172,7 +172,7 @@ def test_async_argument_checks(F, dry):
     assert st.n_calls == 0
     o = F.FcsSimOptions()
     F.lib().fcs_default_options(C.byref(o))
-    assert o.async_launch == 0 and o.n_particles == 0
+    assert o.async_launch == 0 and o.n_particles == 0 and o.reuse_forward_queue == 0
     o.n_particles = -3
     so = F.FcsSimOutput()
     p = np.ascontiguousarray(w.particles)
