@@ -490,9 +490,9 @@ __global__ __launch_bounds__(kBlock) void k_setup_one(const Params* __restrict__
             const double d = a - 1.0 / 3.0;
             const double c = 1.0 / sqrt(9.0 * d);
             uint32_t j = 0, w = 0;
-            while (!gamma_try(d, c, j, P.key0, P.key1, (uint32_t)l, pin, evg, &g, &w) && ++j < 64) {
+            while (!gamma_try<0>(d, c, j, P.key0, P.key1, (uint32_t)l, pin, evg, &g, &w) && ++j < 64) {
             }
-            g = j < 64 ? gamma_boost(g, alpha, w) : d;
+            g = j < 64 ? gamma_boost<0>(g, alpha, w) : d;
         }
     }
     g_s[tid] = g;
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_one(const Params* __restrict__
         const int c0 = s_cnt[0], c1 = s_cnt[1];
         if (tid < c0 + c1) {
             const int task = tid < c0 ? s_list[tid] : s_list[kBlock - 1 - (tid - c0)];
-            long long k = poisson_draw(s_mu[task], P.key0, P.key1, (uint32_t)(task % L), s_pin[task],
+            long long k = poisson_draw<0>(s_mu[task], P.key0, P.key1, (uint32_t)(task % L), s_pin[task],
                                        s_evg[task]);
             if (k < 1) k = 1;
             if (k > P.cap) k = P.cap;
@@ -590,7 +590,10 @@ __device__ __forceinline__ void gamma_next(const Params& P, const int* s_set, do
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
+// Six waves per SIMD (at most 80 VGPRs): the FP64 samplers of large batches
+// are throughput-bound, and the extra waves outweigh the larger call frames.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_setup(
+    const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
     __shared__ double s_g[kSetupTaskCap];       // Gamma draws, then layer energies
@@ -641,7 +644,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
                 double g = 0.0;
                 uint32_t w = 0;
                 const int lp = t / L;
-                bool done = gamma_try(d, c, j, P.key0, P.key1, (uint32_t)(t % L), s_pin[lp], s_evg[lp],
+                bool done = gamma_try<1>(d, c, j, P.key0, P.key1, (uint32_t)(t % L), s_pin[lp], s_evg[lp],
                                       &g, &w);
                 const bool fallback = !done && ++j == 64;
                 if (done || fallback) {
@@ -662,7 +665,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
         const int t = tid + k * kBlock;
         if (t < nt && s_set[t / L] >= 0 && s_n[t] == 0) {
             const double alpha = (double)G(P.alpha)[(s_set[t / L] / (P.n_ebins * P.n_etabins)) * L + t % L];
-            s_g[t] = gamma_boost(s_g[t], alpha, s_w[t]);
+            s_g[t] = gamma_boost<1>(s_g[t], alpha, s_w[t]);
         }
     }
     __syncthreads();
@@ -699,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(const Params* __restrict__ Pp)
         for (int i = tid; i < c0 + c1; i += kBlock) {
             const int t = i < c0 ? s_list[i] : s_list[kSetupTaskCap - 1 - (i - c0)];
             const int lp = t / L;
-            long long k = poisson_draw(s_mu[t], P.key0, P.key1, (uint32_t)(t % L), s_pin[lp], s_evg[lp]);
+            long long k = poisson_draw<1>(s_mu[t], P.key0, P.key1, (uint32_t)(t % L), s_pin[lp], s_evg[lp]);
             if (k < 1) k = 1;
             if (k > P.cap) k = P.cap;
             s_n[t] = (int)k;

@@ -96,10 +96,13 @@ constexpr double kLn2Lo = 1.90821492927058770002e-10;
 constexpr double kInvLn2 = 1.44269504088896338700e+00;
 
 // The Horner steps of the series below are single-rounding fused
-// multiply-adds (v_fma_f64).
+// multiply-adds (v_fma_f64).  The functions are templates on a copy tag
+// only so that each setup kernel gets its own compiled copy (and register
+// budget); the copies compute the same values.
 //
 // log for finite normal x > 0: x = m 2^e with m in [sqrt(1/2), sqrt(2)),
 // log m = 2 atanh(s) with s = (m-1)/(m+1), odd series to s^21
+template <int kCopy>
 __device__ __noinline__ double dlog(double x)
 {
     const long long bits = __double_as_longlong(x);
@@ -127,6 +130,7 @@ __device__ __noinline__ double dlog(double x)
 }
 
 // exp: x = k ln2 + r, Taylor series of e^r to r^13, times 2^k
+template <int kCopy>
 __device__ __noinline__ double dexp(double x)
 {
     if (x < -708.0) return 0.0;
@@ -157,6 +161,7 @@ __device__ __noinline__ double dexp(double x)
 
 // cos(2 pi u), u in (0,1): exact quarter-turn reduction, then a Taylor
 // series of cos (to t^16) or sin (to t^17) on |t| <= pi/4
+template <int kCopy>
 __device__ __noinline__ double dcos_turns(double u)
 {
     const double qt = floor(4.0 * u + 0.5);
@@ -190,18 +195,19 @@ __device__ __noinline__ double dcos_turns(double u)
 }
 
 // log(k!): exact factorial below 10, Stirling series (to 1/(1260 x^5))
+template <int kCopy>
 __device__ __noinline__ double dlnfact(long long k)
 {
     if (k < 10) {
         double f = 1.0;
         for (long long j = 2; j <= k; ++j) f = f * (double)j;
-        return dlog(f);
+        return dlog<kCopy>(f);
     }
     const double x = (double)k + 1.0;
     const double ix = 1.0 / x;
     const double ix2 = ix * ix;
     const double corr = ix * (1.0 / 12.0 - ix2 * (1.0 / 360.0 - ix2 * (1.0 / 1260.0)));
-    return (((x - 0.5) * dlog(x)) - x) + 0.91893853320467274178 + corr;
+    return (((x - 0.5) * dlog<kCopy>(x)) - x) + 0.91893853320467274178 + corr;
 }
 
 // ------------------------------------------------------------ samplers ---
@@ -213,17 +219,18 @@ __device__ __noinline__ double dlnfact(long long k)
 // true and d v when the draw is accepted; *w is the draw's fourth word (the
 // uniform of the alpha < 1 boost).  A task takes attempts j = 0, 1, ... up to
 // 64 and then falls back to d.
+template <int kCopy>
 __device__ __forceinline__ bool gamma_try(double d, double c, uint32_t j, uint32_t k0, uint32_t k1,
                                           uint32_t layer, uint32_t part, uint32_t ev, double* g,
                                           uint32_t* w)
 {
     const U4 x = philox4x32_10(j, layer | (kTagGamma << 8), part, ev, k0, k1);
-    const double z = sqrt(-2.0 * dlog(unit_open(x.x))) * dcos_turns(unit_open(x.y));
+    const double z = sqrt(-2.0 * dlog<kCopy>(unit_open(x.x))) * dcos_turns<kCopy>(unit_open(x.y));
     const double t = 1.0 + c * z;
     if (!(t > 0.0)) return false;
     const double v = (t * t) * t;
-    const double lhs = dlog(unit_open(x.z));
-    const double rhs = ((((0.5 * z) * z) + d) - d * v) + d * dlog(v);
+    const double lhs = dlog<kCopy>(unit_open(x.z));
+    const double rhs = ((((0.5 * z) * z) + d) - d * v) + d * dlog<kCopy>(v);
     if (!(lhs < rhs)) return false;
     *g = d * v;
     *w = x.w;
@@ -231,21 +238,23 @@ __device__ __forceinline__ bool gamma_try(double d, double c, uint32_t j, uint32
 }
 
 // the boost of an accepted draw for alpha < 1: Gamma(alpha) = Gamma(alpha + 1) u^(1/alpha)
+template <int kCopy>
 __device__ __forceinline__ double gamma_boost(double g, double alpha, uint32_t w)
 {
-    return alpha < 1.0 ? g * dexp(dlog(unit_open(w)) / alpha) : g;
+    return alpha < 1.0 ? g * dexp<kCopy>(dlog<kCopy>(unit_open(w)) / alpha) : g;
 }
 
 // Poisson(mu): sequential inversion below mu = 10, transformed rejection
 // (PTRS, Hoermann 1993) above with two attempts per Philox call.
 // Call j uses counter (j, layer | 2 << 8, particle, event).
+template <int kCopy>
 __device__ __noinline__ long long poisson_draw(double mu, uint32_t k0, uint32_t k1, uint32_t layer,
                                                uint32_t part, uint32_t ev)
 {
     if (mu < 10.0) {
         const U4 x = philox4x32_10(0u, layer | (kTagPoisson << 8), part, ev, k0, k1);
         const double u = unit_open(x.x);
-        double pk = dexp(-mu);
+        double pk = dexp<kCopy>(-mu);
         double cdf = pk;
         long long k = 0;
         while (u > cdf && k < 200) {
@@ -256,12 +265,12 @@ __device__ __noinline__ long long poisson_draw(double mu, uint32_t k0, uint32_t 
         return k;
     }
     const double slam = sqrt(mu);
-    const double loglam = dlog(mu);
+    const double loglam = dlog<kCopy>(mu);
     const double b = 0.931 + 2.53 * slam;
     const double a = -0.059 + 0.02483 * b;
     const double invalpha = 1.1239 + 1.1328 / (b - 3.4);
     const double vr = 0.9277 - 3.6224 / (b - 2.0);
-    const double log_ia = dlog(invalpha);
+    const double log_ia = dlog<kCopy>(invalpha);
     for (uint32_t j = 0; j < 32; ++j) {
         const U4 x = philox4x32_10(j, layer | (kTagPoisson << 8), part, ev, k0, k1);
         for (int h = 0; h < 2; ++h) {
@@ -273,8 +282,8 @@ __device__ __noinline__ long long poisson_draw(double mu, uint32_t k0, uint32_t 
             const double kd = floor((((2.0 * a) / us + b) * U + mu) + 0.43);
             if (us >= 0.07 && V <= vr) return (long long)kd;
             if (kd < 0.0 || (us < 0.013 && V > us)) continue;
-            const double lhs = (dlog(V) + log_ia) - dlog(a / (us * us) + b);
-            const double rhs = (-mu + kd * loglam) - dlnfact((long long)kd);
+            const double lhs = (dlog<kCopy>(V) + log_ia) - dlog<kCopy>(a / (us * us) + b);
+            const double rhs = (-mu + kd * loglam) - dlnfact<kCopy>((long long)kd);
             if (lhs <= rhs) return (long long)kd;
         }
     }
