@@ -179,8 +179,8 @@ def main():
                     help="also run a plain device copy of this many MiB (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "events shard across GPUs with no communication, see the design notes.",
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); events shard "
+              "across GPUs by event range with no communication between them.",
               file=sys.stderr)
         return 2
 
@@ -217,7 +217,7 @@ def main():
         return dp, doff, out, cap, q
 
     # ------------------------------------------------ headline: batched sweep
-    w = W.CONFIGS[args.workload]()
+    w = W.BY_NAME[args.workload]()
     dp, doff, out, cap, q = prepare(w)
     hits_per_step = q["n_hits"]
     print(f"bench: {w.name}: {w.n_events} events, {hits_per_step} hits per step", flush=True)

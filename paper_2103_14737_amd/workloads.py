@@ -318,7 +318,7 @@ def subset_events(w: Workload, first: int, count: int) -> Workload:
     return sub
 
 
-CONFIGS = {
+BY_NAME = {
     "single_electron": single_electron,
     "single_particle_sweep": single_particle_sweep,
     "hard_scatter": hard_scatter,
