@@ -51,7 +51,7 @@ struct Counters {
     int32_t n_tiles;
     int32_t error;        // bit set, see kErr*
     int32_t need_chunks;  // chunk entries required when over capacity
-    int32_t pad;
+    uint32_t done;        // workgroups of the count-reset pass that finished
     long long n_blk_list; // nonzero 64-cell blocks listed by the compaction
 };
 
@@ -1535,26 +1535,20 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
 // ---------------------------------------------------- asynchronous calls ---
 // one thread: fold the call's counters and capacity checks into the
 // context's running totals (stream order serializes the calls)
-__device__ __forceinline__ void fold_async(const Params& P, AsyncAcc* acc, bool count_call)
+__device__ __forceinline__ void fold_async(const Params& P, AsyncAcc* acc, bool count_call, long long nnz)
 {
     const auto c = G(P.ctr);
     int err = c->error;
-    if (G(P.out_ids) && c->nnz_total > P.out_cap) err |= kErrCellCap;
+    if (G(P.out_ids) && nnz > P.out_cap) err |= kErrCellCap;
     if (P.want_hits && c->hits_total > P.hit_cap) err |= kErrHitCap;
     const auto a = G(acc);
     if (count_call) {  // simulation calls; adjoint calls fold their errors only
         a->n_calls += 1;
         a->hits += c->hits_total;
         a->hits_out += c->hits_out;
-        a->nnz += c->nnz_total;
+        a->nnz += nnz;
     }
     a->error |= err;
-}
-
-__global__ void k_async_tail(const Params* __restrict__ Pp, AsyncAcc* __restrict__ acc, int count_call)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    fold_async(*Pp, acc, count_call != 0);
 }
 
 // ---------------------------------------------- range-checked loads ---
@@ -1687,7 +1681,7 @@ __global__ __launch_bounds__(1024) void k_seg_top(const Params* __restrict__ Pp)
         if (G(P.out_ev_off)) G(P.out_ev_off)[P.n_events] = P.out_base + nnz;
         // every counter and error bit of the call is final here (the passes
         // after this one set none)
-        if (P.fold_acc) fold_async(P, P.fold_acc, true);
+        if (P.fold_acc) fold_async(P, P.fold_acc, true, nnz);
     }
 }
 
@@ -1744,7 +1738,18 @@ __global__ __launch_bounds__(kBlock) void k_flags_reset(const Params* __restrict
         }
     }
     const long long tot = block_sum_ll(s);
-    if (threadIdx.x == 0 && tot) (void)gfetch_add(&G(P.ctr)->nnz_total, tot);
+    if (threadIdx.x != 0) return;
+    if (tot) (void)gfetch_add(&G(P.ctr)->nnz_total, tot);
+    if (!P.fold_acc) return;
+    // asynchronous calls: the last workgroup to finish folds the call's
+    // totals (its ticket is taken after its own count is added)
+    __threadfence();
+    if (gfetch_add(&G(P.ctr)->done, 1u) == gridDim.x - 1) {
+        __threadfence();
+        const long long nnz =
+            __hip_atomic_load(&G(P.ctr)->nnz_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        fold_async(P, P.fold_acc, true, nnz);
+    }
 }
 
 // emit pass: persistent waves take kEmitBatch listed blocks at a time; all
@@ -1905,6 +1910,8 @@ __global__ void k_adj_elayer(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // asynchronous adjoint calls fold their error bits (all set by now)
+    if (t == 0 && P.fold_acc) fold_async(P, P.fold_acc, false, 0);
     if (t >= P.n_tasks) return;
     const int n = G(P.task_n)[t];
     const double a = G(P.acc_elayer)[t];

@@ -877,8 +877,9 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         if (rc) return rc;
         const int mode = !dense_out ? kPrivate : (P->out_ids ? kDenseCompact : kDenseOnly);
         // asynchronous calls fold their totals into the context's running
-        // totals: in the segment top pass, or after a dense-only call
-        P->fold_acc = (async && mode != kDenseOnly) ? (fcsk::AsyncAcc*)c->w_async.p : nullptr;
+        // totals: in the segment top pass, or in the last workgroup of the
+        // count-reset pass of a dense-only call
+        P->fold_acc = async ? (fcsk::AsyncAcc*)c->w_async.p : nullptr;
         P->validate = validate ? 1 : 0;
         std::memset(hc, 0, sizeof(Counters));
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
@@ -925,9 +926,6 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             HIPCHK(c, hipGetLastError());
         }
         if (async) {
-            if (mode == kDenseOnly)
-                hipLaunchKernelGGL(fcsk::k_async_tail, dim3(1), dim3(64), 0, c->stream,
-                                   (const Params*)c->w_params.p, (fcsk::AsyncAcc*)c->w_async.p, 1);
             HIPCHK(c, hipGetLastError());
             if (keep) {
                 c->q_key = queue_key(o, tu, d_particles, d_evoff, sh.n_events, sh.n_particles, P->ev_base);
@@ -1425,9 +1423,6 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
                            dim3(grid_for(std::min<long long>(c->n_hist, (long long)c->n_cu * 32),
                                          fcsk::kBlock / fcsk::kWave)),
                            dim3(fcsk::kBlock), 0, s, dP);
-        if (async)
-            hipLaunchKernelGGL(fcsk::k_async_tail, dim3(1), dim3(64), 0, s, dP,
-                               (fcsk::AsyncAcc*)c->w_async.p, 0);
         HIPCHK(c, hipGetLastError());
         return FCS_OK;
     };
@@ -1444,7 +1439,9 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         Counters* hc = (Counters*)(blk + kCtrOffset);
         *P = c->q_params;
         P->validate = 0;
-        P->fold_acc = nullptr;
+        // an asynchronous adjoint folds its error bits in k_adj_elayer (the
+        // forward's, already folded, again: the fold is an OR)
+        P->fold_acc = async ? (fcsk::AsyncAcc*)c->w_async.p : nullptr;
         grads_to(P);
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, sizeof(Params), hipMemcpyHostToDevice, s));
         if ((rc = ring_sent(c))) return rc;
@@ -1470,6 +1467,8 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
                           false, async, P)))
             return rc;
         P->validate = in.validate_on_device ? 1 : 0;
+        // an asynchronous adjoint folds its error bits in k_adj_elayer
+        P->fold_acc = async ? (fcsk::AsyncAcc*)c->w_async.p : nullptr;
         grads_to(P);
         std::memset(hc, 0, sizeof(Counters));
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, s));
