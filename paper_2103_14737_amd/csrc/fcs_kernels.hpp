@@ -1772,11 +1772,14 @@ __global__ __launch_bounds__(kBlock) void k_seg_emit(const Params* __restrict__ 
     const auto ids_r = buf_rsrc((const long long*)G(P.cell_id), (uint32_t)(n_cells * 8));
     const int lane = lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
-    const long long waves = (long long)gridDim.x * kWavesPerBlock;
-    for (long long b0 = ((long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kEmitBatch;
-         b0 < n; b0 += waves * kEmitBatch) {
-        unsigned long long e64 = 0;
-        if (lane < kEmitBatch && b0 + lane < n) e64 = list[b0 + lane];
+    const long long step = (long long)gridDim.x * kWavesPerBlock * kEmitBatch;
+    long long b0 = ((long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave) * kEmitBatch;
+    // the list entries of a wave's next batch are loaded while it works on
+    // the current one
+    unsigned long long e_next = 0;
+    if (lane < kEmitBatch && b0 + lane < n) e_next = list[b0 + lane];
+    for (; b0 < n; b0 += step) {
+        const unsigned long long e64 = e_next;
         const int2 ent = make_int2((int)(uint32_t)e64, (int)(uint32_t)(e64 >> 32));
         const int nb = (int)(n - b0 < kEmitBatch ? n - b0 : kEmitBatch);
         float v[kEmitBatch];
@@ -1793,6 +1796,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_emit(const Params* __restrict__ 
             const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane(ent.x, b);
             id[b] = buf_load_i64(ids_r, v[b] != 0.0f ? ((gb & bmask) * 64u + (uint32_t)lane) * 8u : kBufNone);
         }
+        e_next = 0;
+        if (lane < kEmitBatch && b0 + step + lane < n) e_next = list[b0 + step + lane];
 #pragma unroll
         for (int b = 0; b < kEmitBatch; ++b) {
             const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane(ent.x, b);
