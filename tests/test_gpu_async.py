@@ -164,9 +164,53 @@ def test_async_training_steps_match_synchronous(sim, torch_cuda):
     st = sim.synchronize()
     torch.cuda.synchronize()
     assert st["n_calls"] == 3 and st["n_hits"] == 3 * base["stats"]["n_hits"]
+    # dense-only calls fold their nonzero-cell counts in the count-reset pass
+    assert st["n_cells_nonzero"] == 3 * base["stats"]["n_cells_nonzero"] > 0
     for o in outs:
         for a, b in zip(o, ref):
             a, b = _np(a).astype(np.float64), _np(b).astype(np.float64)
             assert np.count_nonzero(b) > 0
             # same kernels: FP32 and FP64 atomic order only
             assert np.all(np.abs(a - b) <= 1e-5 * np.abs(b) + 1e-7 * np.abs(b).max())
+
+
+def test_override_errors_reach_synchronize(sim, torch_cuda):
+    """A negative layer-energy override is an error of the call: raised by a
+    synchronous forward or adjoint call, and by synchronize() after an
+    asynchronous dense-only forward call or an asynchronous adjoint call;
+    the context is clean afterwards."""
+    torch = torch_cuda
+    from paper_2103_14737_amd.fcs import FCS_E_INVALID_ARG, FcsError
+    w = W.subset_events(W.single_pion_diff(), 0, 8)
+    dp, doff = _dev(w, torch)
+    base = sim.simulate_events(dp, doff, w.seed, outputs=("dense", "elayer"))
+    torch.cuda.synchronize()
+    sim.synchronize()
+    bad = base["elayer"].detach().clone()
+    bad[5] = -1.0
+    g = torch.ones(8 * sim.info()["n_cells"], device="cuda")
+    with pytest.raises(FcsError) as e:
+        sim.simulate_events(dp, doff, w.seed, outputs=("dense",), elayer_override=bad)
+    assert e.value.code == FCS_E_INVALID_ARG and "elayer_override" in str(e.value)
+    with pytest.raises(FcsError) as e:
+        sim.backward(dp, doff, w.seed, g, elayer_override=bad)
+    assert e.value.code == FCS_E_INVALID_ARG and "elayer_override" in str(e.value)
+    print("[async] synchronous override errors raised", flush=True)
+    sim.simulate_events(dp, doff, w.seed, outputs=("dense",), elayer_override=bad, async_launch=True)
+    with pytest.raises(FcsError) as e:
+        sim.synchronize()
+    assert e.value.code == FCS_E_INVALID_ARG and "elayer_override" in str(e.value)
+    print("[async] dense-only forward override error reported", flush=True)
+    sim.backward(dp, doff, w.seed, g, elayer_override=bad, async_launch=True)
+    with pytest.raises(FcsError) as e:
+        sim.synchronize()
+    assert e.value.code == FCS_E_INVALID_ARG and "elayer_override" in str(e.value)
+    print("[async] adjoint override error reported", flush=True)
+    el = base["elayer"].detach()
+    r = sim.simulate_events(dp, doff, w.seed, outputs=("dense",), elayer_override=el, async_launch=True)
+    ge, _ = sim.backward(dp, doff, w.seed, g, elayer_override=el, async_launch=True)
+    st = sim.synchronize()
+    torch.cuda.synchronize()
+    assert st["n_calls"] == 1 and st["n_hits"] == base["stats"]["n_hits"]
+    assert torch.count_nonzero(r["cells"]).item() == base["stats"]["n_cells_nonzero"]
+    assert torch.isfinite(ge).all().item()
