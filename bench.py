@@ -155,6 +155,55 @@ def run_fwd_bwd(torch, sim, geo, par, dev, steps, warmup):
     return res
 
 
+def oracle_baseline(w, geo, par, max_threads=16, budget_one=10.0, budget_all=5.0):
+    """The oracle timed on the host: whole passes over the workload on one
+    thread (until about `budget_one` s, at most 5 passes), then the same
+    workload split into event ranges run by independent threads at once
+    (the oracle is re-entrant and releases the interpreter lock while it
+    runs; at most `max_threads`, the CPU share of one GPU) until about
+    `budget_all` s.  Median passes; returns the cpu_baseline record."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    from paper_2103_14737_amd import workloads as W
+    oracle.build(force=False)
+    go, po = oracle.Geometry(geo), oracle.Param(par)
+
+    def run(sw):
+        return oracle.simulate(go, po, sw.particles, sw.event_offsets, sw.seed,
+                               event_index_base=sw.notes.get("event_index_base", 0),
+                               hit_energy_scale=sw.hit_energy_scale)["n_hits_total"]
+
+    runs = []
+    while not runs or (len(runs) < 5 and sum(runs) < budget_one):
+        t0 = time.perf_counter()
+        total = run(w)
+        runs.append(time.perf_counter() - t0)
+    dt = sorted(runs)[len(runs) // 2]
+    one = {"value": total / dt, "cores": 1,
+           "sample": f"the whole {w.name} workload ({w.n_events} events, {total} hits), one "
+                     f"thread, median of {len(runs)} passes ({sum(runs):.1f} s in all)"}
+    print(f"bench: oracle {one['value']:.4g} hits/s on 1 core", flush=True)
+    n_thr = max(1, min(max_threads, len(os.sched_getaffinity(0)), w.n_events))
+    bounds = np.linspace(0, w.n_events, n_thr + 1).astype(int)
+    parts = [W.subset_events(w, int(a), int(b - a)) for a, b in zip(bounds[:-1], bounds[1:])
+             if b > a]
+    runs_n = []
+    with ThreadPoolExecutor(max_workers=len(parts)) as ex:
+        while not runs_n or (len(runs_n) < 10 and sum(runs_n) < budget_all):
+            t0 = time.perf_counter()
+            tot = sum(ex.map(run, parts))
+            runs_n.append(time.perf_counter() - t0)
+            assert tot == total, (tot, total)
+    dt_n = sorted(runs_n)[len(runs_n) // 2]
+    print(f"bench: oracle {total / dt_n:.4g} hits/s on {len(parts)} cores", flush=True)
+    return {"value": total / dt_n, "unit": "hits/s", "cores": len(parts), "kind": "oracle",
+            "sample": f"the whole {w.name} workload ({w.n_events} events, {total} hits) split "
+                      f"into {len(parts)} event ranges run by {len(parts)} threads at once, "
+                      f"median of {len(runs_n)} passes ({sum(runs_n):.1f} s in all)",
+            "one_core": one}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,10 +314,14 @@ def main():
           f"hit kernel {kernel_ms:.3f} ms", flush=True)
 
     # the same batch as synchronous calls (each waits for its results)
+    wall = []
+
     def step_batched(profile=False):
+        t0 = time.perf_counter()
         r = sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap,
                                 out=out, profile=profile, hit_energy_scale=w.hit_energy_scale,
                                 **tuning)
+        wall.append(time.perf_counter() - t0)
         stats.append(r["stats"])
         return r["stats"]["n_hits"]
 
@@ -276,6 +329,7 @@ def main():
     timed = stats[-args.steps:]
     assert all(s["n_hits"] == hits_per_step for s in timed)
     call_ms = float(np.mean([s["device_ms"] for s in timed]))
+    wall_ms = np.array(wall[-args.steps:]) * 1e3
     print(f"bench: synchronous calls {t_sync * 1e3:.3f} ms/step", flush=True)
 
     line = {
@@ -290,7 +344,9 @@ def main():
                    "hits_per_step": hits_per_step, "tuning": tuning or "library defaults"},
         "events_per_s": w.n_events / t_step,
         "synchronous_calls": {"ms_per_step": t_sync * 1e3, "hits_per_s": hits_per_step / t_sync,
-                              "device_ms_per_call": call_ms},
+                              "device_ms_per_call": call_ms,
+                              "median_ms": float(np.median(wall_ms)),
+                              "std_ms": float(np.std(wall_ms))},
         "geometry_param_load_ms": load_ms,
     }
     # roofline of the dominant kernel (the persistent hit kernel)
@@ -353,12 +409,28 @@ def main():
             _sync(torch)
             t_o = (time.perf_counter() - t0) / n_o
             assert st_o["n_hits"] == n_o * qo["n_hits"], st_o
+
+            # the per-event launch form of the same batch
+            def step_o_pe():
+                r = sim.simulate_events(dpo, doffo, wo.seed, mode="per_event", outputs=("compact",),
+                                        cell_capacity=capo, out=outo,
+                                        hit_energy_scale=wo.hit_energy_scale, **tun_o)
+                return r["stats"]["n_hits"]
+
+            t_pe_o, res_o = _time_steps(torch, step_o_pe, 2, 1)
+            assert all(h == qo["n_hits"] for h in res_o)
             others[wo.name] = {"hits_per_step": qo["n_hits"], "ms_per_step": t_o * 1e3,
                                "hits_per_s": qo["n_hits"] / t_o,
                                "events_per_s": wo.n_events / t_o,
                                "hit_energy_scale_MeV": wo.hit_energy_scale,
-                               "tuning": tun_o or "library defaults"}
-            print(f"bench: {wo.name} {qo['n_hits'] / t_o:.4g} hits/s", flush=True)
+                               "tuning": tun_o or "library defaults",
+                               "per_event_launch": {"ms_per_step": t_pe_o * 1e3,
+                                                    "hits_per_s": qo["n_hits"] / t_pe_o,
+                                                    "events_per_s": wo.n_events / t_pe_o,
+                                                    "steps": 2},
+                               "batched_over_per_event": t_pe_o / t_o}
+            print(f"bench: {wo.name} {qo['n_hits'] / t_o:.4g} hits/s; per-event "
+                  f"{t_pe_o * 1e3:.1f} ms/step -> batched is {t_pe_o / t_o:.1f}x faster", flush=True)
             del dpo, doffo, outo
         line["other_workloads"] = others
 
@@ -375,23 +447,7 @@ def main():
 
     # ------------------------------------------------- CPU oracle baseline
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
-        go, po = oracle.Geometry(geo), oracle.Param(par)
-        # whole passes over the workload until about 10 s of CPU work (at
-        # most 5); the median pass is reported
-        runs = []
-        while len(runs) < 5 and sum(runs) < 10.0:
-            t0 = time.perf_counter()
-            ref = oracle.simulate(go, po, w.particles, w.event_offsets, w.seed)
-            runs.append(time.perf_counter() - t0)
-        dt = sorted(runs)[len(runs) // 2]
-        line["cpu_baseline"] = {"value": ref["n_hits_total"] / dt, "unit": "hits/s", "cores": 1,
-                                "kind": "oracle",
-                                "sample": f"the whole {w.name} workload ({w.n_events} events, "
-                                          f"{ref['n_hits_total']} hits), one thread, median of "
-                                          f"{len(runs)} passes ({sum(runs):.1f} s in all)"}
-        print(f"bench: oracle {ref['n_hits_total'] / dt:.4g} hits/s on 1 core", flush=True)
+        line["cpu_baseline"] = oracle_baseline(w, geo, par)
 
     sim.close()
     print(json.dumps(line), flush=True)

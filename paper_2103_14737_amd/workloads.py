@@ -309,12 +309,13 @@ def single_pion_diff(n_events=64, seed=2021):
 
 def subset_events(w: Workload, first: int, count: int) -> Workload:
     """Events [first, first+count) of a workload; returns the slice and keeps
-    the global event index available through notes['event_index_base']."""
+    the global event index of its first event (offset by the parent's own,
+    for a slice of a slice) in notes['event_index_base']."""
     a, b = int(w.event_offsets[first]), int(w.event_offsets[first + count])
     off = w.event_offsets[first:first + count + 1] - w.event_offsets[first]
     sub = Workload(f"{w.name}[{first}:{first + count}]", w.seed, w.particles[a:b].copy(),
                    off.astype(np.int64), w.hit_energy_scale, dict(w.notes))
-    sub.notes["event_index_base"] = first
+    sub.notes["event_index_base"] = int(w.notes.get("event_index_base", 0)) + first
     return sub
 
 
