@@ -204,6 +204,87 @@ def oracle_baseline(w, geo, par, max_threads=16, budget_one=10.0, budget_all=5.0
             "one_core": one}
 
 
+def run_sharing(torch, geo, par, dev, jobs=(1, 2, 4, 8, 16), events_per_call=100, seconds=1.0):
+    """Several jobs on one GPU at once, as in the paper's study of concurrent
+    processes sharing a GPU: each job is a host thread with its own library
+    context (its own stream, workspace and tables) and its own torch stream,
+    simulating its own slice of `events_per_call` single-particle events call
+    after call and waiting for each call's results.  Per-event and batched
+    forms; every job makes the same number of calls (sized so that one job
+    alone runs about `seconds`).  Returns, per form, the hits per second of
+    all jobs together for each job count."""
+    import threading
+
+    from paper_2103_14737_amd import workloads as W
+    from paper_2103_14737_amd.fcs import Simulator, particles_to_device
+    sweep = W.single_particle_sweep()
+    ctx = []
+    for j in range(max(jobs)):
+        sim = Simulator(0)
+        sim.load_geometry(geo)
+        sim.load_parametrization(par)
+        w = W.subset_events(sweep, j * events_per_call, events_per_call)
+        base = w.notes["event_index_base"]
+        dp = particles_to_device(w.particles, dev)
+        doff = torch.from_numpy(w.event_offsets).to(dev)
+        q = sim.query_sizes(dp, doff, w.seed, event_index_base=base)
+        cap = q["max_cells"]
+        out = {"cell_ids": torch.empty(cap, dtype=torch.int64, device=dev),
+               "cell_e": torch.empty(cap, dtype=torch.float32, device=dev),
+               "event_cell_offsets": torch.empty(w.n_events + 1, dtype=torch.int64, device=dev)}
+        ctx.append({"sim": sim, "w": w, "base": base, "dp": dp, "doff": doff, "cap": cap,
+                    "out": out, "hits": q["n_hits"], "stream": torch.cuda.Stream(device=dev)})
+    torch.cuda.synchronize()
+
+    def call(c, mode):
+        r = c["sim"].simulate_events(c["dp"], c["doff"], c["w"].seed, event_index_base=c["base"],
+                                     mode=mode, outputs=("compact",), cell_capacity=c["cap"],
+                                     out=c["out"])
+        assert r["stats"]["n_hits"] == c["hits"]
+
+    res = {}
+    for mode in ("per_event", "batched"):
+        for c in ctx:  # warm-up: workspaces and graphs of every context
+            with torch.cuda.stream(c["stream"]):
+                call(c, mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        call(ctx[0], mode)
+        n_calls = max(3, int(math.ceil(seconds / (time.perf_counter() - t0))))
+        by_n = {}
+        for n in jobs:
+            start = threading.Barrier(n + 1)
+            errors = []
+
+            def job(k):
+                c = ctx[k]
+                try:
+                    with torch.cuda.stream(c["stream"]):
+                        start.wait()
+                        for _ in range(n_calls):
+                            call(c, mode)
+                except BaseException as e:  # re-raised below
+                    errors.append(e)
+
+            threads = [threading.Thread(target=job, args=(k,)) for k in range(n)]
+            for t in threads:
+                t.start()
+            start.wait()
+            t0 = time.perf_counter()
+            for t in threads:
+                t.join()
+            dt = time.perf_counter() - t0
+            if errors:
+                raise errors[0]
+            hits = n_calls * sum(ctx[k]["hits"] for k in range(n))
+            by_n[str(n)] = {"hits_per_s": hits / dt, "calls_per_job": n_calls, "s": dt}
+            print(f"bench: sharing {mode} {n} jobs: {hits / dt:.4g} hits/s", flush=True)
+        res[mode] = by_n
+    for c in ctx:
+        c["sim"].close()
+    return {"events_per_call": events_per_call, "forms": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +294,8 @@ def main():
     ap.add_argument("--fwd-bwd-only", action="store_true",
                     help="time only the forward + backward section and print its figures "
                          "(for profiling; not the benchmark line)")
+    ap.add_argument("--sharing-only", action="store_true",
+                    help="time only the concurrent-jobs study and print its figures")
     ap.add_argument("--only-headline", action="store_true",
                     help="time only the headline batched workload (for profiling)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -248,6 +331,9 @@ def main():
 
     if args.fwd_bwd_only:
         print(json.dumps(run_fwd_bwd(torch, sim, geo, par, dev, args.steps, args.warmup)), flush=True)
+        return 0
+    if args.sharing_only:
+        print(json.dumps(run_sharing(torch, geo, par, dev)), flush=True)
         return 0
 
     def prepare(w, outputs=("compact",)):
@@ -433,6 +519,7 @@ def main():
                   f"{t_pe_o * 1e3:.1f} ms/step -> batched is {t_pe_o / t_o:.1f}x faster", flush=True)
             del dpo, doffo, outo
         line["other_workloads"] = others
+        line["gpu_sharing"] = run_sharing(torch, geo, par, dev)
 
     if args.copy_probe_mb:
         # a plain device copy of known size: the HBM counters of the profiled
