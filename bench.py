@@ -285,6 +285,59 @@ def run_sharing(torch, geo, par, dev, jobs=(1, 2, 4, 8, 16), events_per_call=100
     return {"events_per_call": events_per_call, "forms": res}
 
 
+def run_fine_tables(torch, geo, dev, w, tuning, steps, warmup, n_bins=64):
+    """The parametrization at the table volume of a full physics sample:
+    n_bins x n_bins (E, |eta|) sets, about 0.3 M histograms, generated on the
+    host, then loaded into a fresh context (timed: upload, cumulative and
+    guide tables built on the device) and kept resident; the headline batch
+    is timed on it as on the default tables.  Returns the record."""
+    from paper_2103_14737_amd import workloads as W
+    from paper_2103_14737_amd.fcs import Simulator, particles_to_device
+    par = W.make_param(n_ebins=n_bins, n_etabins=n_bins)
+    sim = Simulator(0)
+    try:
+        sim.load_geometry(geo)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.load_parametrization(par)
+        torch.cuda.synchronize()
+        load_ms = (time.perf_counter() - t0) * 1e3
+        dp = particles_to_device(w.particles, dev)
+        doff = torch.from_numpy(w.event_offsets).to(dev)
+        q = sim.query_sizes(dp, doff, w.seed, hit_energy_scale=w.hit_energy_scale)
+        cap = q["max_cells"]
+        out = {"cell_ids": torch.empty(cap, dtype=torch.int64, device=dev),
+               "cell_e": torch.empty(cap, dtype=torch.float32, device=dev),
+               "event_cell_offsets": torch.empty(w.n_events + 1, dtype=torch.int64, device=dev)}
+
+        def step():
+            sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap,
+                                out=out, hit_energy_scale=w.hit_energy_scale, async_launch=True,
+                                **tuning)
+
+        for _ in range(warmup):
+            step()
+        sim.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        st = sim.synchronize()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        assert st["n_hits"] == steps * q["n_hits"], st
+        n_hist = sim.info()["n_histograms"]
+    finally:
+        sim.close()
+    rec = {"n_ebins": n_bins, "n_etabins": n_bins, "n_histograms": n_hist,
+           "weights_mb": par["weights"].nbytes / 1e6, "load_ms": load_ms,
+           "hits_per_step": q["n_hits"], "ms_per_step": dt * 1e3,
+           "hits_per_s": q["n_hits"] / dt}
+    print(f"bench: {n_bins}x{n_bins} tables ({n_hist} histograms) loaded in {load_ms:.0f} ms; "
+          f"{w.name} {q['n_hits'] / dt:.4g} hits/s on them", flush=True)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +347,8 @@ def main():
     ap.add_argument("--fwd-bwd-only", action="store_true",
                     help="time only the forward + backward section and print its figures "
                          "(for profiling; not the benchmark line)")
+    ap.add_argument("--fine-tables-only", action="store_true",
+                    help="time only the headline batch on 64 x 64-bin tables")
     ap.add_argument("--sharing-only", action="store_true",
                     help="time only the concurrent-jobs study and print its figures")
     ap.add_argument("--only-headline", action="store_true",
@@ -334,6 +389,11 @@ def main():
         return 0
     if args.sharing_only:
         print(json.dumps(run_sharing(torch, geo, par, dev)), flush=True)
+        return 0
+    if args.fine_tables_only:
+        w = W.BY_NAME[args.workload]()
+        print(json.dumps(run_fine_tables(torch, geo, dev, w, {}, args.steps, args.warmup)),
+              flush=True)
         return 0
 
     def prepare(w, outputs=("compact",)):
@@ -520,6 +580,7 @@ def main():
             del dpo, doffo, outo
         line["other_workloads"] = others
         line["gpu_sharing"] = run_sharing(torch, geo, par, dev)
+        line["fine_tables"] = run_fine_tables(torch, geo, dev, w, tuning, args.steps, args.warmup)
 
     if args.copy_probe_mb:
         # a plain device copy of known size: the HBM counters of the profiled

@@ -154,30 +154,36 @@ def _dirichlet_alpha(t, l):
     return 0.1
 
 
-def make_param(n_layers=N_LAYERS):
+def make_param(n_layers=N_LAYERS, n_ebins=N_EBINS, n_etabins=N_ETABINS):
     """Histogram family: sets = 3 types x 16 log-E bins x 10 |eta| bins, one
     32 x 8 (r, alpha) histogram per (set, layer); bin b = ir * 8 + ia.
-    Weights w = exp(-r_c / lambda) / 8 with r_c the bin's radial centre."""
-    e_edges = np.array([1000.0 * 4000.0 ** (k / N_EBINS) for k in range(N_EBINS + 1)],
+    Weights w = exp(-r_c / lambda) / 8 with r_c the bin's radial centre.
+    Finer binnings (up to 64 x 64, about 0.3 M histograms, the table volume
+    of a full physics sample) cover the same E and |eta| ranges with the
+    same lambda(E, |eta|); the default binning is the 16 x 10 family."""
+    e_edges = np.array([1000.0 * 4000.0 ** (k / n_ebins) for k in range(n_ebins + 1)],
                        np.float32)
-    eta_edges = np.array([0.32 * k for k in range(N_ETABINS + 1)], np.float32)
+    eta_edges = np.array([(0.32 * N_ETABINS / n_etabins) * k if n_etabins != N_ETABINS
+                          else 0.32 * k for k in range(n_etabins + 1)], np.float32)
     alpha = np.array([[_dirichlet_alpha(t, l) for l in range(n_layers)]
                       for t in range(N_TYPES)], np.float32)
     dr = R_MAX_MM / N_RBINS
     r_c = (np.arange(N_RBINS) + 0.5) * dr
-    n_sets = N_TYPES * N_EBINS * N_ETABINS
+    n_sets = N_TYPES * n_ebins * n_etabins
     w = np.empty((n_sets, n_layers, N_RBINS, N_ABINS), np.float64)
     for t in range(N_TYPES):
-        for ie in range(N_EBINS):
-            for ih in range(N_ETABINS):
-                s = (t * N_EBINS + ie) * N_ETABINS + ih
+        for ie in range(n_ebins):
+            for ih in range(n_etabins):
+                s = (t * n_ebins + ie) * n_etabins + ih
+                # bin index in units of the 16 x 10 binning (exact for it)
+                xe, xh = ie * N_EBINS / n_ebins, ih * N_ETABINS / n_etabins
                 for l in range(n_layers):
-                    lam = _lambda_base(t, l) * (1.0 + 0.04 * ie) * (1.0 + 0.03 * ih)
+                    lam = _lambda_base(t, l) * (1.0 + 0.04 * xe) * (1.0 + 0.03 * xh)
                     w[s, l] = (np.exp(-r_c / lam) / N_ABINS)[:, None]
     return {
         "n_types": N_TYPES,
-        "n_ebins": N_EBINS,
-        "n_etabins": N_ETABINS,
+        "n_ebins": n_ebins,
+        "n_etabins": n_etabins,
         "n_layers": n_layers,
         "n_rbins": N_RBINS,
         "n_abins": N_ABINS,

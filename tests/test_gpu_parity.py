@@ -510,3 +510,31 @@ def test_backward_reuses_the_forward_queue_only_when_it_matches(sim, geo, torch_
         for a, b in ((a_e, e), (a_w, wg)):
             b = _np(b).astype(np.float64)
             assert np.all(np.abs(a - b) <= 1e-6 * np.abs(a) + 1e-9 * np.abs(a).max()), i
+
+
+# ------------------------------------------- tables at full-sample volume ---
+@pytest.fixture(scope="module")
+def fine_tables(oracle_lib):
+    par = W.make_param(n_ebins=64, n_etabins=64)
+    return par, oracle_lib.Param(par)
+
+
+def test_fine_binned_tables(torch_cuda, oracle_lib, geom_full, geo, fine_tables):
+    """A 64 x 64-bin parametrization (294,912 histograms, the table volume of
+    a full physics sample) loaded once and resident: sweep and hard-scatter
+    slices against the oracle on the same tables."""
+    from paper_2103_14737_amd.fcs import Simulator
+    par, par_o = fine_tables
+    s = Simulator(0)
+    try:
+        s.load_geometry(geo)
+        s.load_parametrization(par)
+        assert s.info()["n_histograms"] == 3 * 64 * 64 * 24
+        for w in (W.subset_events(W.single_particle_sweep(), 2000, 60),
+                  W.subset_events(W.hard_scatter(), 30, 2)):
+            base = w.notes["event_index_base"]
+            r, ref = run_both(s, oracle_lib, geom_full, par_o, geo, w, torch_cuda, hits=False,
+                              base=base)
+            check_parity(r, ref, geo, hits=False, label=f"{w.name}, 64 x 64 tables")
+    finally:
+        s.close()
