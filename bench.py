@@ -338,6 +338,29 @@ def run_fine_tables(torch, geo, dev, w, tuning, steps, warmup, n_bins=64):
     return rec
 
 
+def run_per_task(torch, sim, prepare, w, n_events, batched_hits_per_s):
+    """The per-(particle, layer) launch form on the first `n_events` events of
+    a workload (one launch per task with hits, as the paper's first port);
+    its hits/s beside the batched form's on the whole workload."""
+    from paper_2103_14737_amd import workloads as W
+    ws = W.subset_events(w, 0, n_events)
+    dp, doff, out, cap, q = prepare(ws)
+
+    def step():
+        r = sim.simulate_events(dp, doff, ws.seed, mode="per_task", outputs=("compact",),
+                                cell_capacity=cap, out=out, hit_energy_scale=ws.hit_energy_scale)
+        return r["stats"]["n_hits"]
+
+    t, res = _time_steps(torch, step, 2, 1)
+    assert all(h == q["n_hits"] for h in res)
+    rate = q["n_hits"] / t
+    print(f"bench: per-task {ws.name}: {t * 1e3:.1f} ms per call, {rate:.4g} hits/s -> batched "
+          f"is {batched_hits_per_s / rate:.1f}x faster", flush=True)
+    return {"events": n_events, "hits_per_step": q["n_hits"], "ms_per_step": t * 1e3,
+            "hits_per_s": rate, "events_per_s": n_events / t,
+            "batched_over_per_task": batched_hits_per_s / rate}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -525,6 +548,8 @@ def main():
         print(f"bench: per-event {t_pe * 1e3:.1f} ms/step -> batched is "
               f"{t_pe / t_step:.1f}x faster", flush=True)
 
+        line["per_task_launch"] = run_per_task(torch, sim, prepare, w, 500, value)
+
         line["fwd_bwd"] = run_fwd_bwd(torch, sim, geo, par, dev, args.steps, args.warmup)
 
         # ---------------------------------------- multi-particle workloads
@@ -575,6 +600,9 @@ def main():
                                                     "events_per_s": wo.n_events / t_pe_o,
                                                     "steps": 2},
                                "batched_over_per_event": t_pe_o / t_o}
+            if wo.name.startswith("hard_scatter"):
+                others[wo.name]["per_task_launch"] = run_per_task(
+                    torch, sim, prepare, wo, 5, qo["n_hits"] / t_o)
             print(f"bench: {wo.name} {qo['n_hits'] / t_o:.4g} hits/s; per-event "
                   f"{t_pe_o * 1e3:.1f} ms/step -> batched is {t_pe_o / t_o:.1f}x faster", flush=True)
             del dpo, doffo, outo

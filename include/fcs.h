@@ -16,7 +16,8 @@
  * (type + four-vector, Test Data section) and get back per-event cell
  * energies.  The paper groups the work of many layers, particles and events
  * into one launch (same section, last paragraph); FCS_MODE_BATCHED does that
- * for a whole batch, FCS_MODE_PER_EVENT launches once per event.
+ * for a whole batch, FCS_MODE_PER_EVENT launches once per event and
+ * FCS_MODE_PER_TASK once per (particle, layer), as the paper's first port.
  *
  * Conventions
  *   - Every call returns FCS_OK (0) or a negative FCS_E_* code and never
@@ -162,6 +163,12 @@ typedef struct {
 
 #define FCS_MODE_BATCHED 0   /* the whole batch in one persistent launch   */
 #define FCS_MODE_PER_EVENT 1 /* one launch sequence + sync per event       */
+/* FCS_MODE_PER_TASK: per event, the setup, then the event's hit counts
+ * copied to the host and one launch per (particle, layer) task with hits
+ * (one thread per hit, one device atomic per hit), then the compaction: the
+ * launch structure of the paper's first GPU port (CUDA Implementation
+ * section), kept as a baseline; results as in the other modes. */
+#define FCS_MODE_PER_TASK 2
 
 #define FCS_OUT_DENSE 1u     /* out->cells                                  */
 #define FCS_OUT_COMPACT 2u   /* out->cell_ids / cell_e / event_cell_offsets */

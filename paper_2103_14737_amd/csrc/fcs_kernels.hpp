@@ -1532,6 +1532,68 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     if (threadIdx.x == 0 && tot) (void)gfetch_add(&G(P.ctr)->hits_out, tot);
 }
 
+// ------------------------------------- per-(particle, layer) launches ---
+// The launch form of the paper's first GPU port, kept as a baseline: one
+// launch per (particle, layer) task with one thread per hit.  The hit is the
+// same function of its counter as in k_hits; the task's histogram is read
+// from global memory.  All hits of a task carry the same energy, so each
+// workgroup counts its hits per cell in LDS and adds count x Ehit to the
+// cell with one device atomic (one rounding per cell and workgroup, as the
+// chunk path flushes; a device atomic per hit would round once per hit),
+// keeping the per-block counts of nonzero cells for the compaction.
+constexpr int kTaskSlots = 2 * kBlock;  // LDS cell slots of a workgroup
+static_assert(kTaskSlots == 512, "the slot hash takes 9 bits");
+
+__global__ __launch_bounds__(kBlock) void k_task_hits(const Params* __restrict__ Pp, int t)
+{
+    const Params& P = *Pp;
+    extern __shared__ v4i s_geo[];
+    __shared__ int s_cell[kTaskSlots];
+    __shared__ uint32_t s_cnt[kTaskSlots];
+    if (G(P.ctr)->error & (kErrTooManyHits | kErrChunkCap)) return;
+    const GeoLds geo = stage_geometry(P, s_geo);
+    for (int k = threadIdx.x; k < kTaskSlots; k += kBlock) {
+        s_cell[k] = -1;
+        s_cnt[k] = 0u;
+    }
+    __syncthreads();
+    const int L = P.n_layers;
+    const int gp = t / L, l = t - gp * L;
+    const int n = G(P.task_n)[t];
+    const int i = (int)blockIdx.x * kBlock + (int)threadIdx.x;
+    const int ev = G(P.part_ev)[gp];
+    const float ehit = G(P.task_ehit)[t];
+    long long n_out = 0;
+    if (i < n) {
+        const int H = G(P.part_set)[gp] * L + l;
+        const uint32_t pin = (uint32_t)G(P.part_p)[gp];
+        const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
+        const Particle pt = load_particle(P.particles, gp);
+        const HitOut h = simulate_hit<false>(geo, layer_rec(geo, l), G(P.cum) + (long long)H * kBins,
+                                             G(P.guide) + (long long)H * kGuide, P.r_max / 32.0f,
+                                             P.key0, P.key1, (uint32_t)i, (uint32_t)l, pin, evg,
+                                             pt.eta, pt.phi);
+        if (P.want_hits) write_hit(P, (long long)G(P.task_hoff)[t] + i, h, ehit);
+        if (h.cell < 0) {
+            n_out = 1;
+        } else {
+            // linear probing; at most kBlock distinct cells in kTaskSlots slots
+            uint32_t k = ((uint32_t)h.cell * 2654435761u) >> (32 - 9);
+            for (;;) {
+                const int prev = atomicCAS(&s_cell[k], -1, h.cell);
+                if (prev == -1 || prev == h.cell) break;
+                k = (k + 1) & (kTaskSlots - 1);
+            }
+            atomicAdd(&s_cnt[k], 1u);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kTaskSlots; k += kBlock)
+        if (s_cnt[k]) deposit(P, ev, s_cell[k], (float)s_cnt[k] * ehit);
+    const long long tot = block_sum_ll(n_out);
+    if (threadIdx.x == 0 && tot) (void)gfetch_add(&G(P.ctr)->hits_out, tot);
+}
+
 // ---------------------------------------------------- asynchronous calls ---
 // one thread: fold the call's counters and capacity checks into the
 // context's running totals (stream order serializes the calls)

@@ -56,6 +56,7 @@ struct fcs_ctx {
     int n_cu = 0;
     char name[64] = {0};
     hipStream_t stream = nullptr;
+    std::vector<int32_t> h_task_n;  // per-task launch form: an event's hit counts
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_in = nullptr;
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the hit kernel
     std::string err = "no error";
@@ -855,7 +856,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
               const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
               float* dense_out, const fcs_sim_output* dout, bool want_hits, bool validate,
               bool use_graph, bool profile, Counters* res, double* kernel_ms, bool small_launch,
-              bool async)
+              bool async, bool per_task = false)
 {
     // a launch over few particles (per-event mode) gets a grid sized to its
     // tasks instead of filling the chip with idle persistent workgroups
@@ -903,7 +904,26 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             k1 = c->prof_ev[slot][1];
             ++c->prof_count;
         }
-        if (use_graph && !profile) {
+        if (per_task) {
+            // the per-(particle, layer) launch form: setup and scans, the
+            // tasks' hit counts to the host, one launch per task with hits,
+            // then the compaction
+            enqueue_batch(c, *P, mode, grid, kPre);
+            const long long nt = sh.n_particles * c->n_layers;
+            c->h_task_n.resize((size_t)nt);
+            HIPCHK(c, hipMemcpyAsync(c->h_task_n.data(), P->task_n, (size_t)nt * 4,
+                                     hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            const Params* dP = (const Params*)c->w_params.p;
+            if (profile) HIPCHK(c, hipEventRecord(k0, c->stream));
+            for (long long t = 0; t < nt; ++t)
+                if (c->h_task_n[(size_t)t] > 0)
+                    hipLaunchKernelGGL(fcsk::k_task_hits, dim3(grid_for(c->h_task_n[(size_t)t], fcsk::kBlock)),
+                                       dim3(fcsk::kBlock), geo_lds_bytes(*P), c->stream, dP, (int)t);
+            if (profile) HIPCHK(c, hipEventRecord(k1, c->stream));
+            enqueue_batch(c, *P, mode, grid, kPost);
+            HIPCHK(c, hipGetLastError());
+        } else if (use_graph && !profile) {
             if ((rc = launch_graph(c, *P, key, mode, grid, kAll))) return rc;
         } else {
             // profiled: the hit kernel is launched on its own between two event
@@ -1006,7 +1026,7 @@ int stage_inputs(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
     if (o->nhit_cap < 1) return fail(c, FCS_E_INVALID_ARG, "nhit_cap must be >= 1");
     if (!(o->min_layer_energy_mev > 0.0) || !std::isfinite(o->min_layer_energy_mev))
         return fail(c, FCS_E_INVALID_ARG, "min_layer_energy_mev must be finite and > 0");
-    if (o->mode != FCS_MODE_BATCHED && o->mode != FCS_MODE_PER_EVENT)
+    if (o->mode != FCS_MODE_BATCHED && o->mode != FCS_MODE_PER_EVENT && o->mode != FCS_MODE_PER_TASK)
         return fail(c, FCS_E_INVALID_ARG, "unknown mode %d", o->mode);
     if (o->n_particles < 0) return fail(c, FCS_E_INVALID_ARG, "n_particles < 0");
     if (c->dry) {
@@ -1103,7 +1123,8 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
         return fail(c, FCS_E_INVALID_ARG, "FCS_OUT_HITS needs hit_eta/phi/e/cell, task_hit_offsets, hit_capacity");
     if ((f & FCS_OUT_COUNTS) && !out->counts) return fail(c, FCS_E_INVALID_ARG, "FCS_OUT_COUNTS needs out->counts");
     if ((f & FCS_OUT_ELAYER) && !out->elayer) return fail(c, FCS_E_INVALID_ARG, "FCS_OUT_ELAYER needs out->elayer");
-    const bool per_event = o->mode == FCS_MODE_PER_EVENT;
+    const bool per_event = o->mode != FCS_MODE_BATCHED;  // per event, or per task within events
+    const bool per_task = o->mode == FCS_MODE_PER_TASK;
     const bool async = o->async_launch != 0;
     if (async && (per_event || !o->inputs_on_device || !o->outputs_on_device || o->n_particles <= 0))
         return fail(c, FCS_E_INVALID_ARG,
@@ -1207,7 +1228,7 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
             const float* dov = in.d_override ? in.d_override + p0 * L : nullptr;
             Counters k;
             rc = run_range(c, o, tu, sh, dp, in.d_evoff + e, dov, de.cells, &de, want_hits,
-                           in.validate_on_device, false, profile, &k, &kms, true, false);
+                           in.validate_on_device, false, profile, &k, &kms, true, false, per_task);
             if (rc) return rc;
             hits += k.hits_total;
             hits_out += k.hits_out;

@@ -29,6 +29,7 @@ FCS_DEVICE_NONE = -1
 
 FCS_MODE_BATCHED = 0
 FCS_MODE_PER_EVENT = 1
+FCS_MODE_PER_TASK = 2
 FCS_OUT_DENSE = 1
 FCS_OUT_COMPACT = 2
 FCS_OUT_HITS = 4
@@ -233,7 +234,8 @@ class Simulator:
         self._L.fcs_default_options(C.byref(o))
         o.seed = seed
         o.event_index_base = event_index_base
-        o.mode = {"batched": FCS_MODE_BATCHED, "per_event": FCS_MODE_PER_EVENT}[mode]
+        o.mode = {"batched": FCS_MODE_BATCHED, "per_event": FCS_MODE_PER_EVENT,
+                  "per_task": FCS_MODE_PER_TASK}[mode]
         flags = 0
         for n in outputs:
             flags |= _OUT_NAMES[n]

@@ -196,3 +196,29 @@ def test_async_backward_argument_checks(F, dry):
                               None, None)
     assert rc == F.FCS_E_INVALID_ARG
     assert "async_launch" in F.lib().fcs_last_error(dry._h).decode()
+
+
+def test_launch_modes(F, dry):
+    """The three launch forms are accepted (valid arguments reach the device
+    step); other mode numbers are refused before any device work."""
+    import ctypes as C
+    dry.load_geometry(W.make_geometry())
+    dry.load_parametrization(W.make_param())
+    w = W.single_particle_sweep(n_events=5)
+    for mode in ("batched", "per_event", "per_task"):
+        with pytest.raises(F.FcsError) as e:
+            dry.simulate_events(w.particles, w.event_offsets, 1, mode=mode, cell_capacity=10)
+        assert e.value.code == F.FCS_E_NO_DEVICE, mode
+    assert (F.FCS_MODE_BATCHED, F.FCS_MODE_PER_EVENT, F.FCS_MODE_PER_TASK) == (0, 1, 2)
+    o = F.FcsSimOptions()
+    F.lib().fcs_default_options(C.byref(o))
+    o.mode = 3
+    o.outputs = 8  # counts only
+    so = F.FcsSimOutput()
+    cnt = np.zeros(5 * 24, np.int32)
+    so.counts = cnt.ctypes.data
+    p = np.ascontiguousarray(w.particles)
+    off = np.ascontiguousarray(w.event_offsets)
+    rc = F.lib().fcs_simulate_events(dry._h, p.ctypes.data, off.ctypes.data, 5, C.byref(o), C.byref(so))
+    assert rc == F.FCS_E_INVALID_ARG
+    assert "mode" in F.lib().fcs_last_error(dry._h).decode()

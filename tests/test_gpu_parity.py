@@ -93,7 +93,7 @@ def run_both(sim, oracle_lib, geom_o, param_o, geo, w, torch, mode="batched", hi
 
 
 # ------------------------------------------------------------- workloads ---
-@pytest.mark.parametrize("mode", ["batched", "per_event"])
+@pytest.mark.parametrize("mode", ["batched", "per_event", "per_task"])
 @pytest.mark.parametrize("device_inputs", [True, False])
 def test_single_electron(sim, oracle_lib, geom_full, param_full, geo, torch_cuda, mode,
                          device_inputs):
@@ -103,7 +103,7 @@ def test_single_electron(sim, oracle_lib, geom_full, param_full, geo, torch_cuda
     check_parity(r, ref, geo, label=f"single electron {mode}")
 
 
-@pytest.mark.parametrize("mode", ["batched", "per_event"])
+@pytest.mark.parametrize("mode", ["batched", "per_event", "per_task"])
 def test_single_particle_sweep_slice(sim, oracle_lib, geom_full, param_full, geo, torch_cuda,
                                      mode):
     w = W.subset_events(W.single_particle_sweep(), 1000, 300)
@@ -112,7 +112,7 @@ def test_single_particle_sweep_slice(sim, oracle_lib, geom_full, param_full, geo
     check_parity(r, ref, geo, label=f"sweep[1000:1300] {mode}")
 
 
-@pytest.mark.parametrize("mode", ["batched", "per_event"])
+@pytest.mark.parametrize("mode", ["batched", "per_event", "per_task"])
 def test_hard_scatter_slice(sim, oracle_lib, geom_full, param_full, geo, torch_cuda, mode):
     w = W.subset_events(W.hard_scatter(), 10, 3)
     r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode,
@@ -182,7 +182,7 @@ def test_edge_cases(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
     # 20 MeV per expected hit so that the 4 TeV electron reaches the hit cap
     w = W.Workload("edges", 77, parts, np.array([0, 2, 2, 5, 7], np.int64),
                    hit_energy_scale=20.0)
-    for mode in ("batched", "per_event"):
+    for mode in ("batched", "per_event", "per_task"):
         r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode)
         check_parity(r, ref, geo, label=f"edges {mode}")
         assert ref["n"].max() == 20000
@@ -232,7 +232,7 @@ def test_capacity_and_errors(sim, geo, torch_cuda):
         _np(r1["cell_e"]), _np(r2["cell_e"]), rtol=REL, atol=ABS)
 
 
-@pytest.mark.parametrize("mode", ["batched", "per_event"])
+@pytest.mark.parametrize("mode", ["batched", "per_event", "per_task"])
 def test_bad_device_offsets_rejected(sim, geo, torch_cuda, mode):
     """Decreasing event offsets on the device: the call reports
     FCS_E_INVALID_ARG (checked by the setup kernels in batched mode, on the
@@ -258,7 +258,7 @@ def test_modes_and_graph_replay_agree(sim, geo, torch_cuda):
     dp, doff = _dev(w, torch_cuda)
     outs = []
     for kw in (dict(mode="batched"), dict(mode="batched"), dict(mode="batched", use_graph=False),
-               dict(mode="per_event")):
+               dict(mode="per_event"), dict(mode="per_task")):
         r = sim.simulate_events(dp, doff, w.seed, event_index_base=20,
                                 outputs=("compact", "counts", "hits"), **kw)
         torch_cuda.cuda.synchronize()
