@@ -361,6 +361,45 @@ def run_per_task(torch, sim, prepare, w, n_events, batched_hits_per_s):
             "batched_over_per_task": batched_hits_per_s / rate}
 
 
+def run_fp64_placement(torch, sim, w, dp, doff, out, cap, tuning, steps, warmup, fp32_hits_per_s):
+    """The FP64 placement variant on the headline batch: its throughput
+    (compact output, steps back to back as the headline) and the number of
+    hits whose cell differs from the FP32 placement (both hit lists
+    compared on the device), the quantity behind the paper's count of hits
+    that CPU and GPU put in different cells."""
+    def step():
+        sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap, out=out,
+                            hit_energy_scale=w.hit_energy_scale, async_launch=True,
+                            placement_fp64=True, **tuning)
+
+    for _ in range(warmup):
+        step()
+    sim.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    st = sim.synchronize()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    hits = st["n_hits"] // steps
+    cells = {}
+    for f64 in (False, True):
+        r = sim.simulate_events(dp, doff, w.seed, outputs=("hits",),
+                                hit_energy_scale=w.hit_energy_scale, placement_fp64=f64, **tuning)
+        cells[f64] = r["hit_cell"]
+        del r
+    torch.cuda.synchronize()
+    changed = int((cells[False] != cells[True]).sum().item())
+    out_only = int(((cells[False] < 0) != (cells[True] < 0)).sum().item())
+    del cells
+    print(f"bench: FP64 placement {hits / dt:.4g} hits/s; {changed} of {hits} hits change cell "
+          f"({out_only} at the acceptance edge)", flush=True)
+    return {"hits_per_step": hits, "ms_per_step": dt * 1e3, "hits_per_s": hits / dt,
+            "fp32_over_fp64": fp32_hits_per_s / (hits / dt), "hits_changing_cell": changed,
+            "of_which_acceptance": out_only, "rate": changed / hits}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -370,6 +409,8 @@ def main():
     ap.add_argument("--fwd-bwd-only", action="store_true",
                     help="time only the forward + backward section and print its figures "
                          "(for profiling; not the benchmark line)")
+    ap.add_argument("--fp64-placement-only", action="store_true",
+                    help="time only the FP64 placement variant on the headline batch")
     ap.add_argument("--fine-tables-only", action="store_true",
                     help="time only the headline batch on 64 x 64-bin tables")
     ap.add_argument("--sharing-only", action="store_true",
@@ -433,6 +474,13 @@ def main():
             out["cells"] = torch.empty((w.n_events, geo["n_cells"]), dtype=torch.float32,
                                        device=dev)
         return dp, doff, out, cap, q
+
+    if args.fp64_placement_only:
+        w = W.BY_NAME[args.workload]()
+        dp, doff, out, cap, q = prepare(w)
+        print(json.dumps(run_fp64_placement(torch, sim, w, dp, doff, out, cap, {}, args.steps,
+                                            args.warmup, float("nan"))), flush=True)
+        return 0
 
     # ------------------------------------------------ headline: batched sweep
     w = W.BY_NAME[args.workload]()
@@ -609,6 +657,8 @@ def main():
         line["other_workloads"] = others
         line["gpu_sharing"] = run_sharing(torch, geo, par, dev)
         line["fine_tables"] = run_fine_tables(torch, geo, dev, w, tuning, args.steps, args.warmup)
+        line["placement_fp64"] = run_fp64_placement(torch, sim, w, dp, doff, out, cap, tuning,
+                                                    args.steps, args.warmup, value)
 
     if args.copy_probe_mb:
         # a plain device copy of known size: the HBM counters of the profiled

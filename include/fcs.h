@@ -233,6 +233,16 @@ typedef struct {
                                    has rebuilt the queue since, the adjoint
                                    reuses it (no setup, no scans); otherwise
                                    the flag has no effect.                  */
+    int32_t placement_fp64;      /* fcs_simulate_events: 1 = place every hit
+                                   and look up its cell in FP64 (the same
+                                   uniforms and bin; cos and sin of the
+                                   angle from an FP64 series in turns; the
+                                   FP32 geometry values promoted), a chain
+                                   variant for measuring how many hits the
+                                   FP32 contract puts in another cell.
+                                   Hit positions are returned rounded to
+                                   FP32.  fcs_backward refuses it
+                                   (FCS_E_INVALID_ARG).  Default 0.         */
 } fcs_sim_options;
 
 /* Fill *opt with the defaults: seed 0, batched, compact output, 100 MeV per

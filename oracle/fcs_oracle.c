@@ -68,6 +68,7 @@ typedef struct {
     int32_t nhit_cap;
     double min_layer_energy;    /* layers below this energy get no hits */
     const float *elayer_override; /* [N * L] or NULL */
+    int32_t placement_fp64;     /* 1: place hits in FP64 (chain variant) */
 } og_opts;
 
 typedef struct {
@@ -212,8 +213,10 @@ double oracle_exp(double x)
     return p * scale;
 }
 
-/* cos(2 pi u) for u in (0,1): exact reduction in turns to |t| <= pi/4, then
- * Taylor series of cos (to t^16) or sin (to t^17). */
+/* cos(2 pi u): exact reduction in quarter turns to |t| <= pi/4, then Taylor
+ * series of cos (to t^16) or sin (to t^17); u in (0,1) for the normal draws,
+ * u in [-1/4, 1) for the FP64 placement (the quadrant of a negative multiple
+ * of a quarter turn is taken modulo 4). */
 double oracle_cos_turns(double u)
 {
     double q = floor(4.0 * u + 0.5);
@@ -498,6 +501,61 @@ static og_hit one_hit(const og_geom *G, const float *cum, float r_max, uint64_t 
     return h;
 }
 
+/* ------------------------------------------------------------------------ */
+/* FP64 placement (a chain variant of the same hit; Validation section: the  */
+/* rounding of the placement decides the cell of a few hits)                */
+/* ------------------------------------------------------------------------ */
+/* The cell lookup of oracle_lookup with the position and every product in
+ * FP64, the FP32 geometry values promoted. */
+static int32_t lookup_f64(const og_geom *G, int32_t layer, double eta, double phi)
+{
+    const int32_t R = G->n_regions;
+    const int32_t base = layer * R;
+    if (!(eta >= (double)G->reg_eta_lo[base]) || !(eta < (double)G->reg_eta_hi[base + R - 1]))
+        return -1;
+    int32_t k = 0;
+    for (int32_t j = 1; j < R; ++j)
+        if (eta >= (double)G->reg_eta_lo[base + j]) k = k + 1;
+    const int32_t r = base + k;
+    int32_t ie = (int32_t)floor((eta - (double)G->reg_eta_lo[r]) * (double)G->reg_inv_deta[r]);
+    int32_t ip = (int32_t)floor((phi - (double)G->reg_phi_lo[r]) * (double)G->reg_inv_dphi[r]);
+    if (ie < 0) ie = 0;
+    if (ie > G->reg_neta[r] - 1) ie = G->reg_neta[r] - 1;
+    if (ip < 0) ip = 0;
+    if (ip > G->reg_nphi[r] - 1) ip = G->reg_nphi[r] - 1;
+    return G->reg_offset[r] + ie * G->reg_nphi[r] + ip;
+}
+
+/* The hit of one_hit (same counter, uniforms and bin) placed in FP64: the
+ * radius (ir + u1) * dr, the angle at t = (ia + u2) / 8 turns with its
+ * cosine and sine (the cosine a quarter turn back) from oracle_cos_turns,
+ * then the same (eta, phi) formulas, the phi wrap and the lookup, all in
+ * FP64; the position is returned rounded to FP32. */
+static og_hit one_hit_f64(const og_geom *G, const float *cum, float r_max, uint64_t seed,
+                          uint32_t i, uint32_t layer, uint32_t p, uint32_t ev,
+                          float eta_p, float phi_p)
+{
+    uint32_t x[4];
+    draw(seed, i, layer | (TAG_HIT << 8), p, ev, x);
+    float u0 = u24(x[0]), u1 = u24(x[1]), u2 = u24(x[2]);
+    og_hit h;
+    h.bin = oracle_find_bin(cum, u0);
+    int32_t ir = h.bin >> 3, ia = h.bin & 7;
+    double r = ((double)ir + (double)u1) * (double)(r_max / 32.0f);
+    double t = ((double)ia + (double)u2) * 0.125;
+    double c = oracle_cos_turns(t);
+    double s = oracle_cos_turns(t - 0.25);
+    double inv_r = (double)G->layer_inv_r[layer];
+    double eta = (double)eta_p + (r * c) * inv_r;
+    double phi = (double)phi_p + (r * s) * inv_r;
+    if (phi >= 3.14159265358979323846) phi = phi - TWO_PI;
+    else if (phi < -3.14159265358979323846) phi = phi + TWO_PI;
+    h.eta = (float)eta;
+    h.phi = (float)phi;
+    h.cell = lookup_f64(G, (int32_t)layer, eta, phi);
+    return h;
+}
+
 /* exported single-hit evaluation for tests */
 int32_t oracle_hit(const og_geom *G, const float *cum, float r_max, uint64_t seed, uint32_t i,
                    uint32_t layer, uint32_t p, uint32_t ev, float eta_p, float phi_p,
@@ -589,8 +647,11 @@ int oracle_simulate(const og_geom *G, const og_param *P, const og_particle *part
                 if (out->set) out->set[task] = S.set;
                 const float *cum = P->cum + ((int64_t)S.set * L + l) * NBINS;
                 for (int32_t i = 0; i < S.n[l]; ++i) {
-                    og_hit h = one_hit(G, cum, P->r_max, O->seed, (uint32_t)i, (uint32_t)l, p,
-                                       ev, pt->eta, pt->phi);
+                    og_hit h = O->placement_fp64
+                                   ? one_hit_f64(G, cum, P->r_max, O->seed, (uint32_t)i, (uint32_t)l,
+                                                 p, ev, pt->eta, pt->phi)
+                                   : one_hit(G, cum, P->r_max, O->seed, (uint32_t)i, (uint32_t)l, p,
+                                             ev, pt->eta, pt->phi);
                     out->n_hits_total++;
                     if (h.cell < 0) {
                         out->n_out_of_acc++;

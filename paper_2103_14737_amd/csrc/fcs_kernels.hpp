@@ -122,6 +122,7 @@ struct Params {
     int32_t n_scan_blocks;
     int32_t n_scan_groups;
     int32_t setup_sub;     // scan blocks per setup workgroup
+    int32_t placement_f64; // hit kernels place hits in FP64 (chain variant)
     int32_t validate;      // check device-resident inputs in the setup
     int32_t n_seg_groups;  // groups of kSegGroup segments
     // workspace
@@ -1008,6 +1009,27 @@ __device__ __forceinline__ int lookup_cell(const GeoLds& g, const LayerRec& lr, 
     return iv.z + (int)__umul24((unsigned)ie, (unsigned)iv.y) + ip;
 }
 
+// The same lookup in FP64 (FP64 placement variant): the position compared
+// and scaled in FP64 against the FP32 geometry values.
+__device__ __forceinline__ int lookup_cell_f64(const GeoLds& g, const LayerRec& lr, int l,
+                                               double eta, double phi)
+{
+    if (!(eta >= (double)f_of(lr.a.x)) || !(eta < (double)f_of(lr.a.y))) return -1;
+    int k = (int)(eta >= (double)f_of(lr.b0.y)) + (int)(eta >= (double)f_of(lr.b0.z)) +
+            (int)(eta >= (double)f_of(lr.b0.w));
+    if (g.n_regions > 4)
+        k += (int)(eta >= (double)f_of(lr.b1.x)) + (int)(eta >= (double)f_of(lr.b1.y)) +
+             (int)(eta >= (double)f_of(lr.b1.z)) + (int)(eta >= (double)f_of(lr.b1.w));
+    const int r = l * g.n_regions + k;
+    const v4i f = g.regions[2 * r];
+    const v4i iv = g.regions[2 * r + 1];
+    int ie = (int)floor((eta - (double)f_of(f.x)) * (double)f_of(f.y));
+    int ip = (int)floor((phi - (double)f_of(f.z)) * (double)f_of(f.w));
+    ie = min(max(ie, 0), iv.x - 1);
+    ip = min(max(ip, 0), iv.y - 1);
+    return iv.z + ie * iv.y + ip;
+}
+
 // stage the geometry tables into LDS (call with every thread, then sync)
 __device__ __forceinline__ GeoLds stage_geometry(const Params& P, v4i* s_geo)
 {
@@ -1052,8 +1074,9 @@ struct HitOut {
 // one hit: counter (i, layer | 3 << 8, particle in event, global event)
 // -> three 24-bit uniforms -> (r, alpha) bin -> position in the bin ->
 // (eta, phi) -> cell.  kTask: the wave's hits belong to one task (layer,
-// particle and event uniform; padded guide in LDS).
-template <bool kTask, typename CumT, typename GuideT>
+// particle and event uniform; padded guide in LDS).  kF64: the placement
+// and the cell lookup in FP64 (a chain variant; same uniforms and bin).
+template <bool kTask, bool kF64 = false, typename CumT, typename GuideT>
 __device__ __forceinline__ HitOut simulate_hit(const GeoLds& g, const LayerRec& lr, CumT cum,
                                                GuideT guide, float dr, uint32_t k0, uint32_t k1,
                                                uint32_t i, uint32_t l, uint32_t pin, uint32_t evg,
@@ -1066,6 +1089,24 @@ __device__ __forceinline__ HitOut simulate_hit(const GeoLds& g, const LayerRec& 
     HitOut h;
     h.bin = find_bin<kTask>(cum, guide, x.x, u0);
     const int ir = h.bin >> 3, ia = h.bin & 7;
+    if constexpr (kF64) {
+        // r = (ir + u1) dr and alpha = 2 pi (ia + u2) / 8, both in FP64;
+        // cos and sin from the FP64 series in turns (sin at t - 1/4)
+        const double rr = ((double)ir + (double)u1) * (double)dr;
+        const double t = ((double)ia + (double)u2) * 0.125;
+        const double cd = dcos_turns<2>(t);
+        const double sd = dcos_turns<2>(t - 0.25);
+        const double inv_r64 = (double)inv_r;
+        const double eta64 = (double)eta_p + (rr * cd) * inv_r64;
+        double phi64 = (double)phi_p + (rr * sd) * inv_r64;
+        const double pi64 = 3.14159265358979323846, two_pi64 = 6.28318530717958647692;
+        if (phi64 >= pi64) phi64 = phi64 - two_pi64;
+        else if (phi64 < -pi64) phi64 = phi64 + two_pi64;
+        h.eta = (float)eta64;
+        h.phi = (float)phi64;
+        h.cell = lookup_cell_f64(g, lr, (int)l, eta64, phi64);
+        return h;
+    }
     const float r = __builtin_fmaf(u1, dr, (float)ir * dr);  // lower edge + u1 * dr, one rounding
     float c, s;
     sincos_bin(ia, u2, c, s);
@@ -1393,6 +1434,7 @@ __device__ __forceinline__ bool next_item(const Params& P, WaveQueue& q, int& it
 // once as count * Ehit, one rounding per cell and chunk.  Tile hits that share an
 // (event, cell) with a leading lane are summed across the wave first; each
 // remaining sum goes to the event's cell with one device atomic.
+template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
@@ -1444,7 +1486,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
             const int hbits = hash_bits(ck.count);
             const long long hbase = P.want_hits ? (long long)G(P.task_hoff)[ck.t] : 0;
             for (int i = ck.first + lane; i < ck.first + ck.count; i += kWave) {
-                const HitOut h = simulate_hit<true>(geo, lrec, cum, guide, dr, k0, k1, (uint32_t)i,
+                const HitOut h = simulate_hit<true, kF64>(geo, lrec, cum, guide, dr, k0, k1, (uint32_t)i,
                                               (uint32_t)ck.l, ck.pin, ck.evg, ck.eta_p, ck.phi_p);
                 if (P.want_hits) write_hit(P, hbase + i, h, ck.ehit);
                 n_out += h.cell < 0 ? 1 : 0;
@@ -1478,7 +1520,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                 const bool valid = k < hcount;
                 const int kk = valid ? k : hcount - 1;
                 const SmallHit sh = small_hit(P, s0 + owners[kk], h0 + kk);
-                const HitOut h = simulate_hit<false>(geo, layer_rec(geo, sh.l),
+                const HitOut h = simulate_hit<false, kF64>(geo, layer_rec(geo, sh.l),
                                               G(P.cum) + (long long)sh.H * kBins,
                                               G(P.guide) + (long long)sh.H * kGuide, dr, k0, k1,
                                               (uint32_t)sh.i, (uint32_t)sh.l, sh.pin, sh.evg,
@@ -1544,6 +1586,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
 constexpr int kTaskSlots = 2 * kBlock;  // LDS cell slots of a workgroup
 static_assert(kTaskSlots == 512, "the slot hash takes 9 bits");
 
+template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_task_hits(const Params* __restrict__ Pp, int t)
 {
     const Params& P = *Pp;
@@ -1569,7 +1612,7 @@ __global__ __launch_bounds__(kBlock) void k_task_hits(const Params* __restrict__
         const uint32_t pin = (uint32_t)G(P.part_p)[gp];
         const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
         const Particle pt = load_particle(P.particles, gp);
-        const HitOut h = simulate_hit<false>(geo, layer_rec(geo, l), G(P.cum) + (long long)H * kBins,
+        const HitOut h = simulate_hit<false, kF64>(geo, layer_rec(geo, l), G(P.cum) + (long long)H * kBins,
                                              G(P.guide) + (long long)H * kGuide, P.r_max / 32.0f,
                                              P.key0, P.key1, (uint32_t)i, (uint32_t)l, pin, evg,
                                              pt.eta, pt.phi);

@@ -159,8 +159,9 @@ __device__ __noinline__ double dexp(double x)
     return q * __longlong_as_double((long long)(ki + 1023) << 52);
 }
 
-// cos(2 pi u), u in (0,1): exact quarter-turn reduction, then a Taylor
-// series of cos (to t^16) or sin (to t^17) on |t| <= pi/4
+// cos(2 pi u): exact quarter-turn reduction, then a Taylor series of cos (to
+// t^16) or sin (to t^17) on |t| <= pi/4; u in (0,1) for the normal draws and
+// in [-1/4, 1) for the FP64 placement (a negative quadrant taken modulo 4)
 template <int kCopy>
 __device__ __noinline__ double dcos_turns(double u)
 {

@@ -33,11 +33,11 @@ struct DevBuf {
 
 struct GraphKey {
     long long n_particles, n_events;
-    int mode, grid, part;
+    int mode, grid, part, f64;
     bool operator<(const GraphKey& o) const
     {
-        return std::tie(n_particles, n_events, mode, grid, part) <
-               std::tie(o.n_particles, o.n_events, o.mode, o.grid, o.part);
+        return std::tie(n_particles, n_events, mode, grid, part, f64) <
+               std::tie(o.n_particles, o.n_events, o.mode, o.grid, o.part, o.f64);
     }
 };
 
@@ -721,6 +721,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->scale = o->hit_energy_scale_mev;
     P->cap = o->nhit_cap;
     P->min_e = o->min_layer_energy_mev;
+    P->placement_f64 = o->placement_fp64 ? 1 : 0;
     P->chunk_hits = tu.chunk;
     P->big_thr = tu.big;
     P->tile_hits = tu.tile;
@@ -800,8 +801,10 @@ void enqueue_batch(fcs_ctx* c, const Params& P, int mode, int grid, int part)
             hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(fcsk::kScanThreads), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
     }
-    if (part == kAll || part == kHits)
-        hipLaunchKernelGGL(fcsk::k_hits, dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
+    if ((part == kAll || part == kHits) && P.placement_f64)
+        hipLaunchKernelGGL(fcsk::k_hits<true>, dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
+    else if (part == kAll || part == kHits)
+        hipLaunchKernelGGL(fcsk::k_hits<false>, dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
     if ((part == kAll || part == kPost) && mode == kDenseOnly) {
         const long long words = P.n_events << (P.blk_shift - 4);
         hipLaunchKernelGGL(fcsk::k_flags_reset,
@@ -867,7 +870,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
     c->q_valid = false;
     // a batched call over device inputs leaves a work queue an adjoint call
     // may reuse
-    const bool keep = !small_launch && o->inputs_on_device;
+    const bool keep = !small_launch && o->inputs_on_device && !o->placement_fp64;
     for (int attempt = 0; attempt < 2; ++attempt) {
         char* blk = ring_take(c);
         if (!blk) return fail(c, FCS_E_HIP, "hipEventSynchronize on a parameter block failed");
@@ -885,7 +888,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         std::memset(hc, 0, sizeof(Counters));
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
         if ((rc = ring_sent(c))) return rc;
-        GraphKey key{sh.n_particles, sh.n_events, mode, grid, kAll};
+        GraphKey key{sh.n_particles, sh.n_events, mode, grid, kAll, P->placement_f64};
         hipEvent_t k0 = c->ev_k0, k1 = c->ev_k1;
         if (profile && async) {
             // a free event pair for this call; the oldest pending one is read
@@ -916,10 +919,16 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             HIPCHK(c, hipStreamSynchronize(c->stream));
             const Params* dP = (const Params*)c->w_params.p;
             if (profile) HIPCHK(c, hipEventRecord(k0, c->stream));
-            for (long long t = 0; t < nt; ++t)
-                if (c->h_task_n[(size_t)t] > 0)
-                    hipLaunchKernelGGL(fcsk::k_task_hits, dim3(grid_for(c->h_task_n[(size_t)t], fcsk::kBlock)),
-                                       dim3(fcsk::kBlock), geo_lds_bytes(*P), c->stream, dP, (int)t);
+            for (long long t = 0; t < nt; ++t) {
+                if (c->h_task_n[(size_t)t] <= 0) continue;
+                const dim3 g(grid_for(c->h_task_n[(size_t)t], fcsk::kBlock));
+                if (P->placement_f64)
+                    hipLaunchKernelGGL(fcsk::k_task_hits<true>, g, dim3(fcsk::kBlock), geo_lds_bytes(*P),
+                                       c->stream, dP, (int)t);
+                else
+                    hipLaunchKernelGGL(fcsk::k_task_hits<false>, g, dim3(fcsk::kBlock), geo_lds_bytes(*P),
+                                       c->stream, dP, (int)t);
+            }
             if (profile) HIPCHK(c, hipEventRecord(k1, c->stream));
             enqueue_batch(c, *P, mode, grid, kPost);
             HIPCHK(c, hipGetLastError());
@@ -1397,6 +1406,9 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
     const bool async = o->async_launch != 0;
     if (async && (!o->inputs_on_device || o->n_particles <= 0))
         return fail(c, FCS_E_INVALID_ARG, "async_launch needs device inputs and n_particles");
+    if (o->placement_fp64)
+        return fail(c, FCS_E_INVALID_ARG, "placement_fp64 is a forward-only variant: the adjoint "
+                                          "recomputes hits with the FP32 placement");
     Inputs in;
     if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, false, &in))) return rc;
     const long long nt = in.N * c->n_layers;

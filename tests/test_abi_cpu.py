@@ -222,3 +222,21 @@ def test_launch_modes(F, dry):
     rc = F.lib().fcs_simulate_events(dry._h, p.ctypes.data, off.ctypes.data, 5, C.byref(o), C.byref(so))
     assert rc == F.FCS_E_INVALID_ARG
     assert "mode" in F.lib().fcs_last_error(dry._h).decode()
+
+
+def test_backward_refuses_fp64_placement(F, dry):
+    import ctypes as C
+    dry.load_geometry(W.make_geometry())
+    dry.load_parametrization(W.make_param())
+    w = W.single_particle_sweep(n_events=5)
+    o = F.FcsSimOptions()
+    F.lib().fcs_default_options(C.byref(o))
+    assert o.placement_fp64 == 0
+    o.placement_fp64 = 1
+    p = np.ascontiguousarray(w.particles)
+    off = np.ascontiguousarray(w.event_offsets)
+    g = np.zeros(5 * 191338, np.float32)
+    rc = F.lib().fcs_backward(dry._h, p.ctypes.data, off.ctypes.data, 5, C.byref(o), g.ctypes.data,
+                              None, None)
+    assert rc == F.FCS_E_INVALID_ARG
+    assert "placement_fp64" in F.lib().fcs_last_error(dry._h).decode()

@@ -538,3 +538,25 @@ def test_fine_binned_tables(torch_cuda, oracle_lib, geom_full, geo, fine_tables)
             check_parity(r, ref, geo, hits=False, label=f"{w.name}, 64 x 64 tables")
     finally:
         s.close()
+
+
+# --------------------------------------------------- FP64 placement variant ---
+@pytest.mark.parametrize("case,mode", [("sweep", "batched"), ("hard_scatter", "batched"),
+                                       ("sweep", "per_event"), ("hard_scatter", "per_task")])
+def test_fp64_placement(sim, oracle_lib, geom_full, param_full, geo, torch_cuda, case, mode):
+    """The FP64 placement variant against the oracle's FP64 placement: hit
+    counts, positions and cells bit for bit, energies within tolerance; the
+    FP32 call that follows on the same context gives the FP32 results."""
+    if case == "sweep":
+        w, base = W.subset_events(W.single_particle_sweep(), 3000, 100), 3000
+    else:
+        w, base = W.subset_events(W.hard_scatter(), 40, 1), 40
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode,
+                      base=base, placement_fp64=True)
+    ref = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
+                              event_index_base=base, hit_energy_scale=w.hit_energy_scale,
+                              hit_list=True, placement_fp64=True)
+    check_parity(r, ref, geo, label=f"{case} {mode}, FP64 placement")
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode,
+                      base=base)
+    check_parity(r, ref, geo, label=f"{case} {mode}, FP32 after FP64")

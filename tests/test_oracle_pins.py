@@ -500,3 +500,58 @@ def test_grad_weights_matches_fd(oracle_lib, geom_full, param_full, diff_case):
     # the weight gradient is invariant to a common rescaling: sum_k w_k dW_k = 0
     wh = w0[H * 256:(H + 1) * 256]
     assert abs((wh * dW[H * 256:(H + 1) * 256]).sum()) <= 1e-9 * np.abs(wh * dW[H * 256:(H + 1) * 256]).sum()
+
+
+# ------------------------------------------------- FP64 placement variant ---
+def test_cos_turns_on_the_placement_domain(oracle_lib):
+    """The FP64 placement takes cos(2 pi t) and sin(2 pi t) = cos(2 pi (t - 1/4))
+    for t = (ia + u) / 8 in [0, 1), so the series runs on [-1/4, 1): against
+    an extended-precision reference, and sine/cosine identities."""
+    rng = np.random.default_rng(11)
+    ia = rng.integers(0, 8, 100000)
+    u = rng.integers(0, 2 ** 24, 100000) * 2.0 ** -24
+    t = (ia + u) * 0.125
+    c = oracle_lib.cos_turns(t)
+    s = oracle_lib.cos_turns(t - 0.25)
+    two_pi = np.arctan(np.longdouble(1)) * 8
+    tl = t.astype(np.longdouble)
+    assert np.max(np.abs(c - np.cos(two_pi * tl).astype(np.float64))) <= 4 * 2.0 ** -53
+    assert np.max(np.abs(s - np.sin(two_pi * tl).astype(np.float64))) <= 4 * 2.0 ** -53
+    assert np.max(np.abs(c * c + s * s - 1.0)) <= 8 * 2.0 ** -53
+    # the eight bin edges: exact at the quarter turns, sqrt(1/2) between
+    e = np.arange(8) * 0.125
+    ce, se = oracle_lib.cos_turns(e), oracle_lib.cos_turns(e - 0.25)
+    assert np.array_equal(ce[[0, 4]], [1.0, -1.0]) and np.array_equal(se[[2, 6]], [1.0, -1.0])
+    assert np.allclose(np.abs(ce[1::2]), np.sqrt(0.5), rtol=0, atol=2e-16)
+
+
+def test_fp64_placement_reduces_to_the_fp32_contract(oracle_lib, geom_full, param_full):
+    """The FP64 placement is the FP32 hit chain without its roundings: the
+    same hits (counts, bins, energies), positions within FP32 rounding of
+    the FP32 ones, and every hit whose cell differs lies within that
+    rounding of a cell edge (the cell of the FP32 position is reached by
+    moving the FP64 position by at most 2e-6 in eta or phi)."""
+    w = W.subset_events(W.single_particle_sweep(), 3000, 150)
+    kw = dict(event_index_base=3000, hit_list=True)
+    a = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed, **kw)
+    b = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
+                            placement_fp64=True, **kw)
+    assert np.array_equal(a["n"], b["n"]) and a["n_hits_total"] == b["n_hits_total"]
+    ha, hb = a["hits"], b["hits"]
+    assert np.array_equal(ha["bin"], hb["bin"]) and np.array_equal(ha["e"], hb["e"])
+    deta = np.abs(ha["eta"].astype(np.float64) - hb["eta"])
+    dphi = np.abs(ha["phi"].astype(np.float64) - hb["phi"])
+    dphi = np.minimum(dphi, np.abs(dphi - 2 * np.pi))  # a wrap taken on one side only
+    assert deta.max() <= 1e-6 and dphi.max() <= 1e-6, (deta.max(), dphi.max())
+    assert deta.max() > 0  # the two placements do differ in their roundings
+    diff = np.nonzero(ha["cell"] != hb["cell"])[0]
+    nh = a["n_hits_total"]
+    print(f"[pins] FP64 vs FP32 placement: {len(diff)} of {nh} hits change cell", flush=True)
+    assert len(diff) <= 1e-4 * nh
+    L = param_full.n_layers
+    layer = np.repeat(np.tile(np.arange(L, dtype=np.int32), len(w.particles)), a["n"])
+    for k in diff:
+        cand = {int(oracle_lib.lookup(geom_full, [layer[k]], [hb["eta"][k] + de],
+                                      [hb["phi"][k] + dp])[0])
+                for de in (-2e-6, 0.0, 2e-6) for dp in (-2e-6, 0.0, 2e-6)}
+        assert int(ha["cell"][k]) in cand, (k, ha["cell"][k], hb["cell"][k], cand)
