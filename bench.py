@@ -6,11 +6,16 @@ ordered compaction and accumulator reset), inputs and outputs resident in
 device memory.  The headline workload is the single-particle sweep: 10,000
 events of one e/gamma/pi+- each, E log-uniform 1 GeV - 4 TeV, |eta| < 2.5.
 
-Also reported on the same JSON line: the per-event launch form of the same
-workload (one launch sequence and one host synchronization per event), the
-forward+backward throughput of the differentiable workload (64 single pions),
-the batched throughput of the multi-particle workloads, the roofline of the
-hit kernel and the CPU oracle timed on the host.
+Also reported on the same JSON line: the same batch as synchronous calls;
+the per-event launch form (one launch sequence and one host synchronization
+per event) and the per-(particle, layer) launch form (on a slice); the
+forward+backward throughput of the differentiable workload (64 single
+pions); the multi-particle workloads (hard scatter, pile-up) in the batched
+and per-event forms; several jobs sharing the GPU (1 to 16 contexts on host
+threads); the headline batch on 64 x 64-bin tables and with the FP64
+placement variant (with the count of hits that change cell); the roofline
+of the hit kernel; and the CPU oracle timed on the host (one thread and
+threads over event ranges).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
