@@ -94,7 +94,7 @@ def _time_steps(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) / steps, res
 
 
-def run_fwd_bwd(torch, sim, geo, par, dev, steps, warmup):
+def run_fwd_bwd(torch, sim, geo, par, dev, steps, warmup, tuning=None):
     """Forward (dense cells through the autograd binding) + loss + backward
     (the adjoint) on the 64-pion workload; hits of one forward per second.
     Training steps are enqueued back to back (asynchronous library calls, no
@@ -117,6 +117,11 @@ def run_fwd_bwd(torch, sim, geo, par, dev, steps, warmup):
     target = sim.simulate_events(dpd, doffd, wd.seed, outputs=("dense",),
                                  elayer_override=pert)["cells"]
     from paper_2103_14737_amd.autograd import simulate_dense
+    # The library's default tuning: the step is bound by its launches and by
+    # the loss's passes over the dense cells (measured the same, within
+    # noise, for chunks of 64 to 2048 hits, tiles of 256 or 512 and 4 or 8
+    # workgroups per CU).
+    tuning = tuning or {}
     el_leaf = el.detach().clone().requires_grad_()
     wt_leaf = torch.from_numpy(par["weights"]).to(dev).requires_grad_()
     nh = int(base["stats"]["n_hits"])
@@ -127,7 +132,7 @@ def run_fwd_bwd(torch, sim, geo, par, dev, steps, warmup):
         el_leaf.grad = None
         wt_leaf.grad = None
         cells = simulate_dense(sim, dpd, doffd, wd.seed, el_leaf, wt_leaf,
-                               async_launch=async_launch)
+                               async_launch=async_launch, **tuning)
         loss = F.mse_loss(cells, target, reduction="sum")
         loss.backward()
         return nh
@@ -144,7 +149,7 @@ def run_fwd_bwd(torch, sim, geo, par, dev, steps, warmup):
         wt_leaf.grad = None
         torch.cuda.synchronize()
         a = time.perf_counter()
-        cells = simulate_dense(sim, dpd, doffd, wd.seed, el_leaf, wt_leaf)
+        cells = simulate_dense(sim, dpd, doffd, wd.seed, el_leaf, wt_leaf, **tuning)
         loss = F.mse_loss(cells, target, reduction="sum")
         torch.cuda.synchronize()
         b = time.perf_counter()
@@ -155,8 +160,10 @@ def run_fwd_bwd(torch, sim, geo, par, dev, steps, warmup):
     res = {"workload": "single_pion_diff", "n_events": wd.n_events,
            "hits_per_step": nh, "hits_per_s": nh / t_fb, "ms_per_step": t_fb * 1e3,
            "synchronized_step": {"t_fwd_ms": times["fwd"] / steps * 1e3,
-                                 "t_bwd_ms": times["bwd"] / steps * 1e3}}
-    print(f"bench: fwd+bwd {nh / t_fb:.4g} hits/s ({t_fb * 1e3:.3f} ms/step)", flush=True)
+                                 "t_bwd_ms": times["bwd"] / steps * 1e3},
+           "tuning": tuning or "library defaults"}
+    print(f"bench: fwd+bwd {nh / t_fb:.4g} hits/s ({t_fb * 1e3:.3f} ms/step), tuning {tuning}",
+          flush=True)
     return res
 
 
@@ -454,7 +461,12 @@ def main():
     load_ms = (time.perf_counter() - t0) * 1e3
 
     if args.fwd_bwd_only:
-        print(json.dumps(run_fwd_bwd(torch, sim, geo, par, dev, args.steps, args.warmup)), flush=True)
+        tun = None
+        if args.tuning:
+            c_, b_, t_, w_ = (int(x) for x in args.tuning.split(","))
+            tun = dict(chunk_hits=c_, big_task_hits=b_, tile_hits=t_, wg_per_cu=w_)
+        print(json.dumps(run_fwd_bwd(torch, sim, geo, par, dev, args.steps, args.warmup, tun)),
+              flush=True)
         return 0
     if args.sharing_only:
         print(json.dumps(run_sharing(torch, geo, par, dev)), flush=True)
