@@ -12,8 +12,9 @@ per event) and the per-(particle, layer) launch form (on a slice); the
 forward+backward throughput of the differentiable workload (64 single
 pions); the multi-particle workloads (hard scatter, pile-up) in the batched
 and per-event forms; several jobs sharing the GPU (1 to 16 contexts on host
-threads); the headline batch on 64 x 64-bin tables and with the FP64
-placement variant (with the count of hits that change cell); the roofline
+threads); the headline batch on 64 x 64-bin tables, with the FP64
+placement variant (with the count of hits that change cell) and with the
+per-hit energy fluctuation variant; the roofline
 of the hit kernel; and the CPU oracle timed on the host (one thread and
 threads over event ranges).
 
@@ -412,6 +413,41 @@ def run_fp64_placement(torch, sim, w, dp, doff, out, cap, tuning, steps, warmup,
             "of_which_acceptance": out_only, "rate": changed / hits}
 
 
+def run_hit_fluct(torch, sim, w, dp, doff, out, cap, tuning, steps, warmup, fp32_hits_per_s):
+    """The per-hit energy fluctuation variant on the headline batch: its
+    throughput (compact output, steps back to back as the headline) and the
+    batch's deposited energy against the constant-energy chain (equal on
+    average: the factor has mean 1)."""
+    def step(**kw):
+        sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap, out=out,
+                            hit_energy_scale=w.hit_energy_scale, async_launch=True,
+                            hit_energy_fluct=True, **tuning, **kw)
+
+    for _ in range(warmup):
+        step()
+    sim.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    st = sim.synchronize()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    hits = st["n_hits"] // steps
+    energy = {}
+    for fl in (False, True):
+        r = sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap,
+                                out=out, hit_energy_scale=w.hit_energy_scale, hit_energy_fluct=fl,
+                                **tuning)
+        nnz = int(r["stats"]["n_cells_nonzero"])
+        energy[fl] = float(out["cell_e"][:nnz].double().sum().item())
+    print(f"bench: energy fluctuation {hits / dt:.4g} hits/s; deposited energy "
+          f"{energy[True] / energy[False]:.6f} x the constant-energy chain", flush=True)
+    return {"hits_per_step": hits, "ms_per_step": dt * 1e3, "hits_per_s": hits / dt,
+            "fp32_over_variant": fp32_hits_per_s / (hits / dt),
+            "energy_over_constant": energy[True] / energy[False]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -497,6 +533,8 @@ def main():
         dp, doff, out, cap, q = prepare(w)
         print(json.dumps(run_fp64_placement(torch, sim, w, dp, doff, out, cap, {}, args.steps,
                                             args.warmup, float("nan"))), flush=True)
+        print(json.dumps(run_hit_fluct(torch, sim, w, dp, doff, out, cap, {}, args.steps,
+                                       args.warmup, float("nan"))), flush=True)
         return 0
 
     # ------------------------------------------------ headline: batched sweep
@@ -676,6 +714,8 @@ def main():
         line["fine_tables"] = run_fine_tables(torch, geo, dev, w, tuning, args.steps, args.warmup)
         line["placement_fp64"] = run_fp64_placement(torch, sim, w, dp, doff, out, cap, tuning,
                                                     args.steps, args.warmup, value)
+        line["hit_energy_fluct"] = run_hit_fluct(torch, sim, w, dp, doff, out, cap, tuning,
+                                                 args.steps, args.warmup, value)
 
     if args.copy_probe_mb:
         # a plain device copy of known size: the HBM counters of the profiled

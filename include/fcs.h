@@ -243,6 +243,17 @@ typedef struct {
                                    Hit positions are returned rounded to
                                    FP32.  fcs_backward refuses it
                                    (FCS_E_INVALID_ARG).  Default 0.         */
+    int32_t hit_energy_fluct;    /* fcs_simulate_events: 1 = every hit gets
+                                   the energy Ehit * x with x = -ln u,
+                                   u = ((w >> 8) + 1/2) 2^-24 from the
+                                   fourth word of the hit's Philox draw (an
+                                   exponential factor of mean 1; x in FP64,
+                                   one rounding to FP32): a chain variant
+                                   with a per-hit energy stage in place of
+                                   the constant Ehit.  A task's energy is
+                                   then conserved on average only.  Not
+                                   with placement_fp64; fcs_backward
+                                   refuses it.  Default 0.                  */
 } fcs_sim_options;
 
 /* Fill *opt with the defaults: seed 0, batched, compact output, 100 MeV per

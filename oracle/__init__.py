@@ -46,7 +46,7 @@ class OgOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("event_index_base", C.c_uint64),
                 ("hit_energy_scale", C.c_float), ("nhit_cap", C.c_int32),
                 ("min_layer_energy", C.c_double), ("elayer_override", C.c_void_p),
-                ("placement_fp64", C.c_int32)]
+                ("placement_fp64", C.c_int32), ("hit_energy_fluct", C.c_int32)]
 
 
 class OgOut(C.Structure):
@@ -158,10 +158,11 @@ class Param:
 
 
 def make_opts(seed, event_index_base=0, hit_energy_scale=100.0, nhit_cap=20000,
-              min_layer_energy=1e-6, elayer_override=None, placement_fp64=False):
+              min_layer_energy=1e-6, elayer_override=None, placement_fp64=False,
+              hit_energy_fluct=False):
     ov = None if elayer_override is None else np.ascontiguousarray(elayer_override, np.float32)
     o = OgOpts(seed, event_index_base, hit_energy_scale, nhit_cap, min_layer_energy, _p(ov),
-               1 if placement_fp64 else 0)
+               1 if placement_fp64 else 0, 1 if hit_energy_fluct else 0)
     o._keep = ov
     return o
 
@@ -169,18 +170,19 @@ def make_opts(seed, event_index_base=0, hit_energy_scale=100.0, nhit_cap=20000,
 def simulate(geom: Geometry, param: Param, particles, event_offsets, seed, event_index_base=0,
              hit_energy_scale=100.0, nhit_cap=20000, min_layer_energy=1e-6,
              elayer_override=None, hit_list=False, cell_cap=None, hit_cap=None,
-             placement_fp64=False):
+             placement_fp64=False, hit_energy_fluct=False):
     """Run the oracle.  Returns a dict of numpy arrays: per-task n/elayer/ehit/
     set, per-event sparse cells (ev_cell_off, cell_idx, cell_e, cell_cnt),
     optional hit list, and stats.  placement_fp64: the hits placed and
-    looked up in FP64 (chain variant)."""
+    looked up in FP64; hit_energy_fluct: an exponential per-hit energy
+    factor (chain variants)."""
     parts = np.ascontiguousarray(particles)
     off = np.ascontiguousarray(event_offsets, np.int64)
     n_ev = len(off) - 1
     N = len(parts)
     L = param.n_layers
     opts = make_opts(seed, event_index_base, hit_energy_scale, nhit_cap, min_layer_energy,
-                     elayer_override, placement_fp64)
+                     elayer_override, placement_fp64, hit_energy_fluct)
     res = {"n": np.zeros(N * L, np.int32), "elayer": np.zeros(N * L, np.float64),
            "ehit": np.zeros(N * L, np.float32), "set": np.zeros(N * L, np.int32)}
     while True:

@@ -69,6 +69,7 @@ typedef struct {
     double min_layer_energy;    /* layers below this energy get no hits */
     const float *elayer_override; /* [N * L] or NULL */
     int32_t placement_fp64;     /* 1: place hits in FP64 (chain variant) */
+    int32_t hit_energy_fluct;   /* 1: per-hit energy factor (chain variant) */
 } og_opts;
 
 typedef struct {
@@ -468,6 +469,7 @@ int32_t oracle_lookup(const og_geom *G, int32_t layer, float eta, float phi)
 typedef struct {
     float eta, phi;
     int32_t bin, cell;
+    uint32_t w4; /* the draw's fourth word */
 } og_hit;
 
 static og_hit one_hit(const og_geom *G, const float *cum, float r_max, uint64_t seed,
@@ -480,6 +482,7 @@ static og_hit one_hit(const og_geom *G, const float *cum, float r_max, uint64_t 
     draw(seed, i, layer | (TAG_HIT << 8), p, ev, x);
     float u0 = u24(x[0]), u1 = u24(x[1]), u2 = u24(x[2]);
     og_hit h;
+    h.w4 = x[3];
     h.bin = oracle_find_bin(cum, u0);
     int32_t ir = h.bin >> 3, ia = h.bin & 7;
     float dr = r_max / 32.0f;
@@ -539,6 +542,7 @@ static og_hit one_hit_f64(const og_geom *G, const float *cum, float r_max, uint6
     draw(seed, i, layer | (TAG_HIT << 8), p, ev, x);
     float u0 = u24(x[0]), u1 = u24(x[1]), u2 = u24(x[2]);
     og_hit h;
+    h.w4 = x[3];
     h.bin = oracle_find_bin(cum, u0);
     int32_t ir = h.bin >> 3, ia = h.bin & 7;
     double r = ((double)ir + (double)u1) * (double)(r_max / 32.0f);
@@ -554,6 +558,16 @@ static og_hit one_hit_f64(const og_geom *G, const float *cum, float r_max, uint6
     h.phi = (float)phi;
     h.cell = lookup_f64(G, (int32_t)layer, eta, phi);
     return h;
+}
+
+/* Per-hit energy fluctuation (a chain variant of the constant Ehit of
+ * Listing 1): the hit's energy is Ehit * x with x = -ln u exponential of
+ * mean 1, u = ((w4 >> 8) + 1/2) 2^-24 from the draw's unused fourth word,
+ * x in FP64 with oracle_log, one rounding to FP32. */
+static float fluct_energy(float ehit, uint32_t w4)
+{
+    double u = ((double)(w4 >> 8) + 0.5) * 0x1p-24;
+    return (float)((double)ehit * -oracle_log(u));
 }
 
 /* exported single-hit evaluation for tests */
@@ -652,13 +666,15 @@ int oracle_simulate(const og_geom *G, const og_param *P, const og_particle *part
                                                  p, ev, pt->eta, pt->phi)
                                    : one_hit(G, cum, P->r_max, O->seed, (uint32_t)i, (uint32_t)l, p,
                                              ev, pt->eta, pt->phi);
+                    const float e_hit = O->hit_energy_fluct ? fluct_energy(S.ehit[l], h.w4)
+                                                            : S.ehit[l];
                     out->n_hits_total++;
                     if (h.cell < 0) {
                         out->n_out_of_acc++;
                     } else {
                         if (cellN[h.cell] == 0) touched[n_touched++] = h.cell;
                         cellN[h.cell] += 1;
-                        cellE[h.cell] += (double)S.ehit[l];
+                        cellE[h.cell] += (double)e_hit;
                     }
                     if (out->hit_eta) {
                         if (nhit_out >= out->hit_cap) {
@@ -666,7 +682,7 @@ int oracle_simulate(const og_geom *G, const og_param *P, const og_particle *part
                         } else {
                             out->hit_eta[nhit_out] = h.eta;
                             out->hit_phi[nhit_out] = h.phi;
-                            out->hit_e[nhit_out] = S.ehit[l];
+                            out->hit_e[nhit_out] = e_hit;
                             out->hit_cell[nhit_out] = h.cell;
                             if (out->hit_bin) out->hit_bin[nhit_out] = h.bin;
                         }

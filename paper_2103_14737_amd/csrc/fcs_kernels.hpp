@@ -123,6 +123,7 @@ struct Params {
     int32_t n_scan_groups;
     int32_t setup_sub;     // scan blocks per setup workgroup
     int32_t placement_f64; // hit kernels place hits in FP64 (chain variant)
+    int32_t hit_fluct;     // per-hit energy fluctuation (chain variant)
     int32_t validate;      // check device-resident inputs in the setup
     int32_t n_seg_groups;  // groups of kSegGroup segments
     // workspace
@@ -1069,6 +1070,7 @@ __device__ __forceinline__ int find_bin(CumT cum, GuideT guide, uint32_t x0, flo
 struct HitOut {
     float eta, phi;
     int cell, bin;
+    uint32_t w4;  // the counter's fourth word (the energy fluctuation's uniform)
 };
 
 // one hit: counter (i, layer | 3 << 8, particle in event, global event)
@@ -1087,6 +1089,7 @@ __device__ __forceinline__ HitOut simulate_hit(const GeoLds& g, const LayerRec& 
                        : philox4x32_10(i, l | (kTagHit << 8), pin, evg, k0, k1);
     const float u0 = unit24(x.x), u1 = unit24(x.y), u2 = unit24(x.z);
     HitOut h;
+    h.w4 = x.w;
     h.bin = find_bin<kTask>(cum, guide, x.x, u0);
     const int ir = h.bin >> 3, ia = h.bin & 7;
     if constexpr (kF64) {
@@ -1362,6 +1365,46 @@ __device__ __forceinline__ void wave_hash_flush(const Params& P, uint32_t* hkey,
     }
 }
 
+// ------------------------------------------- per-hit energy fluctuation ---
+// A chain variant: the hit's energy is Ehit x with x = -ln u exponential
+// (mean 1), u = ((w4 >> 8) + 1/2) 2^-24 from the counter's fourth word, x in
+// FP64 with the setup's log series, one rounding to FP32.
+__device__ __forceinline__ float fluct_energy(float ehit, uint32_t w4)
+{
+    const double u = ((double)(w4 >> 8) + 0.5) * 0x1p-24;
+    return (float)((double)ehit * -dlog<2>(u));
+}
+
+// the chunk path's hash with FP64 energy sums per slot (the variant's
+// energies differ per hit, so counts x Ehit do not apply)
+__device__ __forceinline__ void wave_hash_add_e(const Params& P, uint32_t* hkey, double* hsum,
+                                                int bits, uint32_t key, float e, long long ev)
+{
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t slot = (uint32_t)__umul24(key, 0x9E3779u) >> (32 - bits);
+    for (int pr = 0; pr < kHashProbes; ++pr) {
+        const uint32_t old = atomicCAS(&hkey[slot], kEmpty, key);
+        if (old == kEmpty || old == key) {
+            atomicAdd(&hsum[slot], (double)e);
+            return;
+        }
+        slot = (slot + 1) & mask;
+    }
+    deposit(P, ev, (int)key, e);
+}
+
+__device__ __forceinline__ void wave_hash_flush_e(const Params& P, uint32_t* hkey, double* hsum,
+                                                  int bits, long long ev)
+{
+    for (int k = lane_id(); k < (1 << bits); k += kWave) {
+        const uint32_t key = hkey[k];
+        if (key == kEmpty) continue;
+        deposit(P, ev, (int)key, (float)hsum[k]);
+        hkey[k] = kEmpty;
+        hsum[k] = 0.0;
+    }
+}
+
 // ----------------------------------------------------------- work queue ---
 // The items are split into kQueues contiguous ranges with one ticket counter
 // each.  A wave starts on the range of its workgroup's slot (workgroups are
@@ -1434,13 +1477,15 @@ __device__ __forceinline__ bool next_item(const Params& P, WaveQueue& q, int& it
 // once as count * Ehit, one rounding per cell and chunk.  Tile hits that share an
 // (event, cell) with a leading lane are summed across the wave first; each
 // remaining sum goes to the event's cell with one device atomic.
-template <bool kF64>
+template <bool kF64, bool kFluct>
 __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
     extern __shared__ v4i s_geo[];
     __shared__ uint32_t w_key[kWavesPerBlock][kWaveSlots];
     __shared__ uint32_t w_cnt2[kWavesPerBlock][kWaveSlots / 2];
+    // energy fluctuation variant: FP64 energy sums per hash slot
+    __shared__ double w_esum[kFluct ? kWavesPerBlock : 1][kFluct ? kWaveSlots : 1];
     __shared__ float w_cum[kWavesPerBlock][kBins];
     __shared__ v4i w_guide16[kWavesPerBlock][kGuide / 16 + 1];  // + the pad entry
 
@@ -1448,6 +1493,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     const int wv = threadIdx.x / kWave;
     uint32_t* hkey = w_key[wv];
     uint32_t* hcnt2 = w_cnt2[wv];
+    double* hsum = w_esum[kFluct ? wv : 0];
     uint16_t* owners = reinterpret_cast<uint16_t*>(hkey);  // tiles only
     float* cum = w_cum[wv];
     const uint8_t* guide = reinterpret_cast<const uint8_t*>(w_guide16[wv]);
@@ -1468,6 +1514,8 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     const GeoLds geo = stage_geometry(P, s_geo);
     for (int s = lane; s < kWaveSlots; s += kWave) hkey[s] = kEmpty;
     for (int s = lane; s < kWaveSlots / 2; s += kWave) hcnt2[s] = 0;
+    if constexpr (kFluct)
+        for (int s = lane; s < kWaveSlots; s += kWave) hsum[s] = 0.0;
     if (lane == 0) reinterpret_cast<uint8_t*>(w_guide16[wv])[kGuide] = kBins - 1;  // the pad entry
     __syncthreads();
 
@@ -1488,8 +1536,14 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
             for (int i = ck.first + lane; i < ck.first + ck.count; i += kWave) {
                 const HitOut h = simulate_hit<true, kF64>(geo, lrec, cum, guide, dr, k0, k1, (uint32_t)i,
                                               (uint32_t)ck.l, ck.pin, ck.evg, ck.eta_p, ck.phi_p);
-                if (P.want_hits) write_hit(P, hbase + i, h, ck.ehit);
                 n_out += h.cell < 0 ? 1 : 0;
+                if constexpr (kFluct) {
+                    const float e = fluct_energy(ck.ehit, h.w4);
+                    if (P.want_hits) write_hit(P, hbase + i, h, e);
+                    if (h.cell >= 0) wave_hash_add_e(P, hkey, hsum, hbits, (uint32_t)h.cell, e, ck.ev);
+                    continue;
+                }
+                if (P.want_hits) write_hit(P, hbase + i, h, ck.ehit);
                 bool pending = h.cell >= 0;
                 // the lanes in the first pending lane's cell (often the
                 // shower core) are counted with one insert
@@ -1508,7 +1562,8 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                     wave_hash_add(P, hkey, hcnt2, hbits, (uint32_t)h.cell, 1u, ck.ev, ck.ehit);
             }
             wave_sync();
-            wave_hash_flush(P, hkey, hcnt2, hbits, ck.ev, ck.ehit);
+            if constexpr (kFluct) wave_hash_flush_e(P, hkey, hsum, hbits, ck.ev);
+            else wave_hash_flush(P, hkey, hcnt2, hbits, ck.ev, ck.ehit);
             wave_sync();
         } else {
             // ------------------------------------------ tile of small tasks
@@ -1525,8 +1580,9 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                                               G(P.guide) + (long long)sh.H * kGuide, dr, k0, k1,
                                               (uint32_t)sh.i, (uint32_t)sh.l, sh.pin, sh.evg,
                                               sh.eta_p, sh.phi_p);
+                const float e_hit = kFluct ? fluct_energy(sh.ehit, h.w4) : sh.ehit;
                 if (valid && P.want_hits)
-                    write_hit(P, (long long)G(P.task_hoff)[sh.t] + sh.i, h, sh.ehit);
+                    write_hit(P, (long long)G(P.task_hoff)[sh.t] + sh.i, h, e_hit);
                 n_out += (valid && h.cell < 0) ? 1 : 0;
                 // The step's hits are summed per (event, cell) in the wave's
                 // LDS table; the lane that claims a slot deposits its sum, so
@@ -1541,7 +1597,7 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                 if (valid && h.cell >= 0) {
                     owner = tile_slot(tkey, ((unsigned long long)(uint32_t)sh.ev << 32) | (uint32_t)h.cell,
                                       tile_hash((uint32_t)h.cell, (uint32_t)sh.ev), slot);
-                    atomicAdd(&tval[slot], sh.ehit);
+                    atomicAdd(&tval[slot], e_hit);
                 }
                 wave_sync();
                 const float v = owner ? tval[slot] : 0.0f;
@@ -1586,18 +1642,20 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
 constexpr int kTaskSlots = 2 * kBlock;  // LDS cell slots of a workgroup
 static_assert(kTaskSlots == 512, "the slot hash takes 9 bits");
 
-template <bool kF64>
+template <bool kF64, bool kFluct>
 __global__ __launch_bounds__(kBlock) void k_task_hits(const Params* __restrict__ Pp, int t)
 {
     const Params& P = *Pp;
     extern __shared__ v4i s_geo[];
     __shared__ int s_cell[kTaskSlots];
     __shared__ uint32_t s_cnt[kTaskSlots];
+    __shared__ double s_esum[kFluct ? kTaskSlots : 1];  // energy fluctuation variant
     if (G(P.ctr)->error & (kErrTooManyHits | kErrChunkCap)) return;
     const GeoLds geo = stage_geometry(P, s_geo);
     for (int k = threadIdx.x; k < kTaskSlots; k += kBlock) {
         s_cell[k] = -1;
         s_cnt[k] = 0u;
+        if constexpr (kFluct) s_esum[k] = 0.0;
     }
     __syncthreads();
     const int L = P.n_layers;
@@ -1616,7 +1674,8 @@ __global__ __launch_bounds__(kBlock) void k_task_hits(const Params* __restrict__
                                              G(P.guide) + (long long)H * kGuide, P.r_max / 32.0f,
                                              P.key0, P.key1, (uint32_t)i, (uint32_t)l, pin, evg,
                                              pt.eta, pt.phi);
-        if (P.want_hits) write_hit(P, (long long)G(P.task_hoff)[t] + i, h, ehit);
+        const float e_hit = kFluct ? fluct_energy(ehit, h.w4) : ehit;
+        if (P.want_hits) write_hit(P, (long long)G(P.task_hoff)[t] + i, h, e_hit);
         if (h.cell < 0) {
             n_out = 1;
         } else {
@@ -1628,11 +1687,12 @@ __global__ __launch_bounds__(kBlock) void k_task_hits(const Params* __restrict__
                 k = (k + 1) & (kTaskSlots - 1);
             }
             atomicAdd(&s_cnt[k], 1u);
+            if constexpr (kFluct) atomicAdd(&s_esum[k], (double)e_hit);
         }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kTaskSlots; k += kBlock)
-        if (s_cnt[k]) deposit(P, ev, s_cell[k], (float)s_cnt[k] * ehit);
+        if (s_cnt[k]) deposit(P, ev, s_cell[k], kFluct ? (float)s_esum[k] : (float)s_cnt[k] * ehit);
     const long long tot = block_sum_ll(n_out);
     if (threadIdx.x == 0 && tot) (void)gfetch_add(&G(P.ctr)->hits_out, tot);
 }

@@ -722,6 +722,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->cap = o->nhit_cap;
     P->min_e = o->min_layer_energy_mev;
     P->placement_f64 = o->placement_fp64 ? 1 : 0;
+    P->hit_fluct = o->hit_energy_fluct ? 1 : 0;
     P->chunk_hits = tu.chunk;
     P->big_thr = tu.big;
     P->tile_hits = tu.tile;
@@ -802,9 +803,11 @@ void enqueue_batch(fcs_ctx* c, const Params& P, int mode, int grid, int part)
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
     }
     if ((part == kAll || part == kHits) && P.placement_f64)
-        hipLaunchKernelGGL(fcsk::k_hits<true>, dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
+        hipLaunchKernelGGL((fcsk::k_hits<true, false>), dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
+    else if ((part == kAll || part == kHits) && P.hit_fluct)
+        hipLaunchKernelGGL((fcsk::k_hits<false, true>), dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
     else if (part == kAll || part == kHits)
-        hipLaunchKernelGGL(fcsk::k_hits<false>, dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
+        hipLaunchKernelGGL((fcsk::k_hits<false, false>), dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
     if ((part == kAll || part == kPost) && mode == kDenseOnly) {
         const long long words = P.n_events << (P.blk_shift - 4);
         hipLaunchKernelGGL(fcsk::k_flags_reset,
@@ -870,7 +873,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
     c->q_valid = false;
     // a batched call over device inputs leaves a work queue an adjoint call
     // may reuse
-    const bool keep = !small_launch && o->inputs_on_device && !o->placement_fp64;
+    const bool keep = !small_launch && o->inputs_on_device && !o->placement_fp64 && !o->hit_energy_fluct;
     for (int attempt = 0; attempt < 2; ++attempt) {
         char* blk = ring_take(c);
         if (!blk) return fail(c, FCS_E_HIP, "hipEventSynchronize on a parameter block failed");
@@ -888,7 +891,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         std::memset(hc, 0, sizeof(Counters));
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
         if ((rc = ring_sent(c))) return rc;
-        GraphKey key{sh.n_particles, sh.n_events, mode, grid, kAll, P->placement_f64};
+        GraphKey key{sh.n_particles, sh.n_events, mode, grid, kAll, P->placement_f64 + 2 * P->hit_fluct};
         hipEvent_t k0 = c->ev_k0, k1 = c->ev_k1;
         if (profile && async) {
             // a free event pair for this call; the oldest pending one is read
@@ -923,11 +926,14 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
                 if (c->h_task_n[(size_t)t] <= 0) continue;
                 const dim3 g(grid_for(c->h_task_n[(size_t)t], fcsk::kBlock));
                 if (P->placement_f64)
-                    hipLaunchKernelGGL(fcsk::k_task_hits<true>, g, dim3(fcsk::kBlock), geo_lds_bytes(*P),
-                                       c->stream, dP, (int)t);
+                    hipLaunchKernelGGL((fcsk::k_task_hits<true, false>), g, dim3(fcsk::kBlock),
+                                       geo_lds_bytes(*P), c->stream, dP, (int)t);
+                else if (P->hit_fluct)
+                    hipLaunchKernelGGL((fcsk::k_task_hits<false, true>), g, dim3(fcsk::kBlock),
+                                       geo_lds_bytes(*P), c->stream, dP, (int)t);
                 else
-                    hipLaunchKernelGGL(fcsk::k_task_hits<false>, g, dim3(fcsk::kBlock), geo_lds_bytes(*P),
-                                       c->stream, dP, (int)t);
+                    hipLaunchKernelGGL((fcsk::k_task_hits<false, false>), g, dim3(fcsk::kBlock),
+                                       geo_lds_bytes(*P), c->stream, dP, (int)t);
             }
             if (profile) HIPCHK(c, hipEventRecord(k1, c->stream));
             enqueue_batch(c, *P, mode, grid, kPost);
@@ -1037,6 +1043,8 @@ int stage_inputs(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         return fail(c, FCS_E_INVALID_ARG, "min_layer_energy_mev must be finite and > 0");
     if (o->mode != FCS_MODE_BATCHED && o->mode != FCS_MODE_PER_EVENT && o->mode != FCS_MODE_PER_TASK)
         return fail(c, FCS_E_INVALID_ARG, "unknown mode %d", o->mode);
+    if (o->placement_fp64 && o->hit_energy_fluct)
+        return fail(c, FCS_E_INVALID_ARG, "placement_fp64 and hit_energy_fluct are exclusive");
     if (o->n_particles < 0) return fail(c, FCS_E_INVALID_ARG, "n_particles < 0");
     if (c->dry) {
         if (!o->inputs_on_device) {
@@ -1406,9 +1414,10 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
     const bool async = o->async_launch != 0;
     if (async && (!o->inputs_on_device || o->n_particles <= 0))
         return fail(c, FCS_E_INVALID_ARG, "async_launch needs device inputs and n_particles");
-    if (o->placement_fp64)
-        return fail(c, FCS_E_INVALID_ARG, "placement_fp64 is a forward-only variant: the adjoint "
-                                          "recomputes hits with the FP32 placement");
+    if (o->placement_fp64 || o->hit_energy_fluct)
+        return fail(c, FCS_E_INVALID_ARG, "placement_fp64 and hit_energy_fluct are forward-only "
+                                          "variants: the adjoint follows the FP32 chain with one "
+                                          "energy per task");
     Inputs in;
     if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, false, &in))) return rc;
     const long long nt = in.N * c->n_layers;

@@ -77,7 +77,8 @@ class FcsSimOptions(C.Structure):
                 ("inputs_on_device", C.c_int32), ("outputs_on_device", C.c_int32),
                 ("profile", C.c_int32), ("elayer_override", _vp), ("stream", _vp),
                 ("n_particles", C.c_int64), ("async_launch", C.c_int32),
-                ("reuse_forward_queue", C.c_int32), ("placement_fp64", C.c_int32)]
+                ("reuse_forward_queue", C.c_int32), ("placement_fp64", C.c_int32),
+                ("hit_energy_fluct", C.c_int32)]
 
 
 class FcsSimOutput(C.Structure):
@@ -277,7 +278,8 @@ class Simulator:
                         nhit_cap=20000, min_layer_energy=1e-6, chunk_hits=0, big_task_hits=0,
                         tile_hits=0, wg_per_cu=0, use_graph=True, elayer_override=None,
                         cell_capacity=None, hit_capacity=None, n_particles=None, out=None,
-                        profile=False, async_launch=False, placement_fp64=False):
+                        profile=False, async_launch=False, placement_fp64=False,
+                        hit_energy_fluct=False):
         """Run fcs_simulate_events.  Returns a dict of the requested outputs
         (numpy for host inputs, torch CUDA tensors for device inputs) and the
         statistics.  Capacities default to the sizes fcs_query_sizes
@@ -288,7 +290,9 @@ class Simulator:
         total), "stats" is None, and synchronize() reports errors and totals.
 
         placement_fp64: place the hits and look up their cells in FP64 (a
-        chain variant of the FP32 contract)."""
+        chain variant of the FP32 contract).  hit_energy_fluct: every hit's
+        energy is Ehit times an exponential factor of mean 1 (a chain
+        variant)."""
         p, off, ov, dev, stream, n_events = self._inputs(particles, event_offsets, elayer_override)
         N = (int(p.shape[0]) if dev else len(p)) if n_particles is None else n_particles
         o = self._options(seed, event_index_base, mode, outputs, hit_energy_scale, nhit_cap,
@@ -297,6 +301,7 @@ class Simulator:
                           async_launch=async_launch)
         o.profile = 1 if profile else 0
         o.placement_fp64 = 1 if placement_fp64 else 0
+        o.hit_energy_fluct = 1 if hit_energy_fluct else 0
         L = self.n_layers
         need_sizes = (("compact" in outputs and cell_capacity is None) or
                       ("hits" in outputs and hit_capacity is None))

@@ -240,3 +240,30 @@ def test_backward_refuses_fp64_placement(F, dry):
                               None, None)
     assert rc == F.FCS_E_INVALID_ARG
     assert "placement_fp64" in F.lib().fcs_last_error(dry._h).decode()
+
+
+def test_chain_variant_options(F, dry):
+    """The two chain variants exclude each other, and the adjoint refuses the
+    energy fluctuation."""
+    import ctypes as C
+    dry.load_geometry(W.make_geometry())
+    dry.load_parametrization(W.make_param())
+    w = W.single_particle_sweep(n_events=5)
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10, placement_fp64=True,
+                            hit_energy_fluct=True)
+    assert e.value.code == F.FCS_E_INVALID_ARG and "exclusive" in str(e.value)
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10, hit_energy_fluct=True)
+    assert e.value.code == F.FCS_E_NO_DEVICE  # valid: reaches the device step
+    o = F.FcsSimOptions()
+    F.lib().fcs_default_options(C.byref(o))
+    assert o.hit_energy_fluct == 0
+    o.hit_energy_fluct = 1
+    p = np.ascontiguousarray(w.particles)
+    off = np.ascontiguousarray(w.event_offsets)
+    g = np.zeros(5 * 191338, np.float32)
+    rc = F.lib().fcs_backward(dry._h, p.ctypes.data, off.ctypes.data, 5, C.byref(o), g.ctypes.data,
+                              None, None)
+    assert rc == F.FCS_E_INVALID_ARG
+    assert "hit_energy_fluct" in F.lib().fcs_last_error(dry._h).decode()

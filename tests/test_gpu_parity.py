@@ -560,3 +560,26 @@ def test_fp64_placement(sim, oracle_lib, geom_full, param_full, geo, torch_cuda,
     r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode,
                       base=base)
     check_parity(r, ref, geo, label=f"{case} {mode}, FP32 after FP64")
+
+
+# -------------------------------------------- energy fluctuation variant ---
+@pytest.mark.parametrize("case,mode", [("sweep", "batched"), ("hard_scatter", "batched"),
+                                       ("sweep", "per_event"), ("hard_scatter", "per_task")])
+def test_energy_fluctuation(sim, oracle_lib, geom_full, param_full, geo, torch_cuda, case, mode):
+    """The per-hit energy fluctuation variant against the oracle's: hit
+    energies bit for bit (same FP64 log series and rounding), cells and
+    counts exact, cell energies within tolerance; the constant-energy call
+    that follows on the same context gives the usual results."""
+    if case == "sweep":
+        w, base = W.subset_events(W.single_particle_sweep(), 4000, 100), 4000
+    else:
+        w, base = W.subset_events(W.hard_scatter(), 50, 1), 50
+    r, _ = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode,
+                    base=base, hit_energy_fluct=True)
+    ref = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
+                              event_index_base=base, hit_energy_scale=w.hit_energy_scale,
+                              hit_list=True, hit_energy_fluct=True)
+    check_parity(r, ref, geo, label=f"{case} {mode}, energy fluctuation")
+    r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode,
+                      base=base)
+    check_parity(r, ref, geo, label=f"{case} {mode}, constant energy after fluctuation")

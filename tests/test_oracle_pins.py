@@ -555,3 +555,51 @@ def test_fp64_placement_reduces_to_the_fp32_contract(oracle_lib, geom_full, para
                                       [hb["phi"][k] + dp])[0])
                 for de in (-2e-6, 0.0, 2e-6) for dp in (-2e-6, 0.0, 2e-6)}
         assert int(ha["cell"][k]) in cand, (k, ha["cell"][k], hb["cell"][k], cand)
+
+
+# ---------------------------------------------- per-hit energy fluctuation ---
+def test_energy_fluctuation_from_the_fourth_word(oracle_lib, geom_full, param_full):
+    """The fluctuation variant keeps every hit's counter, bin, position and
+    cell and replaces the constant Ehit by Ehit * x, x = -ln u with u from the
+    fourth word of the hit's Philox draw: recomputed here from the (pinned)
+    Philox generator with numpy's log (within two float ulps), the factors
+    are exponential of mean 1 (Kolmogorov-Smirnov), and the cell energies
+    are the sums of the hit energies."""
+    from scipy import stats
+    base = 5000
+    w = W.subset_events(W.single_particle_sweep(), base, 60)
+    kw = dict(event_index_base=base, hit_list=True)
+    a = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed, **kw)
+    b = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
+                            hit_energy_fluct=True, **kw)
+    ha, hb = a["hits"], b["hits"]
+    assert np.array_equal(a["n"], b["n"])
+    for k in ("cell", "bin", "eta", "phi"):
+        assert np.array_equal(ha[k], hb[k]), k
+    L = param_full.n_layers
+    n = a["n"]
+    t = np.repeat(np.arange(len(n)), n)
+    i = np.concatenate([np.arange(m) for m in n]).astype(np.uint32)
+    gp, lay = t // L, t % L
+    ev = base + np.searchsorted(w.event_offsets, gp, side="right") - 1
+    pin = gp - w.event_offsets[ev - base]
+    ctr = np.stack([i, (lay | (3 << 8)).astype(np.uint32), pin.astype(np.uint32),
+                    ev.astype(np.uint32)], axis=1)
+    w4 = oracle_lib.philox(ctr, [w.seed & 0xffffffff, w.seed >> 32])[:, 3].astype(np.uint64)
+    x = -np.log(((w4 >> 8).astype(np.float64) + 0.5) * 2.0 ** -24)
+    ehit = a["ehit"][t]
+    assert np.array_equal(ha["e"], ehit)
+    e_np = (ehit.astype(np.float64) * x).astype(np.float32)
+    assert np.all(np.abs(hb["e"] - e_np) <= 2 * np.spacing(e_np)), np.abs(hb["e"] - e_np).max()
+    xo = hb["e"].astype(np.float64) / ehit
+    assert abs(xo.mean() - 1.0) < 4.0 / np.sqrt(len(xo))
+    assert stats.kstest(xo, "expon").pvalue > 1e-3
+    # cell energies: the hit energies summed per (event, cell)
+    keys = (ev - base).astype(np.int64) * geom_full.n_cells + hb["cell"]
+    ok = hb["cell"] >= 0
+    uk, inv = np.unique(keys[ok], return_inverse=True)
+    sums = np.bincount(inv, weights=hb["e"][ok].astype(np.float64))
+    ev_of = np.repeat(np.arange(w.n_events), np.diff(b["ev_cell_off"]))
+    got = ev_of.astype(np.int64) * geom_full.n_cells + b["cell_idx"]
+    assert np.array_equal(got, uk)
+    assert np.allclose(b["cell_e"], sums, rtol=1e-12, atol=0)
