@@ -14,8 +14,9 @@ pions); the multi-particle workloads (hard scatter, pile-up) in the batched
 and per-event forms; several jobs sharing the GPU (1 to 16 contexts on host
 threads); the headline batch on 64 x 64-bin tables, with the FP64
 placement variant (with the count of hits that change cell) and with the
-per-hit energy fluctuation variant; the roofline
-of the hit kernel; and the CPU oracle timed on the host (one thread and
+per-hit energy fluctuation variant; the device-atomic ceiling (FP32
+atomic adds into one event's cells, uniform and at a hot spot); the
+roofline of the hit kernel; and the CPU oracle timed on the host (one thread and
 threads over event ranges).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -448,6 +449,36 @@ def run_hit_fluct(torch, sim, w, dp, doff, out, cap, tuning, steps, warmup, fp32
             "energy_over_constant": energy[True] / energy[False]}
 
 
+def run_atomic_ceiling(torch, dev, n_cells=191338, n_ops=1 << 25, reps=5):
+    """The device-atomic ceiling of a deposit of one atomic per hit: FP32
+    atomic adds into one event's cell array (191,338 cells, 765 KB) through
+    torch's index_add_ (one atomic add per element on this GPU), at
+    uniformly random cells and at a shower-like hot spot (cells at an
+    exponentially distributed distance, mean 8 cells, from one centre).
+    Atomic adds per second; the hit kernel's privatized deposit (hits
+    counted per cell in LDS) is compared against it."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    cells = torch.zeros(n_cells, dtype=torch.float32, device=dev)
+    vals = torch.ones(n_ops, dtype=torch.float32, device=dev)
+    idx_u = torch.randint(0, n_cells, (n_ops,), device=dev, generator=g)
+    dist = torch.empty(n_ops, dtype=torch.float32, device=dev).exponential_(1.0 / 8.0, generator=g)
+    sign = torch.randint(0, 2, (n_ops,), device=dev, generator=g) * 2 - 1
+    idx_h = (n_cells // 2 + sign * dist.long()).clamp_(0, n_cells - 1)
+    res = {"cells": n_cells, "atomics_per_pass": n_ops}
+    for name, idx in (("uniform", idx_u), ("hot_spot", idx_h)):
+        cells.index_add_(0, idx, vals)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            cells.index_add_(0, idx, vals)
+        torch.cuda.synchronize()
+        res[f"{name}_per_s"] = n_ops * reps / (time.perf_counter() - t0)
+    print(f"bench: FP32 atomic adds into 765 KB: {res['uniform_per_s']:.3g}/s uniform, "
+          f"{res['hot_spot_per_s']:.3g}/s at a hot spot", flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -624,6 +655,12 @@ def main():
     # roofline of the dominant kernel (the persistent hit kernel)
     ops = OPS_PER_HIT * hits_per_step
     achieved = ops / (kernel_ms * 1e-3)
+    # context: one device atomic per hit could not reach this rate
+    if not args.only_headline:
+        ceil = run_atomic_ceiling(torch, dev)
+        ceil["hits_per_s_over_uniform"] = value / ceil["uniform_per_s"]
+        ceil["hits_per_s_over_hot_spot"] = value / ceil["hot_spot_per_s"]
+        line["atomic_ceiling"] = ceil
     line["roofline"] = {"kernel": "k_hits", "bound": "alu", "achieved": achieved / 1e12,
                         "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tops/s",
                         "frac": achieved / VALU_LANE_OPS_PEAK,
