@@ -252,8 +252,11 @@ typedef struct {
                                    with a per-hit energy stage in place of
                                    the constant Ehit.  A task's energy is
                                    then conserved on average only.  Not
-                                   with placement_fp64; fcs_backward
-                                   refuses it.  Default 0.                  */
+                                   with placement_fp64.  fcs_backward
+                                   follows it: dL/dE_l = (1/n) sum over
+                                   the task's hits of x g(cell), and the
+                                   weight gradient takes each hit's own
+                                   energy.  Default 0.                      */
 } fcs_sim_options;
 
 /* Fill *opt with the defaults: seed 0, batched, compact output, 100 MeV per

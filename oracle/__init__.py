@@ -246,11 +246,11 @@ def perturbed_elayer(param: Param, particles, event_offsets, seed, sigma=0.2,
 
 def gradient(geom: Geometry, param: Param, particles, event_offsets, seed, grad_cells,
              event_index_base=0, hit_energy_scale=100.0, nhit_cap=20000,
-             min_layer_energy=1e-6, elayer_override=None):
+             min_layer_energy=1e-6, elayer_override=None, hit_energy_fluct=False):
     parts = np.ascontiguousarray(particles)
     off = np.ascontiguousarray(event_offsets, np.int64)
     opts = make_opts(seed, event_index_base, hit_energy_scale, nhit_cap, min_layer_energy,
-                     elayer_override)
+                     elayer_override, hit_energy_fluct=hit_energy_fluct)
     g = np.ascontiguousarray(grad_cells, np.float32)
     dE = np.zeros(len(parts) * param.n_layers, np.float64)
     dW = np.zeros(param.weights.size, np.float64)
@@ -264,11 +264,11 @@ def gradient(geom: Geometry, param: Param, particles, event_offsets, seed, grad_
 
 def surrogate_loss(geom: Geometry, param: Param, w, particles, event_offsets, seed, targets,
                    event_index_base=0, hit_energy_scale=100.0, nhit_cap=20000,
-                   min_layer_energy=1e-6, elayer_override=None):
+                   min_layer_energy=1e-6, elayer_override=None, hit_energy_fluct=False):
     parts = np.ascontiguousarray(particles)
     off = np.ascontiguousarray(event_offsets, np.int64)
     opts = make_opts(seed, event_index_base, hit_energy_scale, nhit_cap, min_layer_energy,
-                     elayer_override)
+                     elayer_override, hit_energy_fluct=hit_energy_fluct)
     w = np.ascontiguousarray(w, np.float64)
     T = np.ascontiguousarray(targets, np.float64)
     return lib().oracle_surrogate_loss(C.byref(geom.c), C.byref(param.c), _p(param.weights),

@@ -564,10 +564,15 @@ static og_hit one_hit_f64(const og_geom *G, const float *cum, float r_max, uint6
  * Listing 1): the hit's energy is Ehit * x with x = -ln u exponential of
  * mean 1, u = ((w4 >> 8) + 1/2) 2^-24 from the draw's unused fourth word,
  * x in FP64 with oracle_log, one rounding to FP32. */
-static float fluct_energy(float ehit, uint32_t w4)
+static double fluct_factor(uint32_t w4)
 {
     double u = ((double)(w4 >> 8) + 0.5) * 0x1p-24;
-    return (float)((double)ehit * -oracle_log(u));
+    return -oracle_log(u);
+}
+
+static float fluct_energy(float ehit, uint32_t w4)
+{
+    return (float)((double)ehit * fluct_factor(w4));
 }
 
 /* exported single-hit evaluation for tests */
@@ -794,8 +799,15 @@ int oracle_gradient(const og_geom *G, const og_param *P, const float *w0, int64_
                                        ev, pt->eta, pt->phi);
                     if (h.cell < 0) continue;
                     double gc = (double)grad_cells[e * C + h.cell];
-                    gsum = gsum + gc;
-                    A[H * NBINS + h.bin] += gc * (double)S.ehit[l];
+                    if (O->hit_energy_fluct) {
+                        /* E_hit = (E_l / n) x: d E_hit / d E_l = x / n (the
+                         * rounding of E_hit taken as identity) */
+                        gsum = gsum + gc * fluct_factor(h.w4);
+                        A[H * NBINS + h.bin] += gc * (double)fluct_energy(S.ehit[l], h.w4);
+                    } else {
+                        gsum = gsum + gc;
+                        A[H * NBINS + h.bin] += gc * (double)S.ehit[l];
+                    }
                 }
                 grad_elayer[gp * L + l] = S.n[l] > 0 ? gsum / (double)S.n[l] : 0.0;
             }
@@ -859,7 +871,8 @@ double oracle_surrogate_loss(const og_geom *G, const og_param *P, const float *w
                     if (h.cell < 0) continue;
                     double ratio = (w[H * NBINS + h.bin] / W1[H]) /
                                    ((double)w0[H * NBINS + h.bin] / W0[H]);
-                    cells[h.cell] += (double)S.ehit[l] * ratio;
+                    float e_hit = O->hit_energy_fluct ? fluct_energy(S.ehit[l], h.w4) : S.ehit[l];
+                    cells[h.cell] += (double)e_hit * ratio;
                 }
             }
         }

@@ -43,7 +43,8 @@ class _SimulateDense(torch.autograd.Function):
             return (None,) * 7
         bkw = {k: v for k, v in ctx.kw.items()
                if k in ("event_index_base", "hit_energy_scale", "nhit_cap", "min_layer_energy",
-                        "async_launch", "chunk_hits", "big_task_hits", "tile_hits", "wg_per_cu")}
+                        "async_launch", "chunk_hits", "big_task_hits", "tile_hits", "wg_per_cu",
+                        "hit_energy_fluct")}
         # the forward's work queue is reused when no other call has rebuilt it
         # since (the library checks inputs, options and tuning)
         ge, gw = ctx.sim.backward(ctx.particles, ctx.event_offsets, ctx.seed,
@@ -64,8 +65,8 @@ def simulate_dense(sim, particles, event_offsets, seed, elayer, weights=None, **
     """Dense cell energies [n_events, n_cells] (device f32) as a differentiable
     function of `elayer` (and of `weights`, when given).  `particles` and
     `event_offsets` must be device tensors; `kw` takes event_index_base,
-    hit_energy_scale, nhit_cap, min_layer_energy, async_launch and the launch
-    tuning."""
+    hit_energy_scale, nhit_cap, min_layer_energy, async_launch,
+    hit_energy_fluct and the launch tuning."""
     if not (torch.is_tensor(elayer) and elayer.is_cuda and elayer.dtype == torch.float32):
         raise TypeError("elayer must be a float32 CUDA tensor")
     if weights is None:

@@ -1369,10 +1369,15 @@ __device__ __forceinline__ void wave_hash_flush(const Params& P, uint32_t* hkey,
 // A chain variant: the hit's energy is Ehit x with x = -ln u exponential
 // (mean 1), u = ((w4 >> 8) + 1/2) 2^-24 from the counter's fourth word, x in
 // FP64 with the setup's log series, one rounding to FP32.
-__device__ __forceinline__ float fluct_energy(float ehit, uint32_t w4)
+__device__ __forceinline__ double fluct_factor(uint32_t w4)
 {
     const double u = ((double)(w4 >> 8) + 0.5) * 0x1p-24;
-    return (float)((double)ehit * -dlog<2>(u));
+    return -dlog<2>(u);
+}
+
+__device__ __forceinline__ float fluct_energy(float ehit, uint32_t w4)
+{
+    return (float)((double)ehit * fluct_factor(w4));
 }
 
 // the chunk path's hash with FP64 energy sums per slot (the variant's
@@ -1987,6 +1992,9 @@ __global__ __launch_bounds__(kBlock) void k_seg_emit(const Params* __restrict__ 
 // cell and accumulated in FP64 per task (sum of g) and per histogram bin (sum
 // of g * Ehit); a chunk keeps its 256 bin sums in the wave's LDS and flushes
 // them once.
+// kFluct: the per-hit energy fluctuation variant; a hit carries E_l x / n, so
+// it adds g x to its task's sum and g E_hit to its bin's.
+template <bool kFluct>
 __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
@@ -2032,8 +2040,14 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
                                               (uint32_t)ck.l, ck.pin, ck.evg, ck.eta_p, ck.phi_p);
                 if (h.cell < 0) continue;
                 const double gc = (double)g[h.cell];
-                gsum += gc;
-                atomicAdd(&bins[h.bin], gc * (double)ck.ehit);
+                if constexpr (kFluct) {
+                    const double x = fluct_factor(h.w4);
+                    gsum += gc * x;
+                    atomicAdd(&bins[h.bin], gc * (double)(float)((double)ck.ehit * x));
+                } else {
+                    gsum += gc;
+                    atomicAdd(&bins[h.bin], gc * (double)ck.ehit);
+                }
             }
 #pragma unroll
             for (int d = kWave / 2; d > 0; d >>= 1) gsum += __shfl_xor(gsum, d, kWave);
@@ -2062,8 +2076,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
                                               sh.eta_p, sh.phi_p);
                 if (h.cell < 0) continue;
                 const double gc = (double)G(P.grad_cells)[(long long)sh.ev * C + h.cell];
-                gadd(G(P.acc_elayer) + sh.t, gc);
-                gadd(G(P.acc_bins) + (long long)sh.H * kBins + h.bin, gc * (double)sh.ehit);
+                const double x = kFluct ? fluct_factor(h.w4) : 1.0;
+                const float e_hit = kFluct ? (float)((double)sh.ehit * x) : sh.ehit;
+                gadd(G(P.acc_elayer) + sh.t, gc * x);
+                gadd(G(P.acc_bins) + (long long)sh.H * kBins + h.bin, gc * (double)e_hit);
                 G(P.hist_mark)[sh.H] = 1;
             }
             wave_sync();
@@ -2074,7 +2090,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const Params* __restrict__ P
     }
 }
 
-// dL/dE_layer = (sum of g over the task's in-acceptance hits) / n.  The
+// dL/dE_layer = (sum of g, times the hits' energy factors in the fluctuation
+// variant, over the task's in-acceptance hits) / n.  The
 // accumulator is cleared once read, so the next call starts from zero.
 __global__ void k_adj_elayer(const Params* __restrict__ Pp)
 {

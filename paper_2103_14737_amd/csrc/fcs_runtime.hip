@@ -1414,10 +1414,9 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
     const bool async = o->async_launch != 0;
     if (async && (!o->inputs_on_device || o->n_particles <= 0))
         return fail(c, FCS_E_INVALID_ARG, "async_launch needs device inputs and n_particles");
-    if (o->placement_fp64 || o->hit_energy_fluct)
-        return fail(c, FCS_E_INVALID_ARG, "placement_fp64 and hit_energy_fluct are forward-only "
-                                          "variants: the adjoint follows the FP32 chain with one "
-                                          "energy per task");
+    if (o->placement_fp64)
+        return fail(c, FCS_E_INVALID_ARG, "placement_fp64 is a forward-only variant: the adjoint "
+                                          "recomputes hits with the FP32 placement");
     Inputs in;
     if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, false, &in))) return rc;
     const long long nt = in.N * c->n_layers;
@@ -1458,8 +1457,12 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
     // the adjoint passes; the last two run whatever gradients are asked for:
     // they also clear the accumulators
     auto launch_adjoint = [&](const Params& P) -> int {
-        hipLaunchKernelGGL(fcsk::k_adjoint, dim3(c->n_cu * tu.wg_per_cu), dim3(fcsk::kBlock),
-                           geo_lds_bytes(P), s, dP);
+        if (P.hit_fluct)
+            hipLaunchKernelGGL((fcsk::k_adjoint<true>), dim3(c->n_cu * tu.wg_per_cu), dim3(fcsk::kBlock),
+                               geo_lds_bytes(P), s, dP);
+        else
+            hipLaunchKernelGGL((fcsk::k_adjoint<false>), dim3(c->n_cu * tu.wg_per_cu), dim3(fcsk::kBlock),
+                               geo_lds_bytes(P), s, dP);
         hipLaunchKernelGGL(fcsk::k_adj_elayer, dim3(grid_for(nt, 256)), dim3(256), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_adj_weights,
                            dim3(grid_for(std::min<long long>(c->n_hist, (long long)c->n_cu * 32),

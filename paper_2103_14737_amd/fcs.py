@@ -388,7 +388,7 @@ class Simulator:
                  hit_energy_scale=100.0, nhit_cap=20000, min_layer_energy=1e-6,
                  elayer_override=None, grad_elayer=None, grad_weights=None, chunk_hits=0,
                  big_task_hits=0, tile_hits=0, wg_per_cu=0, need_elayer=True, need_weights=True,
-                 async_launch=False, reuse_forward_queue=False):
+                 async_launch=False, reuse_forward_queue=False, hit_energy_fluct=False):
         """fcs_backward on device tensors: returns (grad_elayer [N*L],
         grad_weights [n_hist*256]) as torch CUDA float32 tensors; a gradient
         with need_* False is not computed and returned as None.  With
@@ -405,6 +405,7 @@ class Simulator:
                           min_layer_energy, chunk_hits, big_task_hits, tile_hits, wg_per_cu,
                           False, dev, ov, stream, n_particles=N, async_launch=async_launch)
         o.reuse_forward_queue = 1 if reuse_forward_queue else 0
+        o.hit_energy_fluct = 1 if hit_energy_fluct else 0
         g = grad_cells.contiguous().float()
         if not need_elayer:
             grad_elayer = None

@@ -243,8 +243,8 @@ def test_backward_refuses_fp64_placement(F, dry):
 
 
 def test_chain_variant_options(F, dry):
-    """The two chain variants exclude each other, and the adjoint refuses the
-    energy fluctuation."""
+    """The two chain variants exclude each other; the adjoint takes the
+    energy fluctuation (valid arguments reach the device step)."""
     import ctypes as C
     dry.load_geometry(W.make_geometry())
     dry.load_parametrization(W.make_param())
@@ -265,5 +265,4 @@ def test_chain_variant_options(F, dry):
     g = np.zeros(5 * 191338, np.float32)
     rc = F.lib().fcs_backward(dry._h, p.ctypes.data, off.ctypes.data, 5, C.byref(o), g.ctypes.data,
                               None, None)
-    assert rc == F.FCS_E_INVALID_ARG
-    assert "hit_energy_fluct" in F.lib().fcs_last_error(dry._h).decode()
+    assert rc == F.FCS_E_NO_DEVICE, F.lib().fcs_last_error(dry._h).decode()

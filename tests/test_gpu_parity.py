@@ -350,14 +350,19 @@ def test_full_pileup_sampled_events(sim, oracle_lib, geom_full, param_full, geo,
 
 
 # --------------------------------------------------------------- adjoint ---
-def test_backward_matches_oracle_gradient(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+@pytest.mark.parametrize("fluct", [False, True])
+def test_backward_matches_oracle_gradient(sim, oracle_lib, geom_full, param_full, geo, torch_cuda,
+                                          fluct):
+    """fcs_backward against the oracle's FP64 gradient, for the constant hit
+    energy and for the per-hit energy fluctuation variant."""
     torch = torch_cuda
     w = W.single_pion_diff()
     C = geo["n_cells"]
     ep = oracle_lib.perturbed_elayer(param_full, w.particles, w.event_offsets, w.seed)
     T = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
-                            elayer_override=ep)
-    E = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed)
+                            elayer_override=ep, hit_energy_fluct=fluct)
+    E = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
+                            hit_energy_fluct=fluct)
 
     def dense(res):
         d = np.zeros(w.n_events * C)
@@ -368,9 +373,9 @@ def test_backward_matches_oracle_gradient(sim, oracle_lib, geom_full, param_full
 
     g = (2.0 * (dense(E) - dense(T))).astype(np.float32)
     dE_ref, dW_ref = oracle_lib.gradient(geom_full, param_full, w.particles, w.event_offsets,
-                                         w.seed, g)
+                                         w.seed, g, hit_energy_fluct=fluct)
     dp, doff = _dev(w, torch)
-    dE, dW = sim.backward(dp, doff, w.seed, torch.from_numpy(g).cuda())
+    dE, dW = sim.backward(dp, doff, w.seed, torch.from_numpy(g).cuda(), hit_energy_fluct=fluct)
     torch.cuda.synchronize()
     dE, dW = _np(dE).astype(np.float64), _np(dW).astype(np.float64)
     sE = np.abs(dE_ref).max()

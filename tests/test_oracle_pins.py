@@ -603,3 +603,58 @@ def test_energy_fluctuation_from_the_fourth_word(oracle_lib, geom_full, param_fu
     got = ev_of.astype(np.int64) * geom_full.n_cells + b["cell_idx"]
     assert np.array_equal(got, uk)
     assert np.allclose(b["cell_e"], sums, rtol=1e-12, atol=0)
+
+
+def test_fluctuation_gradients_match_fd(oracle_lib, geom_full, param_full):
+    """With the per-hit energy fluctuation, cell energies stay linear in the
+    layer energies (each hit carries E_l x / n): the layer-energy gradient
+    (1/n) sum x g and the weight gradient (per-hit energies in the
+    likelihood ratio) against central finite differences of the loss and of
+    the frozen-sample surrogate loss in the same mode."""
+    w = W.single_pion_diff()
+    sub = W.subset_events(w, 3, 2)
+    C = geom_full.n_cells
+    kw = dict(event_index_base=3, hit_energy_fluct=True)
+    ep = oracle_lib.perturbed_elayer(param_full, sub.particles, sub.event_offsets, w.seed,
+                                     event_index_base=3)
+    Td = _dense(oracle_lib.simulate(geom_full, param_full, sub.particles, sub.event_offsets,
+                                    w.seed, elayer_override=ep, **kw), sub.n_events, C)
+    base = oracle_lib.simulate(geom_full, param_full, sub.particles, sub.event_offsets, w.seed, **kw)
+    Ed = _dense(base, sub.n_events, C)
+    g = (2.0 * (Ed - Td)).astype(np.float32)
+    dE, dW = oracle_lib.gradient(geom_full, param_full, sub.particles, sub.event_offsets, w.seed,
+                                 g, **kw)
+    dE0, _ = oracle_lib.gradient(geom_full, param_full, sub.particles, sub.event_offsets, w.seed,
+                                 g, event_index_base=3)
+    assert not np.allclose(dE, dE0, rtol=1e-3)  # the factors do enter the gradient
+    el = base["elayer"].astype(np.float32)
+    for t in list(np.argsort(-np.abs(dE))[:3]):
+        h = 1e-3 * float(el[t])
+        vals = []
+        for sgn in (+1, -1):
+            ov = el.copy()
+            ov[t] = el[t] + sgn * h
+            r = oracle_lib.simulate(geom_full, param_full, sub.particles, sub.event_offsets,
+                                    w.seed, elayer_override=ov, **kw)
+            vals.append(((_dense(r, sub.n_events, C) - Td) ** 2).sum())
+        assert (vals[0] - vals[1]) / (2 * h) == pytest.approx(dE[t], rel=2e-3,
+                                                              abs=1e-6 * np.abs(dE).max())
+    w0 = param_full.weights.astype(np.float64)
+    L0 = oracle_lib.surrogate_loss(geom_full, param_full, w0, sub.particles, sub.event_offsets,
+                                   w.seed, Td, **kw)
+    assert L0 == pytest.approx(((Ed - Td) ** 2).sum(), rel=1e-12)
+    touched = np.nonzero(dW)[0]
+    H = touched[np.argmax(np.abs(dW[touched]))] // 256
+    for k in (int(np.argmax(np.abs(dW[H * 256:(H + 1) * 256]))), 9):
+        j = H * 256 + k
+        if w0[j] == 0:
+            continue
+        h = 1e-3 * w0[j]
+        vals = []
+        for sgn in (+1, -1):
+            wv = w0.copy()
+            wv[j] += sgn * h
+            vals.append(oracle_lib.surrogate_loss(geom_full, param_full, wv, sub.particles,
+                                                  sub.event_offsets, w.seed, Td, **kw))
+        assert (vals[0] - vals[1]) / (2 * h) == pytest.approx(dW[j], rel=1e-4,
+                                                              abs=1e-7 * np.abs(dW).max())
