@@ -588,3 +588,24 @@ def test_energy_fluctuation(sim, oracle_lib, geom_full, param_full, geo, torch_c
     r, ref = run_both(sim, oracle_lib, geom_full, param_full, geo, w, torch_cuda, mode=mode,
                       base=base)
     check_parity(r, ref, geo, label=f"{case} {mode}, constant energy after fluctuation")
+
+
+def test_dense_output_in_every_launch_form(sim, torch_cuda):
+    """Dense cell output (zero fill and count reset instead of compaction)
+    in the three launch forms: the same cells, energies within tolerance,
+    and the same nonzero-cell statistic."""
+    torch = torch_cuda
+    w = W.subset_events(W.hard_scatter(), 60, 2)
+    dp, doff = _dev(w, torch)
+    outs = []
+    for mode in ("batched", "per_event", "per_task"):
+        r = sim.simulate_events(dp, doff, w.seed, event_index_base=60, mode=mode, outputs=("dense",))
+        torch.cuda.synchronize()
+        outs.append((_np(r["cells"]), r["stats"]["n_cells_nonzero"]))
+        print(f"[parity] dense output, {mode}: {r['stats']['n_cells_nonzero']} cells", flush=True)
+    ref, nnz = outs[0]
+    assert nnz == np.count_nonzero(ref) > 0
+    for d, n in outs[1:]:
+        assert n == nnz
+        assert np.array_equal(d != 0, ref != 0)
+        assert np.allclose(d, ref, rtol=REL, atol=ABS)
