@@ -658,3 +658,35 @@ def test_fluctuation_gradients_match_fd(oracle_lib, geom_full, param_full):
                                                   sub.event_offsets, w.seed, Td, **kw))
         assert (vals[0] - vals[1]) / (2 * h) == pytest.approx(dW[j], rel=1e-4,
                                                               abs=1e-7 * np.abs(dW).max())
+
+
+def test_fine_binned_family(oracle_lib):
+    """The parametrization family at finer (E, |eta|) binnings: edges cover
+    the same ranges, the weights keep the shape law (each histogram's r
+    profile falls off, alpha-flat), the default binning is the 16 x 10
+    family, and set selection on the fine family lands in the bins the
+    edges define."""
+    p0 = W.make_param()
+    p = W.make_param(n_ebins=32, n_etabins=20)
+    assert p["weights"].size == 3 * 32 * 20 * 24 * 256
+    assert p["e_edges"][0] == p0["e_edges"][0] and p["e_edges"][-1] == p0["e_edges"][-1]
+    assert np.all(np.diff(p["e_edges"]) > 0) and np.all(np.diff(p["eta_edges"]) > 0)
+    assert p["eta_edges"][-1] == np.float32(3.2)
+    # every second fine E edge is a default edge (same log spacing)
+    assert np.allclose(p["e_edges"][::2], p0["e_edges"], rtol=1e-6)
+    w = p["weights"].reshape(-1, 32, 8)
+    assert np.all(w > 0) and np.all(np.diff(w[:, :, 0], axis=1) < 0)
+    assert np.all(w == w[:, :, :1])
+    # the fine bin at the default bin's lower edge has that bin's lambda
+    w0 = p0["weights"].reshape(3, 16, 10, 24, 32, 8)
+    wf = p["weights"].reshape(3, 32, 20, 24, 32, 8)
+    assert np.array_equal(wf[:, ::2, ::2], w0)
+    # oracle set selection on the fine family: a 2 GeV electron at |eta| 0.5
+    po = oracle_lib.Param(p)
+    parts = np.zeros(1, W.PARTICLE_DTYPE)
+    parts["pdg"], parts["e"], parts["eta"], parts["phi"] = 11, 2000.0, 0.5, 0.0
+    r = oracle_lib.simulate(oracle_lib.Geometry(W.make_geometry()), po, parts,
+                            np.array([0, 1], np.int64), 5)
+    ie = int(np.searchsorted(p["e_edges"][1:-1], np.float32(2000.0), side="right"))
+    ih = int(np.searchsorted(p["eta_edges"][1:-1], np.float32(0.5), side="right"))
+    assert r["set"][0] == (0 * 32 + ie) * 20 + ih
