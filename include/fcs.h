@@ -165,8 +165,9 @@ typedef struct {
 #define FCS_MODE_PER_EVENT 1 /* one launch sequence + sync per event       */
 /* FCS_MODE_PER_TASK: per event, the setup, then the event's hit counts
  * copied to the host and one launch per (particle, layer) task with hits
- * (one thread per hit, one device atomic per hit), then the compaction: the
- * launch structure of the paper's first GPU port (CUDA Implementation
+ * (one thread per hit; each workgroup counts its hits per cell in LDS and
+ * adds count x Ehit with one device atomic per cell), then the compaction:
+ * the launch structure of the paper's first GPU port (CUDA Implementation
  * section), kept as a baseline; results as in the other modes. */
 #define FCS_MODE_PER_TASK 2
 
@@ -185,7 +186,10 @@ typedef struct {
     uint32_t outputs;           /* FCS_OUT_* bit set                         */
     float hit_energy_scale_mev; /* expected hits of a layer = E_layer / this */
     int32_t nhit_cap;           /* hits per (particle, layer) are capped     */
-    double min_layer_energy_mev;/* layers with less energy get no hits       */
+    double min_layer_energy_mev;/* layers with less energy get no hits; at
+                                   least FLT_MIN x nhit_cap (x 2^26 with
+                                   hit_energy_fluct), so that no hit energy
+                                   is a subnormal FP32 number               */
     int32_t chunk_hits;         /* tuning, 0 = default: hits per work item of
                                    a large (particle, layer) task, <= 32768 */
     int32_t big_task_hits;      /* tuning, 0 = default: tasks with at least
@@ -205,7 +209,13 @@ typedef struct {
                                    the stream it runs on (out->kernel_ms)    */
     const float *elayer_override; /* [N * n_layers] or NULL: energies used for
                                    Ehit; hit counts still come from the
-                                   particle's own layer energies            */
+                                   particle's own layer energies.  Values
+                                   must be finite and >= 0, and a (particle,
+                                   layer) with hits must get a hit energy
+                                   value / n of at least FLT_MIN (x 2^26
+                                   with hit_energy_fluct); else
+                                   FCS_E_INVALID_ARG (checked on the device
+                                   once the hit counts are known)           */
     void *stream;               /* hipStream_t the call orders after; NULL =
                                    the context's stream                     */
     int64_t n_particles;        /* device inputs: number of records in

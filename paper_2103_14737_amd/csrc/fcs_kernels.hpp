@@ -71,7 +71,7 @@ enum : int32_t {
     kErrOffsets = 4,      // malformed event offsets
     kErrTooManyHits = 8,  // more than 2^31-1 hits in one batch
     kErrChunkCap = 16,    // chunk list capacity exceeded (internal retry)
-    kErrOverride = 32,    // negative or non-finite layer-energy override
+    kErrOverride = 32,    // negative or non-finite override, or a subnormal hit energy from it
     kErrCellCap = 64,     // compacted cells beyond the output capacity (async calls)
     kErrHitCap = 128,     // hits beyond the hit-list capacity (async calls)
 };
@@ -115,6 +115,7 @@ struct Params {
     float scale;
     int32_t cap;
     double min_e;
+    float ehit_min;          // smallest positive hit energy an override may give
     int32_t chunk_hits, big_thr, tile_hits;
     int32_t want_hits;
     int32_t clean_cells;  // reset the accumulator while compacting
@@ -540,10 +541,17 @@ __global__ __launch_bounds__(kBlock) void k_setup_one(const Params* __restrict__
         double e_used = el;
         if (G(P.elayer_override)) {
             const float ov = G(P.elayer_override)[t];
-            if (!(ov >= 0.0f) || !isfinite(ov)) gor(&G(P.ctr)->error, (int)kErrOverride);
-            e_used = ov >= 0.0f ? (double)ov : 0.0;
+            const bool ok = ov >= 0.0f && isfinite(ov);
+            if (!ok) gor(&G(P.ctr)->error, (int)kErrOverride);
+            e_used = ok ? (double)ov : 0.0;
         }
         ehit = n > 0 ? (float)(e_used / (double)n) : 0.0f;
+        // an override below FLT_MIN x n would give subnormal hit energies,
+        // which the deposits' count of new cells cannot take
+        if (ehit > 0.0f && ehit < P.ehit_min) {
+            gor(&G(P.ctr)->error, (int)kErrOverride);
+            ehit = 0.0f;
+        }
     }
     if (active) {
         G(P.task_n)[t] = n;
@@ -722,10 +730,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
             double e_used = el;
             if (G(P.elayer_override)) {
                 const float ov = G(P.elayer_override)[gt];
-                if (!(ov >= 0.0f) || !isfinite(ov)) gor(&G(P.ctr)->error, (int)kErrOverride);
-                e_used = ov >= 0.0f ? (double)ov : 0.0;
+                const bool ok = ov >= 0.0f && isfinite(ov);
+                if (!ok) gor(&G(P.ctr)->error, (int)kErrOverride);
+                e_used = ok ? (double)ov : 0.0;
             }
             ehit = n > 0 ? (float)(e_used / (double)n) : 0.0f;
+            if (ehit > 0.0f && ehit < P.ehit_min) {
+                gor(&G(P.ctr)->error, (int)kErrOverride);
+                ehit = 0.0f;
+            }
         }
         G(P.task_n)[gt] = n;
         G(P.task_ehit)[gt] = ehit;

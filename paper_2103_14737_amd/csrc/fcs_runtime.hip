@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -221,6 +222,18 @@ void drop_graphs(fcs_ctx* c)
 }
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
+
+// The smallest hit energy E_layer / n a call may produce: FLT_MIN, and with
+// the energy fluctuation FLT_MIN 2^26 (its factor exceeds 2^-26), so that every
+// deposited energy is a normal FP32 number.  The deposits count a cell as new
+// when an atomic add finds it at zero, which a flushed subnormal addend would
+// break.  A call's own layer energies are at least min_layer_energy_mev,
+// checked against nhit_cap times this bound; an override is checked per
+// (particle, layer) with hits on the device.
+double min_hit_energy(const fcs_sim_options* o)
+{
+    return o->hit_energy_fluct ? (double)FLT_MIN * 0x1p26 : (double)FLT_MIN;
+}
 
 }  // namespace
 
@@ -458,14 +471,17 @@ int fcs_load_geometry(fcs_ctx* c, const fcs_geometry* g)
     c->n_layers = L;
     c->n_regions = R;
     c->has_geom = true;
+    // Captured launch sequences hold grids and LDS sizes derived from the
+    // layer and region counts, and a kept work queue holds the old layout:
+    // neither survives a reload.
+    drop_graphs(c);
+    c->q_valid = false;
     if (changed) {
         // accumulator layout depends on the cell count: start it over
         release(c, c->w_cells);
         release(c, c->w_flags);
         c->cells_events = 0;
         c->flag_events = 0;
-        drop_graphs(c);
-        c->q_valid = false;
     }
     if (c->has_param && c->n_layers != L) c->has_param = false;
     return FCS_OK;
@@ -521,6 +537,9 @@ int fcs_load_parametrization(fcs_ctx* c, const fcs_param* p)
     }
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    // a kept work queue refers to the old tables (their pointers and
+    // histogram count): an adjoint may not reuse it after a reload
+    c->q_valid = false;
     int rc = 0;
     if ((rc = upload(c, c->p_e_edges, p->e_edges, (size_t)p->n_ebins + 1)) ||
         (rc = upload(c, c->p_eta_edges, p->eta_edges, (size_t)p->n_etabins + 1)) ||
@@ -721,6 +740,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->scale = o->hit_energy_scale_mev;
     P->cap = o->nhit_cap;
     P->min_e = o->min_layer_energy_mev;
+    P->ehit_min = (float)min_hit_energy(o);
     P->placement_f64 = o->placement_fp64 ? 1 : 0;
     P->hit_fluct = o->hit_energy_fluct ? 1 : 0;
     P->chunk_hits = tu.chunk;
@@ -849,7 +869,10 @@ int counters_error(fcs_ctx* c, const Counters& k)
         return fail(c, FCS_E_INVALID_ARG, "particle energy must be finite and > 0, eta/phi finite");
     if (k.error & fcsk::kErrOffsets) return fail(c, FCS_E_INVALID_ARG, "malformed event_offsets");
     if (k.error & fcsk::kErrOverride)
-        return fail(c, FCS_E_INVALID_ARG, "elayer_override holds a negative or non-finite energy");
+        return fail(c, FCS_E_INVALID_ARG,
+                    "elayer_override holds a negative or non-finite energy, or one that gives a "
+                    "(particle, layer) with hits a hit energy below FLT_MIN (x 2^26 with "
+                    "hit_energy_fluct)");
     if (k.error & fcsk::kErrTooManyHits)
         return fail(c, FCS_E_CAPACITY, "more than 2^31-1 hits in one batch: split the batch");
     return FCS_OK;
@@ -1041,6 +1064,11 @@ int stage_inputs(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
     if (o->nhit_cap < 1) return fail(c, FCS_E_INVALID_ARG, "nhit_cap must be >= 1");
     if (!(o->min_layer_energy_mev > 0.0) || !std::isfinite(o->min_layer_energy_mev))
         return fail(c, FCS_E_INVALID_ARG, "min_layer_energy_mev must be finite and > 0");
+    if (o->min_layer_energy_mev < min_hit_energy(o) * (double)o->nhit_cap)
+        return fail(c, FCS_E_INVALID_ARG,
+                    "min_layer_energy_mev = %g is below %g (FLT_MIN%s x nhit_cap): hit energies "
+                    "could be subnormal", o->min_layer_energy_mev,
+                    min_hit_energy(o) * (double)o->nhit_cap, o->hit_energy_fluct ? " x 2^26" : "");
     if (o->mode != FCS_MODE_BATCHED && o->mode != FCS_MODE_PER_EVENT && o->mode != FCS_MODE_PER_TASK)
         return fail(c, FCS_E_INVALID_ARG, "unknown mode %d", o->mode);
     if (o->placement_fp64 && o->hit_energy_fluct)

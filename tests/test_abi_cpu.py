@@ -266,3 +266,30 @@ def test_chain_variant_options(F, dry):
     rc = F.lib().fcs_backward(dry._h, p.ctypes.data, off.ctypes.data, 5, C.byref(o), g.ctypes.data,
                               None, None)
     assert rc == F.FCS_E_NO_DEVICE, F.lib().fcs_last_error(dry._h).decode()
+
+
+def test_min_layer_energy_keeps_hit_energies_normal(F, dry):
+    """min_layer_energy_mev must be at least FLT_MIN x nhit_cap (x 2^26 with
+    the energy fluctuation): with at most nhit_cap hits no hit energy of a
+    layer above the bound is a subnormal FP32 number."""
+    dry.load_geometry(W.make_geometry())
+    dry.load_parametrization(W.make_param())
+    w = W.single_particle_sweep(n_events=3)
+    flt_min = float(np.finfo(np.float32).tiny)
+    ok = flt_min * 20000 * 1.0001
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10,
+                            min_layer_energy=ok)
+    assert e.value.code == F.FCS_E_NO_DEVICE         # valid: reaches the device step
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10,
+                            min_layer_energy=flt_min * 20000 * 0.999)
+    assert e.value.code == F.FCS_E_INVALID_ARG and "min_layer_energy" in str(e.value)
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10,
+                            min_layer_energy=ok, hit_energy_fluct=True)
+    assert e.value.code == F.FCS_E_INVALID_ARG and "2^26" in str(e.value)
+    with pytest.raises(F.FcsError) as e:
+        dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10,
+                            min_layer_energy=ok * 2 ** 26, hit_energy_fluct=True)
+    assert e.value.code == F.FCS_E_NO_DEVICE

@@ -3,6 +3,8 @@
 Bar: hit counts, hit positions (bit patterns), hit cells and the set and
 order of compacted cells are identical; cell energies (FP32 accumulation)
 agree with the FP64 oracle within relative 1e-5 or absolute 1e-3 MeV."""
+import os
+
 import numpy as np
 import pytest
 
@@ -326,7 +328,11 @@ def test_setup_groupings(sim, oracle_lib, geom_full, param_full, geo, torch_cuda
     check_parity(r, ref, geo, hits=False, label=f"hard scatter {n_events} events ({len(w.particles)} particles)")
 
 
-def test_full_pileup_sampled_events(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+def test_full_pileup_every_event(sim, oracle_lib, geom_full, param_full, geo, torch_cuda):
+    """The whole 20-event pile-up batch (214 M hits) in one batched call, as
+    the benchmark runs it; every event against the oracle (run per event in
+    host threads: events are independent and keyed by their global index)."""
+    from concurrent.futures import ThreadPoolExecutor
     full = W.pileup()
     dp, doff = _dev(full, torch_cuda)
     r = sim.simulate_events(dp, doff, full.seed, outputs=("compact", "counts"),
@@ -336,17 +342,29 @@ def test_full_pileup_sampled_events(sim, oracle_lib, geom_full, param_full, geo,
     ids, es, off = _np(r["cell_ids"]), _np(r["cell_e"]), _np(r["event_cell_offsets"])
     counts = _np(r["counts"])
     L = 24
-    for e in (0, 13, 19):
+
+    def ref_event(e):
         sub = W.subset_events(full, e, 1)
-        ref = oracle_lib.simulate(geom_full, param_full, sub.particles, sub.event_offsets,
-                                  full.seed, event_index_base=e,
-                                  hit_energy_scale=full.hit_energy_scale)
+        return oracle_lib.simulate(geom_full, param_full, sub.particles, sub.event_offsets,
+                                   full.seed, event_index_base=e,
+                                   hit_energy_scale=full.hit_energy_scale)
+
+    n_thr = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(max_workers=n_thr) as ex:
+        refs = list(ex.map(ref_event, range(full.n_events)))
+    assert sum(x["n_hits_total"] for x in refs) == r["stats"]["n_hits"]
+    assert sum(x["n_out_of_acc"] for x in refs) == r["stats"]["n_hits_out_of_acceptance"]
+    nnz = 0
+    for e, ref in enumerate(refs):
         a, b = full.event_offsets[e], full.event_offsets[e + 1]
-        assert np.array_equal(counts[a * L:b * L], ref["n"])
+        assert np.array_equal(counts[a * L:b * L], ref["n"]), e
         s, t = off[e], off[e + 1]
-        assert np.array_equal(ids[s:t], geo["cell_id"][ref["cell_idx"]])
+        assert s == nnz and t - s == ref["n_cells_nonzero"], e
+        nnz = t
+        assert np.array_equal(ids[s:t], geo["cell_id"][ref["cell_idx"]]), e
         err = np.abs(es[s:t].astype(np.float64) - ref["cell_e"])
-        assert np.all(err <= np.maximum(REL * ref["cell_e"], ABS))
+        assert np.all(err <= np.maximum(REL * ref["cell_e"], ABS)), e
+    assert off[full.n_events] == nnz == r["stats"]["n_cells_nonzero"]
 
 
 # --------------------------------------------------------------- adjoint ---
