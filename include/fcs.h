@@ -329,6 +329,31 @@ int fcs_simulate_events(fcs_ctx *ctx, const fcs_particle *particles,
                         const int64_t *event_offsets, int64_t n_events,
                         const fcs_sim_options *opt, fcs_sim_output *out);
 
+/* fcs_simulate_events for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same results, but the call allocates nothing.  Every
+ * device buffer of the call other than its inputs, its outputs and the
+ * loaded tables (the parameter block, counters and work-queue tickets, the
+ * per-(particle, layer) arrays, the work queue, the per-block cell counts,
+ * the compaction lists and, without FCS_OUT_DENSE, the cell accumulator)
+ * is carved from a fixed 64 MiB array in device memory that the library
+ * holds on each GPU it runs on until the process ends; no captured graph is
+ * used.  Requirements: FCS_MODE_BATCHED, inputs_on_device and
+ * outputs_on_device (FCS_E_INVALID_ARG otherwise).  A batch whose workspace
+ * does not fit the array fails with FCS_E_INVALID_ARG and a message saying
+ * so (about 48 bytes per (particle, layer), 30 KB per event, and 765 KB per
+ * event of the 191,338-cell geometry without FCS_OUT_DENSE; split the
+ * batch).  The call zeroes the parts of the array that must start at zero.
+ * All contexts on one GPU share that GPU's array and each call leaves its
+ * contents behind: calls that overlap on one GPU (contexts used from
+ * several threads, or an asynchronous call still running when another
+ * context's call starts) race and give undefined results.  Calls on one
+ * context are ordered on its stream and do not race.  The work queue of
+ * such a call is not kept for fcs_backward's reuse_forward_queue. */
+int fcs_simulate_events_noalloc(fcs_ctx *ctx, const fcs_particle *particles,
+                                const int64_t *event_offsets, int64_t n_events,
+                                const fcs_sim_options *opt, fcs_sim_output *out);
+
 /* Statistics of the asynchronous calls since the last fcs_synchronize. */
 typedef struct {
     int64_t n_calls;

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -130,6 +131,13 @@ struct fcs_ctx {
     bool q_valid = false;
     QueueKey q_key{};
     Params q_params{};
+    // device address of the Params block (Counters at kCtrOffset) that the
+    // kernels of the current call read: w_params, or the start of the
+    // no-allocation scratch array
+    char* cur_params = nullptr;
+    // this device's scratch array for fcs_simulate_events_noalloc (its
+    // address looked up once per device at the first fcs_create there)
+    char* scratch = nullptr;
 };
 
 namespace {
@@ -223,6 +231,37 @@ void drop_graphs(fcs_ctx* c)
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
 
+// ------------------------------------------ no-allocation scratch array ---
+// fcs_simulate_events_noalloc keeps every device buffer of a call other than
+// its inputs, outputs and the loaded tables (parameter block, counters,
+// work-queue tickets, task arrays, work queue, block counts, compaction
+// lists, private accumulator) in this array.  Each GPU the library runs on
+// holds its own copy until the process ends.  In host code the name is not a
+// device address: its address on a device is looked up once per device with
+// hipGetSymbolAddress (with that device current) and kept in g_scratch_dev.
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxDevices] = {};
+
+// the scratch array's address on `device` (current); nullptr on failure
+char* scratch_on_device(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_dev[device] = (char*)ptr;
+    }
+    return g_scratch_dev[device];
+}
+
 // The smallest hit energy E_layer / n a call may produce: FLT_MIN, and with
 // the energy fluctuation FLT_MIN 2^26 (its factor exceeds 2^-26), so that every
 // deposited energy is a normal FP32 number.  The deposits count a cell as new
@@ -303,6 +342,11 @@ int fcs_create(fcs_ctx** out, int device)
             fcs_destroy(c);
             return fail(nullptr, FCS_E_HIP, "event creation failed");
         }
+    c->scratch = scratch_on_device(device);
+    if (!c->scratch) {
+        fcs_destroy(c);
+        return fail(nullptr, FCS_E_HIP, "hipGetSymbolAddress of the scratch array failed");
+    }
     if (ensure(c, c->w_params, kBlockBytes) ||
         ensure(c, c->w_queue, 2 * fcsk::kQueues * fcsk::kQueueStride * sizeof(int32_t)) ||
         ensure(c, c->w_async, sizeof(fcsk::AsyncAcc)) ||
@@ -640,10 +684,41 @@ void launch_setup(hipStream_t s, const Params* dP, long long N, int L, int n_cu)
                            dP);
 }
 
-// `dense_out` (device) is the caller's dense cell buffer or NULL.
+// Where a call's workspace lives: the context's grow-only buffers, or (with
+// `base`, no-allocation calls) consecutive 256-byte aligned pieces of the
+// scratch array, in the order they are taken.
+struct Carver {
+    fcs_ctx* c;
+    char* base;
+    size_t used;
+    int take(DevBuf& b, size_t bytes, void** out, bool* grown = nullptr)
+    {
+        if (!base) {
+            const int rc = ensure(c, b, bytes, grown);
+            *out = b.p;
+            return rc;
+        }
+        bytes = bytes ? (bytes + 255) & ~(size_t)255 : 256;
+        if (used + bytes > kScratchBytes)
+            return fail(c, FCS_E_INVALID_ARG,
+                        "batch too large for fcs_simulate_events_noalloc: its workspace needs more "
+                        "than the %zu bytes of the scratch array (split the batch)", kScratchBytes);
+        *out = base + used;
+        used += bytes;
+        return FCS_OK;
+    }
+    size_t left() const { return base ? kScratchBytes - used : 0; }
+};
+
+// `dense_out` (device) is the caller's dense cell buffer or NULL.  With
+// `scratch` (the device's scratch array) nothing is allocated: the whole
+// workspace, the parameter block and the tickets are carved from it, the
+// block counts and the private accumulator are zeroed by the call itself,
+// and the chunk list takes what remains of the array.
 int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
             const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
-            float* dense_out, const fcs_sim_output* dout, bool want_hits, bool async, Params* P)
+            float* dense_out, const fcs_sim_output* dout, bool want_hits, bool async, Params* P,
+            char* scratch = nullptr)
 {
     const int L = c->n_layers;
     const long long N = sh.n_particles;
@@ -671,33 +746,70 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
         if (c->chunk_cap < most) c->chunk_cap = most;
     }
     int rc = 0;
-    if ((rc = ensure(c, c->w_task_n, nt * 4)) || (rc = ensure(c, c->w_task_ehit, nt * 4)) ||
-        (rc = ensure(c, c->w_part_ev, N * 4)) || (rc = ensure(c, c->w_part_p, N * 4)) ||
-        (rc = ensure(c, c->w_part_set, N * 4)) || (rc = ensure(c, c->w_blk_sums, nsb * 16)) ||
-        (rc = ensure(c, c->w_blk_offs, nsb * 16)) || (rc = ensure(c, c->w_grp, nsg * 40)) ||
-        (rc = ensure(c, c->w_task_hoff, want_hits ? nt * 4 : 4)) ||
-        (rc = ensure(c, c->w_chunks, (size_t)c->chunk_cap * 16)) ||
-        (rc = ensure(c, c->w_small_rec, (size_t)nt * 32)) ||
-        (rc = ensure(c, c->w_tile_first, (nt + 1) * 4)) ||
-        (rc = ensure(c, c->w_seg_off, nseg * 8)) ||
-        (rc = ensure(c, c->w_seg_blk, nsegb * 8)) ||
-        (rc = ensure(c, c->w_blk_list, (size_t)nseg * fcsk::kSegBlocks * 8)))
-        return rc;
-    // flags and the private accumulator are kept zero between calls
-    if (c->flag_events < E) {
-        bool grown = false;
-        if ((rc = ensure(c, c->w_flags, (size_t)E * n_blk, &grown))) return rc;
-        hipLaunchKernelGGL(fcsk::k_fill_u8, dim3(1024), dim3(256), 0, c->stream,
-                           (uint8_t*)c->w_flags.p, (long long)(c->w_flags.bytes));
-        c->flag_events = (long long)(c->w_flags.bytes / (size_t)n_blk);
+    Carver cv{c, scratch, 0};
+    void *p_params = nullptr, *p_queue = nullptr, *p_task_n, *p_task_ehit, *p_part_ev, *p_part_p,
+         *p_part_set, *p_blk_sums, *p_blk_offs, *p_grp, *p_task_hoff, *p_small_rec, *p_tile_first,
+         *p_seg_off, *p_seg_blk, *p_blk_list, *p_flags, *p_cells = nullptr, *p_chunks;
+    if (scratch) {
+        // the parameter block first (kernels and uploads address it), then
+        // the tickets, then the buffers that must start at zero
+        if ((rc = cv.take(c->w_params, kBlockBytes, &p_params)) ||
+            (rc = cv.take(c->w_queue, 2 * fcsk::kQueues * fcsk::kQueueStride * sizeof(int32_t), &p_queue)) ||
+            (rc = cv.take(c->w_flags, (size_t)E * n_blk, &p_flags)) ||
+            (!dense_out && (rc = cv.take(c->w_cells, (size_t)E * c->n_cells * 4, &p_cells))))
+            return rc;
+    } else {
+        p_params = c->w_params.p;
+        p_queue = c->w_queue.p;
     }
-    if (!dense_out && c->cells_events < E) {
-        if ((rc = ensure(c, c->w_cells, (size_t)E * c->n_cells * 4))) return rc;
-        hipLaunchKernelGGL(fcsk::k_fill_u32, dim3(4096), dim3(256), 0, c->stream,
-                           (uint32_t*)c->w_cells.p, (long long)(c->w_cells.bytes / 4), 0u);
-        c->cells_events = (long long)(c->w_cells.bytes / 4 / (size_t)c->n_cells);
+    if ((rc = cv.take(c->w_task_n, nt * 4, &p_task_n)) || (rc = cv.take(c->w_task_ehit, nt * 4, &p_task_ehit)) ||
+        (rc = cv.take(c->w_part_ev, N * 4, &p_part_ev)) || (rc = cv.take(c->w_part_p, N * 4, &p_part_p)) ||
+        (rc = cv.take(c->w_part_set, N * 4, &p_part_set)) ||
+        (rc = cv.take(c->w_blk_sums, nsb * 16, &p_blk_sums)) ||
+        (rc = cv.take(c->w_blk_offs, nsb * 16, &p_blk_offs)) || (rc = cv.take(c->w_grp, nsg * 40, &p_grp)) ||
+        (rc = cv.take(c->w_task_hoff, want_hits ? nt * 4 : 4, &p_task_hoff)) ||
+        (rc = cv.take(c->w_small_rec, (size_t)nt * 32, &p_small_rec)) ||
+        (rc = cv.take(c->w_tile_first, (nt + 1) * 4, &p_tile_first)) ||
+        (rc = cv.take(c->w_seg_off, nseg * 8, &p_seg_off)) ||
+        (rc = cv.take(c->w_seg_blk, nsegb * 8, &p_seg_blk)) ||
+        (rc = cv.take(c->w_blk_list, (size_t)nseg * fcsk::kSegBlocks * 8, &p_blk_list)))
+        return rc;
+    long long chunk_cap = c->chunk_cap;
+    if (scratch) {
+        // the chunk list takes the rest of the array; a batch needing more
+        // chunks than that fails (the call cannot grow it)
+        chunk_cap = std::min<long long>((long long)(cv.left() / 16), 2147483647LL);
+        if (chunk_cap < 1024)
+            return fail(c, FCS_E_INVALID_ARG,
+                        "batch too large for fcs_simulate_events_noalloc: no room left for its work "
+                        "queue in the %zu-byte scratch array (split the batch)", kScratchBytes);
+        p_chunks = scratch + cv.used;
+        // what must start at zero: the block counts and the accumulator
+        hipLaunchKernelGGL(fcsk::k_fill_u8, dim3(1024), dim3(256), 0, c->stream, (uint8_t*)p_flags,
+                           (long long)E * n_blk);
+        if (p_cells)
+            hipLaunchKernelGGL(fcsk::k_fill_u32, dim3(4096), dim3(256), 0, c->stream, (uint32_t*)p_cells,
+                               E * c->n_cells, 0u);
+    } else {
+        if ((rc = cv.take(c->w_chunks, (size_t)chunk_cap * 16, &p_chunks))) return rc;
+        // flags and the private accumulator are kept zero between calls
+        if (c->flag_events < E) {
+            if ((rc = ensure(c, c->w_flags, (size_t)E * n_blk))) return rc;
+            hipLaunchKernelGGL(fcsk::k_fill_u8, dim3(1024), dim3(256), 0, c->stream,
+                               (uint8_t*)c->w_flags.p, (long long)(c->w_flags.bytes));
+            c->flag_events = (long long)(c->w_flags.bytes / (size_t)n_blk);
+        }
+        p_flags = c->w_flags.p;
+        if (!dense_out && c->cells_events < E) {
+            if ((rc = ensure(c, c->w_cells, (size_t)E * c->n_cells * 4))) return rc;
+            hipLaunchKernelGGL(fcsk::k_fill_u32, dim3(4096), dim3(256), 0, c->stream,
+                               (uint32_t*)c->w_cells.p, (long long)(c->w_cells.bytes / 4), 0u);
+            c->cells_events = (long long)(c->w_cells.bytes / 4 / (size_t)c->n_cells);
+        }
+        if (!dense_out) p_cells = c->w_cells.p;
     }
     HIPCHK(c, hipGetLastError());
+    c->cur_params = (char*)p_params;
 
     std::memset(P, 0, sizeof *P);
     P->n_cells = c->n_cells;
@@ -748,35 +860,35 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->tile_hits = tu.tile;
     P->want_hits = want_hits ? 1 : 0;
     P->clean_cells = dense_out ? 0 : 1;
-    P->chunk_cap = (int)std::min<long long>(c->chunk_cap, 2147483647LL);
+    P->chunk_cap = (int)std::min<long long>(chunk_cap, 2147483647LL);
     P->n_scan_blocks = (int)nsb;
     P->n_scan_groups = (int)nsg;
     P->setup_sub = setup_sub(N, L, c->n_cu);
     P->n_seg_groups = (int)nsegb;
-    P->task_n = (int32_t*)c->w_task_n.p;
-    P->task_ehit = (float*)c->w_task_ehit.p;
-    P->part_ev = (int32_t*)c->w_part_ev.p;
-    P->part_p = (uint32_t*)c->w_part_p.p;
-    P->part_set = (int32_t*)c->w_part_set.p;
-    P->blk_sums = (int32_t*)c->w_blk_sums.p;
-    P->blk_offs = (int32_t*)c->w_blk_offs.p;
+    P->task_n = (int32_t*)p_task_n;
+    P->task_ehit = (float*)p_task_ehit;
+    P->part_ev = (int32_t*)p_part_ev;
+    P->part_p = (uint32_t*)p_part_p;
+    P->part_set = (int32_t*)p_part_set;
+    P->blk_sums = (int32_t*)p_blk_sums;
+    P->blk_offs = (int32_t*)p_blk_offs;
     // group records: rest and offsets (16 bytes each, aligned), then hits
-    P->grp_rest = (int32_t*)c->w_grp.p;
-    P->grp_offs = (int32_t*)((char*)c->w_grp.p + nsg * 16);
-    P->grp_hits = (long long*)((char*)c->w_grp.p + nsg * 32);
-    P->task_hoff = (int32_t*)c->w_task_hoff.p;
-    P->chunks = (int4*)c->w_chunks.p;
-    P->small_rec = (int4*)c->w_small_rec.p;
+    P->grp_rest = (int32_t*)p_grp;
+    P->grp_offs = (int32_t*)((char*)p_grp + nsg * 16);
+    P->grp_hits = (long long*)((char*)p_grp + nsg * 32);
+    P->task_hoff = (int32_t*)p_task_hoff;
+    P->chunks = (int4*)p_chunks;
+    P->small_rec = (int4*)p_small_rec;
     P->geo_layers = (const int4*)c->g_layers.p;
     P->geo_regions = (const int4*)c->g_regions.p;
-    P->tile_first = (int32_t*)c->w_tile_first.p;
-    P->cells = dense_out ? dense_out : (float*)c->w_cells.p;
-    P->flags = (uint8_t*)c->w_flags.p;
-    P->seg_off = (long long*)c->w_seg_off.p;
-    P->seg_blk = (long long*)c->w_seg_blk.p;
-    P->blk_list = (unsigned long long*)c->w_blk_list.p;
-    P->ctr = (Counters*)((char*)c->w_params.p + kCtrOffset);
-    P->queue = (int32_t*)c->w_queue.p;
+    P->tile_first = (int32_t*)p_tile_first;
+    P->cells = dense_out ? dense_out : (float*)p_cells;
+    P->flags = (uint8_t*)p_flags;
+    P->seg_off = (long long*)p_seg_off;
+    P->seg_blk = (long long*)p_seg_blk;
+    P->blk_list = (unsigned long long*)p_blk_list;
+    P->ctr = (Counters*)((char*)p_params + kCtrOffset);
+    P->queue = (int32_t*)p_queue;
     if (dout) {
         P->out_elayer = dout->elayer;
         P->out_counts = dout->counts;
@@ -812,7 +924,7 @@ enum CellMode { kPrivate = 0, kDenseCompact = 1, kDenseOnly = 2 };
 void enqueue_batch(fcs_ctx* c, const Params& P, int mode, int grid, int part)
 {
     const bool dense = mode != kPrivate;
-    const Params* dP = (const Params*)c->w_params.p;
+    const Params* dP = (const Params*)c->cur_params;
     hipStream_t s = c->stream;
     if (part == kAll || part == kPre) {
         if (dense) hipLaunchKernelGGL(fcsk::k_fill_dense, dim3(2048), dim3(256), 0, s, dP);
@@ -885,7 +997,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
               const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
               float* dense_out, const fcs_sim_output* dout, bool want_hits, bool validate,
               bool use_graph, bool profile, Counters* res, double* kernel_ms, bool small_launch,
-              bool async, bool per_task = false)
+              bool async, bool per_task = false, char* scratch = nullptr)
 {
     // a launch over few particles (per-event mode) gets a grid sized to its
     // tasks instead of filling the chip with idle persistent workgroups
@@ -896,14 +1008,16 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
     c->q_valid = false;
     // a batched call over device inputs leaves a work queue an adjoint call
     // may reuse
-    const bool keep = !small_launch && o->inputs_on_device && !o->placement_fp64 && !o->hit_energy_fluct;
+    // (not a no-allocation call: its queue lives in the shared scratch array)
+    const bool keep = !small_launch && o->inputs_on_device && !o->placement_fp64 && !o->hit_energy_fluct &&
+                      !scratch;
     for (int attempt = 0; attempt < 2; ++attempt) {
         char* blk = ring_take(c);
         if (!blk) return fail(c, FCS_E_HIP, "hipEventSynchronize on a parameter block failed");
         Params* P = (Params*)blk;
         Counters* hc = (Counters*)(blk + kCtrOffset);
         int rc = prepare(c, o, tu, sh, d_particles, d_evoff, d_override, dense_out, dout, want_hits,
-                         async, P);
+                         async, P, scratch);
         if (rc) return rc;
         const int mode = !dense_out ? kPrivate : (P->out_ids ? kDenseCompact : kDenseOnly);
         // asynchronous calls fold their totals into the context's running
@@ -912,7 +1026,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         P->fold_acc = async ? (fcsk::AsyncAcc*)c->w_async.p : nullptr;
         P->validate = validate ? 1 : 0;
         std::memset(hc, 0, sizeof(Counters));
-        HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->cur_params, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
         if ((rc = ring_sent(c))) return rc;
         GraphKey key{sh.n_particles, sh.n_events, mode, grid, kAll, P->placement_f64 + 2 * P->hit_fluct};
         hipEvent_t k0 = c->ev_k0, k1 = c->ev_k1;
@@ -943,7 +1057,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             HIPCHK(c, hipMemcpyAsync(c->h_task_n.data(), P->task_n, (size_t)nt * 4,
                                      hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
-            const Params* dP = (const Params*)c->w_params.p;
+            const Params* dP = (const Params*)c->cur_params;
             if (profile) HIPCHK(c, hipEventRecord(k0, c->stream));
             for (long long t = 0; t < nt; ++t) {
                 if (c->h_task_n[(size_t)t] <= 0) continue;
@@ -992,10 +1106,15 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             }
             return FCS_OK;
         }
-        HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),
+        HIPCHK(c, hipMemcpyAsync(hc, c->cur_params + kCtrOffset, sizeof(Counters),
                                  hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         *res = *hc;
+        if ((res->error & fcsk::kErrChunkCap) && scratch)
+            return fail(c, FCS_E_INVALID_ARG,
+                        "batch too large for fcs_simulate_events_noalloc: its work queue needs %d "
+                        "entries, the scratch array holds %d (split the batch)", res->need_chunks,
+                        P->chunk_cap);
         if ((res->error & fcsk::kErrChunkCap) && attempt == 0) {
             c->chunk_cap = (long long)res->need_chunks + 1024;
             continue;
@@ -1149,14 +1268,24 @@ int stage_inputs(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
 
 extern "C" {
 
-int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
-                        int64_t n_events, const fcs_sim_options* o, fcs_sim_output* out)
+}  // extern "C"
+
+namespace {
+
+// fcs_simulate_events, and with `noalloc` fcs_simulate_events_noalloc (the
+// workspace carved from the device's scratch array; batched mode, device
+// inputs and outputs, no captured graphs)
+int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
+                  int64_t n_events, const fcs_sim_options* o, fcs_sim_output* out, bool noalloc)
 {
     if (!c) return FCS_E_INVALID_ARG;
     if (!out) return fail(c, FCS_E_INVALID_ARG, "output struct is NULL");
     Tuning tu;
     int rc = o ? check_tuning(c, o, &tu) : fail(c, FCS_E_INVALID_ARG, "options are NULL");
     if (rc) return rc;
+    if (noalloc && (o->mode != FCS_MODE_BATCHED || !o->inputs_on_device || !o->outputs_on_device))
+        return fail(c, FCS_E_INVALID_ARG,
+                    "fcs_simulate_events_noalloc needs batched mode and device inputs and outputs");
     const uint32_t f = o->outputs;
     if ((f & FCS_OUT_DENSE) && !out->cells) return fail(c, FCS_E_INVALID_ARG, "FCS_OUT_DENSE needs out->cells");
     if ((f & FCS_OUT_COMPACT) && (!out->cell_ids || !out->cell_e || !out->event_cell_offsets))
@@ -1176,6 +1305,8 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
                     "async_launch needs batched mode, device inputs and outputs and n_particles");
     Inputs in;
     if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, per_event, &in))) return rc;
+    char* const scratch = noalloc ? c->scratch : nullptr;
+    if (noalloc && !scratch) return fail(c, FCS_E_NO_DEVICE, "context has no scratch array");
     const int L = c->n_layers;
     const long long N = in.N;
     const long long C = c->n_cells;
@@ -1243,8 +1374,8 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
         Shape sh{N, 0, n_events, 0, 0, 0};
         Counters k;
         rc = run_range(c, o, tu, sh, in.d_particles, in.d_evoff, in.d_override, d.cells, &d,
-                       want_hits, in.validate_on_device, o->use_graph != 0, profile, &k, &kms, false,
-                       async);
+                       want_hits, in.validate_on_device, o->use_graph != 0 && !scratch, profile, &k,
+                       &kms, false, async, false, scratch);
         if (rc) return rc;
         hits = k.hits_total;
         hits_out = k.hits_out;
@@ -1345,6 +1476,22 @@ int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t
     if ((f & FCS_OUT_HITS) && hits > out->hit_capacity)
         return fail(c, FCS_E_CAPACITY, "hit_capacity %lld < %lld hits", (long long)out->hit_capacity, hits);
     return FCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
+                        int64_t n_events, const fcs_sim_options* o, fcs_sim_output* out)
+{
+    return simulate_impl(c, particles, event_offsets, n_events, o, out, false);
+}
+
+int fcs_simulate_events_noalloc(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
+                                int64_t n_events, const fcs_sim_options* o, fcs_sim_output* out)
+{
+    return simulate_impl(c, particles, event_offsets, n_events, o, out, true);
 }
 
 int fcs_synchronize(fcs_ctx* c, fcs_async_stats* st)

@@ -41,7 +41,7 @@ _OUT_NAMES = {"dense": FCS_OUT_DENSE, "compact": FCS_OUT_COMPACT, "hits": FCS_OU
 # every symbol include/fcs.h declares
 EXPORTS = ("fcs_create", "fcs_destroy", "fcs_last_error", "fcs_get_info", "fcs_load_geometry",
            "fcs_load_parametrization", "fcs_default_options", "fcs_simulate_events",
-           "fcs_query_sizes", "fcs_backward", "fcs_synchronize")
+           "fcs_simulate_events_noalloc", "fcs_query_sizes", "fcs_backward", "fcs_synchronize")
 
 _vp = C.c_void_p
 
@@ -133,13 +133,15 @@ def lib():
         L.fcs_default_options.restype = None
         L.fcs_simulate_events.argtypes = [_vp, _vp, _vp, C.c_int64, C.POINTER(FcsSimOptions),
                                           C.POINTER(FcsSimOutput)]
+        L.fcs_simulate_events_noalloc.argtypes = L.fcs_simulate_events.argtypes
         L.fcs_query_sizes.argtypes = [_vp, _vp, _vp, C.c_int64, C.POINTER(FcsSimOptions),
                                       C.POINTER(FcsSizes)]
         L.fcs_backward.argtypes = [_vp, _vp, _vp, C.c_int64, C.POINTER(FcsSimOptions), _vp, _vp,
                                    _vp]
         L.fcs_synchronize.argtypes = [_vp, C.POINTER(FcsAsyncStats)]
         for f in ("fcs_get_info", "fcs_load_geometry", "fcs_load_parametrization",
-                  "fcs_simulate_events", "fcs_query_sizes", "fcs_backward", "fcs_synchronize"):
+                  "fcs_simulate_events", "fcs_simulate_events_noalloc", "fcs_query_sizes",
+                  "fcs_backward", "fcs_synchronize"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -279,7 +281,7 @@ class Simulator:
                         tile_hits=0, wg_per_cu=0, use_graph=True, elayer_override=None,
                         cell_capacity=None, hit_capacity=None, n_particles=None, out=None,
                         profile=False, async_launch=False, placement_fp64=False,
-                        hit_energy_fluct=False):
+                        hit_energy_fluct=False, noalloc=False):
         """Run fcs_simulate_events.  Returns a dict of the requested outputs
         (numpy for host inputs, torch CUDA tensors for device inputs) and the
         statistics.  Capacities default to the sizes fcs_query_sizes
@@ -292,7 +294,11 @@ class Simulator:
         placement_fp64: place the hits and look up their cells in FP64 (a
         chain variant of the FP32 contract).  hit_energy_fluct: every hit's
         energy is Ehit times an exponential factor of mean 1 (a chain
-        variant)."""
+        variant).
+
+        noalloc: call fcs_simulate_events_noalloc (batched mode, device inputs
+        and outputs; pass `out` buffers and capacities so that the binding
+        allocates nothing either)."""
         p, off, ov, dev, stream, n_events = self._inputs(particles, event_offsets, elayer_override)
         N = (int(p.shape[0]) if dev else len(p)) if n_particles is None else n_particles
         o = self._options(seed, event_index_base, mode, outputs, hit_energy_scale, nhit_cap,
@@ -347,8 +353,8 @@ class Simulator:
             so.counts = _ptr(alloc("counts", (N * L,), np.int32))
         if "elayer" in outputs:
             so.elayer = _ptr(alloc("elayer", (N * L,), np.float32))
-        rc = self._L.fcs_simulate_events(self._h, _ptr(p), _ptr(off), n_events, C.byref(o),
-                                         C.byref(so))
+        call = self._L.fcs_simulate_events_noalloc if noalloc else self._L.fcs_simulate_events
+        rc = call(self._h, _ptr(p), _ptr(off), n_events, C.byref(o), C.byref(so))
         self._check(rc)
         if async_launch:
             res["stats"] = None

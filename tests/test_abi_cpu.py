@@ -293,3 +293,32 @@ def test_min_layer_energy_keeps_hit_energies_normal(F, dry):
         dry.simulate_events(w.particles, w.event_offsets, 1, cell_capacity=10,
                             min_layer_energy=ok * 2 ** 26, hit_energy_fluct=True)
     assert e.value.code == F.FCS_E_NO_DEVICE
+
+
+def test_noalloc_entry_point_argument_checks(F, dry):
+    """fcs_simulate_events_noalloc takes batched mode with device inputs and
+    outputs only; valid arguments reach the device step (a device-less
+    context never reads the pointers)."""
+    import ctypes as C
+    dry.load_geometry(W.make_geometry())
+    dry.load_parametrization(W.make_param())
+    L = F.lib()
+    dummy = C.c_void_p(0x1000)
+
+    def call(**kw):
+        o = F.FcsSimOptions()
+        L.fcs_default_options(C.byref(o))
+        o.inputs_on_device = o.outputs_on_device = 1
+        o.n_particles = 3
+        for k, v in kw.items():
+            setattr(o, k, v)
+        so = F.FcsSimOutput()
+        so.cell_ids = so.cell_e = so.event_cell_offsets = dummy
+        so.cell_capacity = 10
+        return L.fcs_simulate_events_noalloc(dry._h, dummy, dummy, 3, C.byref(o), C.byref(so))
+
+    assert call() == F.FCS_E_NO_DEVICE
+    assert call(mode=F.FCS_MODE_PER_EVENT) == F.FCS_E_INVALID_ARG
+    assert "batched mode" in L.fcs_last_error(dry._h).decode()
+    assert call(inputs_on_device=0) == F.FCS_E_INVALID_ARG
+    assert call(outputs_on_device=0) == F.FCS_E_INVALID_ARG
