@@ -1,23 +1,28 @@
 """Benchmark of the batched hit simulation on one MI355X.
 
 One step = one fcs_simulate_events call over the whole batch in batched mode
-(per-(particle, layer) setup, work-queue build, persistent hit kernel,
-ordered compaction and accumulator reset), inputs and outputs resident in
-device memory.  The headline workload is the single-particle sweep: 10,000
-events of one e/gamma/pi+- each, E log-uniform 1 GeV - 4 TeV, |eta| < 2.5.
+(per-(particle, layer) setup, work-queue build, the hit step -- window pass
+for the small tasks and the persistent hit kernel for the large ones --,
+ordered compaction and accumulator reset) plus the copy of its compacted
+{cell_id, E} lists to pinned host buffers (as the paper's event loop copies
+each call's results back), inputs resident in device memory.  Steps are
+enqueued back to back as asynchronous calls: the copy of one batch runs on
+a second stream beside the next batch.  The headline workload is the
+pile-up batch: 20 events of 1,500 hard-scatter particles plus 200 x 60
+soft ones, 214 M hits per step.
 
-Also reported on the same JSON line: the same batch as synchronous calls;
-the per-event launch form (one launch sequence and one host synchronization
-per event) and the per-(particle, layer) launch form (on a slice); the
-forward+backward throughput of the differentiable workload (64 single
-pions); the multi-particle workloads (hard scatter, pile-up) in the batched
-and per-event forms; several jobs sharing the GPU (1 to 16 contexts on host
-threads); the headline batch on 64 x 64-bin tables, with the FP64
-placement variant (with the count of hits that change cell) and with the
-per-hit energy fluctuation variant; the device-atomic ceiling (FP32
-atomic adds into one event's cells, uniform and at a hot spot); the
-roofline of the hit kernel; and the CPU oracle timed on the host (one thread and
-threads over event ranges).
+Also reported on the same JSON line: the same batch with the lists left in
+device memory, as synchronous calls, and in the per-event launch form; the
+hard-scatter batch (100 events of 500-2000 particles) and the
+single-particle sweep (10,000 events) in the batched, per-event and
+per-(particle, layer) forms; a roofline object for each of the three, on
+the hit step's HIP-event time in the timed steps; forward+backward of the
+differentiable workload (64 single pions); jobs sharing the GPU; the sweep
+on 64 x 64-bin tables, with the FP64 placement and with the per-hit energy
+fluctuation; an asynchronous table load beside a running batch; the
+measured ceilings of the chip (atomics, HBM copy, VALU clock, launches);
+and the CPU oracle timed on the host on a bounded sample of the headline
+workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -37,24 +42,29 @@ METRIC = "hits/s & events/s, batched vs per-event launch; fwd+bwd hits/s (1 GPU)
 
 # peak figures of the chip (MI355X): 256 CUs, 4 SIMD x 16 lanes per CU, 2.4 GHz
 N_CU, CLOCK_HZ = 256, 2.4e9
-VALU_LANE_OPS_PEAK = N_CU * 64 * CLOCK_HZ       # 32-bit VALU lane-ops per second
+VALU_SLOT_PEAK = N_CU * 64 * CLOCK_HZ   # VALU lane-instruction slots per second
 HBM_PEAK = 8.0e12
 
-# Algorithmic 32-bit operations per hit (a 32x32->64 product counts as its two
-# 32-bit halves): Philox4x32-10 = 10 rounds x (2 products = 4 + 4 xor) = 80
-# (the key schedule is shared by all hits); three 24-bit uniforms (shift,
-# convert, scale) = 9; bin choice from the guide table (index + ~2 compares)
-# = 3; radial / angular bin split = 2; radius = 4; octant sine and cosine
-# (offset, square, 4 + 5 multiply-add steps, final multiply, quadrant select)
-# = 24; deta / dphi = 4; eta / phi = 2; phi wrap = 3; region-grid lookup
-# (acceptance, region, two floor-and-clamp indices, linear index) = 22;
-# deposit = 1.
-OPS_PER_HIT = 80 + 9 + 3 + 2 + 4 + 24 + 4 + 2 + 3 + 22 + 1
+# Algorithmic work per hit in gfx950 VALU instruction slots (the fewest
+# instructions that compute a hit's arithmetic): Philox4x32-10 = 10 rounds x
+# (2 v_mad_u64_u32 32x32->64 products + 2 three-input xor v_bitop3) = 40;
+# three 24-bit uniforms (shift, convert, scale) = 9; bin choice from the
+# guide table (index + ~2 compares) = 3; radial / angular bin split = 2;
+# radius = 4; octant sine and cosine (offset, square, 4 + 5 multiply-add
+# steps, final multiply, quadrant select) = 24; deta / dphi = 4; eta / phi =
+# 2; phi wrap = 3; region-grid lookup (acceptance, region, two
+# floor-and-clamp indices, linear index) = 22; deposit = 1.  A Philox draw
+# measured alone issues at 40 slots (run_ceilings), so its 80 32-bit
+# operations (each product and each three-input xor counting twice) are
+# counted as the 40 slots they take.
+PHILOX_SLOTS = 40
+SLOTS_PER_HIT = PHILOX_SLOTS + 9 + 3 + 2 + 4 + 24 + 4 + 2 + 3 + 22 + 1
+OPS_PER_HIT = SLOTS_PER_HIT + PHILOX_SLOTS  # the same work in 32-bit operations
 KERNEL_SOURCES = ("paper_2103_14737_amd/csrc/fcs_math.hpp",
                   "paper_2103_14737_amd/csrc/fcs_kernels.hpp",
                   "paper_2103_14737_amd/csrc/fcs_runtime.hip",
                   "paper_2103_14737_amd/build.py")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hits_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hit_step_traffic.json")
 
 
 def kernel_source_hash():
@@ -67,9 +77,9 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload, tuning):
-    """HBM bytes per launch of the hit kernel from the committed counter
-    summaries: the entry taken on the current kernel sources, this workload
-    and this tuning, if there is one; else None."""
+    """HBM bytes per launch of the hit step (window pass + hit kernel) from
+    the committed counter summaries: the entry taken on the current kernel
+    sources, this workload and this tuning, if there is one; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             entries = json.load(f).get("entries", [])
@@ -80,6 +90,15 @@ def measured_traffic(workload, tuning):
         if t.get("source_hash") == h and t.get("workload") == workload and t.get("tuning") == tuning:
             return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
     return None
+
+
+TUNING_KEYS = ("chunk_hits", "big_task_hits", "tile_hits", "wg_per_cu", "window_particles")
+
+
+def parse_tuning(text):
+    """'chunk,big,tile,wg[,window_particles]' -> tuning dict"""
+    vals = [int(x) for x in text.split(",")]
+    return dict(zip(TUNING_KEYS, vals))
 
 
 def _sync(torch):
@@ -169,13 +188,16 @@ def run_fwd_bwd(torch, sim, geo, par, dev, steps, warmup, tuning=None):
     return res
 
 
-def oracle_baseline(w, geo, par, max_threads=16, budget_one=10.0, budget_all=5.0):
-    """The oracle timed on the host: whole passes over the workload on one
-    thread (until about `budget_one` s, at most 5 passes), then the same
-    workload split into event ranges run by independent threads at once
-    (the oracle is re-entrant and releases the interpreter lock while it
-    runs; at most `max_threads`, the CPU share of one GPU) until about
-    `budget_all` s.  Median passes; returns the cpu_baseline record."""
+def oracle_baseline(w, geo, par, max_threads=16, one_core_events=2, budget_one=10.0,
+                    budget_all=10.0):
+    """The oracle timed on the host on a bounded sample of the workload: one
+    thread over its first `one_core_events` events (passes until about
+    `budget_one` s, at most 5), then the whole workload split into event
+    ranges run by independent threads at once (the oracle is re-entrant and
+    its C code runs outside the interpreter lock; at most `max_threads`, the
+    host share of one GPU, whatever nproc reports) until about `budget_all`
+    s, at most 5 passes.  Median passes; returns the cpu_baseline record in
+    hits/s, with the host's nproc."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
@@ -188,32 +210,36 @@ def oracle_baseline(w, geo, par, max_threads=16, budget_one=10.0, budget_all=5.0
                                event_index_base=sw.notes.get("event_index_base", 0),
                                hit_energy_scale=sw.hit_energy_scale)["n_hits_total"]
 
+    sample = W.subset_events(w, 0, min(one_core_events, w.n_events))
     runs = []
     while not runs or (len(runs) < 5 and sum(runs) < budget_one):
         t0 = time.perf_counter()
-        total = run(w)
+        n1 = run(sample)
         runs.append(time.perf_counter() - t0)
     dt = sorted(runs)[len(runs) // 2]
-    one = {"value": total / dt, "cores": 1,
-           "sample": f"the whole {w.name} workload ({w.n_events} events, {total} hits), one "
-                     f"thread, median of {len(runs)} passes ({sum(runs):.1f} s in all)"}
+    one = {"value": n1 / dt, "cores": 1,
+           "sample": f"events 0-{sample.n_events - 1} of {w.name} ({n1} hits), one thread, "
+                     f"median of {len(runs)} passes ({sum(runs):.1f} s in all)"}
     print(f"bench: oracle {one['value']:.4g} hits/s on 1 core", flush=True)
-    n_thr = max(1, min(max_threads, len(os.sched_getaffinity(0)), w.n_events))
+    nproc = len(os.sched_getaffinity(0))
+    n_thr = max(1, min(max_threads, nproc, w.n_events))
     bounds = np.linspace(0, w.n_events, n_thr + 1).astype(int)
     parts = [W.subset_events(w, int(a), int(b - a)) for a, b in zip(bounds[:-1], bounds[1:])
              if b > a]
     runs_n = []
     with ThreadPoolExecutor(max_workers=len(parts)) as ex:
-        while not runs_n or (len(runs_n) < 10 and sum(runs_n) < budget_all):
+        while not runs_n or (len(runs_n) < 5 and sum(runs_n) < budget_all):
             t0 = time.perf_counter()
-            tot = sum(ex.map(run, parts))
+            total = sum(ex.map(run, parts))
             runs_n.append(time.perf_counter() - t0)
-            assert tot == total, (tot, total)
     dt_n = sorted(runs_n)[len(runs_n) // 2]
-    print(f"bench: oracle {total / dt_n:.4g} hits/s on {len(parts)} cores", flush=True)
+    print(f"bench: oracle {total / dt_n:.4g} hits/s on {len(parts)} threads (nproc {nproc})",
+          flush=True)
     return {"value": total / dt_n, "unit": "hits/s", "cores": len(parts), "kind": "oracle",
+            "nproc": nproc, "hits_per_pass": total,
             "sample": f"the whole {w.name} workload ({w.n_events} events, {total} hits) split "
-                      f"into {len(parts)} event ranges run by {len(parts)} threads at once, "
+                      f"into {len(parts)} event ranges run by {len(parts)} threads at once "
+                      f"(capped at {max_threads}, the host share of one GPU; nproc {nproc}), "
                       f"median of {len(runs_n)} passes ({sum(runs_n):.1f} s in all)",
             "one_core": one}
 
@@ -449,34 +475,71 @@ def run_hit_fluct(torch, sim, w, dp, doff, out, cap, tuning, steps, warmup, fp32
             "energy_over_constant": energy[True] / energy[False]}
 
 
-def run_atomic_ceiling(torch, dev, n_cells=191338, n_ops=1 << 25, reps=5):
-    """The device-atomic ceiling of a deposit of one atomic per hit: FP32
-    atomic adds into one event's cell array (191,338 cells, 765 KB) through
-    torch's index_add_ (one atomic add per element on this GPU), at
-    uniformly random cells and at a shower-like hot spot (cells at an
-    exponentially distributed distance, mean 8 cells, from one centre).
-    Atomic adds per second; the hit kernel's privatized deposit (hits
-    counted per cell in LDS) is compared against it."""
-    g = torch.Generator(device=dev)
-    g.manual_seed(1)
-    cells = torch.zeros(n_cells, dtype=torch.float32, device=dev)
-    vals = torch.ones(n_ops, dtype=torch.float32, device=dev)
-    idx_u = torch.randint(0, n_cells, (n_ops,), device=dev, generator=g)
-    dist = torch.empty(n_ops, dtype=torch.float32, device=dev).exponential_(1.0 / 8.0, generator=g)
-    sign = torch.randint(0, 2, (n_ops,), device=dev, generator=g) * 2 - 1
-    idx_h = (n_cells // 2 + sign * dist.long()).clamp_(0, n_cells - 1)
-    res = {"cells": n_cells, "atomics_per_pass": n_ops}
-    for name, idx in (("uniform", idx_u), ("hot_spot", idx_h)):
-        cells.index_add_(0, idx, vals)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            cells.index_add_(0, idx, vals)
-        torch.cuda.synchronize()
-        res[f"{name}_per_s"] = n_ops * reps / (time.perf_counter() - t0)
-    print(f"bench: FP32 atomic adds into 765 KB: {res['uniform_per_s']:.3g}/s uniform, "
-          f"{res['hot_spot_per_s']:.3g}/s at a hot spot", flush=True)
+def run_ceilings(n_cells=191338, n_events_big=100):
+    """Measured ceilings (libfcs_ceilings.so): FP32 device atomic adds into one
+    event's cells (765 KB) and into a 100-event array (76.5 MB), uniform and
+    in wave-sized "showers", with and without the returned value; an HBM
+    copy; Philox4x32-10 draws per second with the shader clock under that
+    load; and the cost of a launch (stream launches, hipGraph replays, a
+    launch the host waits for).  Returns the record."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2103_14737_amd", "libfcs_ceilings.so"))
+    d = C.c_double
+    res = {"atomic_fp32_adds_per_s": {}}
+    n_ops = 1 << 25
+    for cells, label in ((n_cells, "765KB"), (n_cells * n_events_big, "76MB")):
+        for pattern, pname in ((0, "uniform"), (1, "showers"), (2, "rows")):
+            for ret in (0, 1):
+                v = d()
+                rc = lib.fcs_ceil_atomic(0, C.c_longlong(cells), C.c_longlong(n_ops), pattern, ret, 5,
+                                         C.byref(v))
+                assert rc == 0, rc
+                key = f"{label}_{pname}_{'returning' if ret else 'no_return'}"
+                res["atomic_fp32_adds_per_s"][key] = v.value
+    v = d()
+    assert lib.fcs_ceil_copy(0, C.c_longlong(1 << 30), 10, C.byref(v)) == 0
+    res["hbm_copy_bytes_per_s"] = v.value
+    draws, clk = d(), d()
+    assert lib.fcs_ceil_philox(0, N_CU * 8, 4096, C.byref(draws), C.byref(clk)) == 0
+    res["philox"] = {"draws_per_s": draws.value, "clock_hz": clk.value,
+                     "slots_per_draw": PHILOX_SLOTS,
+                     "lane_slots_per_s": draws.value * PHILOX_SLOTS,
+                     "frac_of_valu_peak": draws.value * PHILOX_SLOTS / VALU_SLOT_PEAK,
+                     "valu_peak_at_measured_clock": N_CU * 64 * clk.value,
+                     "frac_at_measured_clock": draws.value * PHILOX_SLOTS / (N_CU * 64 * clk.value)}
+    res["d2h_pinned_bytes_per_s"] = {}
+    for mb in (1, 12, 48):
+        v2 = d()
+        assert lib.fcs_ceil_d2h(0, C.c_longlong(mb << 20), 10, C.byref(v2)) == 0
+        res["d2h_pinned_bytes_per_s"][f"{mb}MB"] = v2.value
+    a, b, c_ = d(), d(), d()
+    assert lib.fcs_ceil_launch(0, 10000, 100, 2000, C.byref(a), C.byref(b), C.byref(c_)) == 0
+    res["launch_us"] = {"stream": a.value, "graph": b.value, "host_waited": c_.value}
+    at = res["atomic_fp32_adds_per_s"]
+    print(f"bench: ceilings: atomics 765KB uniform {at['765KB_uniform_no_return']:.3g}/s "
+          f"(returning {at['765KB_uniform_returning']:.3g}), 76MB uniform "
+          f"{at['76MB_uniform_no_return']:.3g}/s (returning {at['76MB_uniform_returning']:.3g}), "
+          f"showers {at['76MB_showers_no_return']:.3g}/s, rows {at['76MB_rows_no_return']:.3g}/s; "
+          f"HBM copy {v.value / 1e12:.2f} TB/s; D2H to pinned host "
+          f"{res['d2h_pinned_bytes_per_s']['48MB'] / 1e9:.1f} GB/s; "
+          f"Philox {draws.value:.3g} draws/s at {clk.value / 1e9:.2f} GHz; launch "
+          f"{a.value:.2f} us stream, {b.value:.2f} us graph, {c_.value:.1f} us host-waited",
+          flush=True)
     return res
+
+
+def roofline(hits, kernel_ms, workload, tuning):
+    """The roofline object of the hit step (window pass + hit kernel, the
+    dominant kernels) from its HIP-event time per launch: algorithmic VALU
+    instruction slots per launch over that time, against the chip's issue
+    rate at the nominal clock."""
+    achieved = SLOTS_PER_HIT * hits / (kernel_ms * 1e-3)
+    return {"kernel": "hit step (k_windows + k_hits)", "bound": "alu",
+            "achieved": achieved / 1e12, "peak": VALU_SLOT_PEAK / 1e12,
+            "unit": "T VALU lane-instruction slots/s", "frac": achieved / VALU_SLOT_PEAK,
+            "traffic": measured_traffic(workload, tuning),
+            "kernel_source_hash": kernel_source_hash(), "slots_per_hit": SLOTS_PER_HIT,
+            "ops_per_hit": OPS_PER_HIT, "hits_per_launch": hits, "kernel_ms": kernel_ms}
 
 
 def main():
@@ -492,6 +555,8 @@ def main():
                     help="time only the FP64 placement variant on the headline batch")
     ap.add_argument("--fine-tables-only", action="store_true",
                     help="time only the headline batch on 64 x 64-bin tables")
+    ap.add_argument("--ceilings-only", action="store_true",
+                    help="measure only the chip's ceilings and print them")
     ap.add_argument("--sharing-only", action="store_true",
                     help="time only the concurrent-jobs study and print its figures")
     ap.add_argument("--only-headline", action="store_true",
@@ -499,12 +564,15 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default tuning instead of the autotuner's")
     ap.add_argument("--tuning", type=str, default="",
-                    help="chunk_hits,big_task_hits,tile_hits,wg_per_cu (skips the autotuner)")
-    ap.add_argument("--workload", default="single_particle_sweep",
+                    help="chunk_hits,big_task_hits,tile_hits,wg_per_cu[,window_particles] "
+                         "(skips the autotuner)")
+    ap.add_argument("--workload", default="pileup",
                     choices=["single_particle_sweep", "hard_scatter", "pileup"],
                     help="headline workload to time (the other choices are for profiling)")
+    ap.add_argument("--device-outputs", action="store_true",
+                    help="headline steps leave their lists in device memory (for profiling)")
     ap.add_argument("--write-tuning", type=str, default="",
-                    help="write the tuning used as chunk,big,tile,wg to this file")
+                    help="write the tuning used as chunk,big,tile,wg,window_particles to this file")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter scaling)")
     args = ap.parse_args()
@@ -528,18 +596,18 @@ def main():
     load_ms = (time.perf_counter() - t0) * 1e3
 
     if args.fwd_bwd_only:
-        tun = None
-        if args.tuning:
-            c_, b_, t_, w_ = (int(x) for x in args.tuning.split(","))
-            tun = dict(chunk_hits=c_, big_task_hits=b_, tile_hits=t_, wg_per_cu=w_)
+        tun = parse_tuning(args.tuning) if args.tuning else None
         print(json.dumps(run_fwd_bwd(torch, sim, geo, par, dev, args.steps, args.warmup, tun)),
               flush=True)
+        return 0
+    if args.ceilings_only:
+        print(json.dumps(run_ceilings()), flush=True)
         return 0
     if args.sharing_only:
         print(json.dumps(run_sharing(torch, geo, par, dev)), flush=True)
         return 0
     if args.fine_tables_only:
-        w = W.BY_NAME[args.workload]()
+        w = W.BY_NAME["single_particle_sweep"]()
         print(json.dumps(run_fine_tables(torch, geo, dev, w, {}, args.steps, args.warmup)),
               flush=True)
         return 0
@@ -560,7 +628,7 @@ def main():
         return dp, doff, out, cap, q
 
     if args.fp64_placement_only:
-        w = W.BY_NAME[args.workload]()
+        w = W.BY_NAME["single_particle_sweep"]()
         dp, doff, out, cap, q = prepare(w)
         print(json.dumps(run_fp64_placement(torch, sim, w, dp, doff, out, cap, {}, args.steps,
                                             args.warmup, float("nan"))), flush=True)
@@ -568,72 +636,90 @@ def main():
                                        args.warmup, float("nan"))), flush=True)
         return 0
 
-    # ------------------------------------------------ headline: batched sweep
-    w = W.BY_NAME[args.workload]()
-    dp, doff, out, cap, q = prepare(w)
-    hits_per_step = q["n_hits"]
-    print(f"bench: {w.name}: {w.n_events} events, {hits_per_step} hits per step", flush=True)
-    tuning = {}
-    if args.tuning:
-        c_, b_, t_, w_ = (int(x) for x in args.tuning.split(","))
-        tuning = dict(chunk_hits=c_, big_task_hits=b_, tile_hits=t_, wg_per_cu=w_)
-    elif not args.no_autotune:
+    def tune_for(w, dp, doff, out, cap):
+        if args.tuning:
+            return parse_tuning(args.tuning)
+        if args.no_autotune:
+            return {}
         from paper_2103_14737_amd import autotune
         t0 = time.perf_counter()
-        tuning = autotune.tune(sim, dp, doff, w.seed, out=out, cell_capacity=cap,
-                               hit_energy_scale=w.hit_energy_scale,
-                               verbose=bool(os.environ.get("FCS_TUNE_VERBOSE")))
-        print(f"bench: autotuned {tuning} in {time.perf_counter() - t0:.1f} s", flush=True)
+        tun = autotune.tune(sim, dp, doff, w.seed, out=out, cell_capacity=cap,
+                            hit_energy_scale=w.hit_energy_scale,
+                            verbose=bool(os.environ.get("FCS_TUNE_VERBOSE")))
+        print(f"bench: {w.name}: autotuned {tun} in {time.perf_counter() - t0:.1f} s", flush=True)
+        return tun
+
+    def batched(w, dp, doff, out, cap, tun, steps, warmup, host_out):
+        """K asynchronous calls back to back between two synchronizations;
+        with host_out the lists go to two sets of pinned host buffers in
+        turn, sized to the batch's compacted total (+2 %; the DMA copy moves
+        the whole capacity).  Returns (s per step, hit-step ms per launch,
+        totals, host capacity)."""
+        cap_h = cap
+        if host_out:
+            r0 = sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap,
+                                     out=out, hit_energy_scale=w.hit_energy_scale, **tun)
+            cap_h = int(r0["stats"]["n_cells_nonzero"] * 1.02) + 64
+            hbufs = [{"cell_ids": sim.host_empty((cap_h,), np.int64),
+                      "cell_e": sim.host_empty((cap_h,), np.float32),
+                      "event_cell_offsets": sim.host_empty((w.n_events + 1,), np.int64)}
+                     for _ in range(2)]
+
+        def step(i):
+            sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap_h,
+                                out=hbufs[i % 2] if host_out else out, profile=True,
+                                hit_energy_scale=w.hit_energy_scale, async_launch=True,
+                                host_outputs=host_out, **tun)
+
+        for i in range(warmup):
+            step(i)
+        sim.synchronize()
+        _sync(torch)
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(i)
+        st = sim.synchronize()
+        _sync(torch)
+        dt = (time.perf_counter() - t0) / steps
+        assert st["n_calls"] == steps and st["n_hits"] == steps * q_hits[w.name], st
+        if host_out:  # the copies hold what the device compacted
+            ref = sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap,
+                                      out=out, hit_energy_scale=w.hit_energy_scale, **tun)
+            nnz = ref["stats"]["n_cells_nonzero"]
+            hb = hbufs[(steps - 1) % 2]
+            assert np.array_equal(hb["event_cell_offsets"], out["event_cell_offsets"].cpu().numpy())
+            assert np.array_equal(hb["cell_ids"][:nnz], out["cell_ids"][:nnz].cpu().numpy())
+        return dt, st["kernel_ms"] / steps, st, cap_h
+
+    def per_event(w, dp, doff, out, cap, tun, steps=2):
+        def step():
+            r = sim.simulate_events(dp, doff, w.seed, mode="per_event", outputs=("compact",),
+                                    cell_capacity=cap, out=out,
+                                    hit_energy_scale=w.hit_energy_scale, **tun)
+            return r["stats"]["n_hits"]
+        t, res = _time_steps(torch, step, steps, 1)
+        assert all(h == q_hits[w.name] for h in res)
+        return t
+
+    q_hits = {}
+
+    # ------------------------------------------------ headline: pile-up batch
+    w = W.BY_NAME[args.workload]()
+    dp, doff, out, cap, q = prepare(w)
+    q_hits[w.name] = hits_per_step = q["n_hits"]
+    print(f"bench: {w.name}: {w.n_events} events, {hits_per_step} hits per step", flush=True)
+    tuning = tune_for(w, dp, doff, out, cap)
     if args.write_tuning:
         with open(args.write_tuning, "w") as f:
-            t_ = tuning or {}
-            f.write(",".join(str(t_.get(k, 0)) for k in ("chunk_hits", "big_task_hits",
-                                                          "tile_hits", "wg_per_cu")))
-    stats = []
-
-    # Timed steps: the batch is enqueued K times back to back (asynchronous
-    # calls, as a serving loop issues them) between two device
-    # synchronizations; the hit kernel of every step is timed with HIP events
-    # on the library's stream.  fcs_synchronize returns the steps' totals.
-    def step_async():
-        sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap, out=out,
-                            profile=True, hit_energy_scale=w.hit_energy_scale, async_launch=True,
-                            **tuning)
-
-    for _ in range(args.warmup):
-        step_async()
-    sim.synchronize()
-    _sync(torch)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step_async()
-    st = sim.synchronize()
-    _sync(torch)
-    t_step = (time.perf_counter() - t0) / args.steps
-    assert st["n_calls"] == args.steps and st["n_hits"] == args.steps * hits_per_step, st
-    kernel_ms = st["kernel_ms"] / args.steps
+            f.write(",".join(str((tuning or {}).get(k, 0)) for k in TUNING_KEYS))
+    host_out = not args.device_outputs
+    t_step, kernel_ms, st, cap_h = batched(w, dp, doff, out, cap, tuning, args.steps,
+                                           args.warmup, host_out)
     value = hits_per_step / t_step
-    print(f"bench: batched {t_step * 1e3:.3f} ms/step, {value:.4g} hits/s, "
-          f"hit kernel {kernel_ms:.3f} ms", flush=True)
-
-    # the same batch as synchronous calls (each waits for its results)
-    wall = []
-
-    def step_batched(profile=False):
-        t0 = time.perf_counter()
-        r = sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap,
-                                out=out, profile=profile, hit_energy_scale=w.hit_energy_scale,
-                                **tuning)
-        wall.append(time.perf_counter() - t0)
-        stats.append(r["stats"])
-        return r["stats"]["n_hits"]
-
-    t_sync, _ = _time_steps(torch, step_batched, args.steps, 1)
-    timed = stats[-args.steps:]
-    assert all(s["n_hits"] == hits_per_step for s in timed)
-    call_ms = float(np.mean([s["device_ms"] for s in timed]))
-    wall_ms = np.array(wall[-args.steps:]) * 1e3
-    print(f"bench: synchronous calls {t_sync * 1e3:.3f} ms/step", flush=True)
+    nnz = st["n_cells_nonzero"] // args.steps
+    print(f"bench: batched {t_step * 1e3:.3f} ms/step, {value:.4g} hits/s, hit step "
+          f"{kernel_ms:.3f} ms ({'lists copied to pinned host buffers' if host_out else 'lists in device memory'})",
+          flush=True)
 
     line = {
         "metric": METRIC, "value": value, "unit": "hits/s", "n_gpus": 1,
@@ -643,116 +729,94 @@ def main():
         "config": {"workload": args.workload, "n_events": w.n_events,
                    "n_particles": w.n_particles, "seed": w.seed,
                    "hit_energy_scale_MeV": w.hit_energy_scale, "n_cells": geo["n_cells"],
-                   "mode": "batched", "outputs": "compact (cell_id, E) per event",
-                   "hits_per_step": hits_per_step, "tuning": tuning or "library defaults"},
+                   "mode": "batched",
+                   "outputs": ("compact (cell_id, E) per event, copied to pinned host buffers "
+                               "inside each step") if host_out else
+                              "compact (cell_id, E) per event, in device memory",
+                   "hits_per_step": hits_per_step, "cells_per_step": nnz,
+                   "tuning": tuning or "library defaults"},
         "events_per_s": w.n_events / t_step,
-        "synchronous_calls": {"ms_per_step": t_sync * 1e3, "hits_per_s": hits_per_step / t_sync,
-                              "device_ms_per_call": call_ms,
-                              "median_ms": float(np.median(wall_ms)),
-                              "std_ms": float(np.std(wall_ms))},
         "geometry_param_load_ms": load_ms,
     }
-    # roofline of the dominant kernel (the persistent hit kernel)
-    ops = OPS_PER_HIT * hits_per_step
-    achieved = ops / (kernel_ms * 1e-3)
-    # context: one device atomic per hit could not reach this rate
+    line["roofline"] = roofline(hits_per_step, kernel_ms, args.workload, tuning)
+    line["d2h_bytes_per_step"] = cap_h * 12 + (w.n_events + 1) * 8 if host_out else 0
+
     if not args.only_headline:
-        ceil = run_atomic_ceiling(torch, dev)
-        ceil["hits_per_s_over_uniform"] = value / ceil["uniform_per_s"]
-        ceil["hits_per_s_over_hot_spot"] = value / ceil["hot_spot_per_s"]
-        line["atomic_ceiling"] = ceil
-    line["roofline"] = {"kernel": "k_hits", "bound": "alu", "achieved": achieved / 1e12,
-                        "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tops/s",
-                        "frac": achieved / VALU_LANE_OPS_PEAK,
-                        "traffic": measured_traffic(args.workload, tuning),
-                        "kernel_source_hash": kernel_source_hash(),
-                        "ops_per_hit": OPS_PER_HIT, "hits_per_launch": hits_per_step,
-                        "kernel_ms": kernel_ms}
+        t_dev, k_dev, _, _ = batched(w, dp, doff, out, cap, tuning, args.steps, args.warmup, False)
+        line["device_resident"] = {"ms_per_step": t_dev * 1e3, "hits_per_s": hits_per_step / t_dev,
+                                   "hit_step_ms": k_dev}
+        print(f"bench: lists kept in device memory: {t_dev * 1e3:.3f} ms/step", flush=True)
+        # the same batch as synchronous calls (each waits for its results)
+        wall = []
 
-    if not args.only_headline and args.workload == "single_particle_sweep":
-        # -------------------------------------------- per-event launch form
-        pe_steps = max(1, min(2, args.steps))
-        stats.clear()
-
-        def step_per_event():
-            r = sim.simulate_events(dp, doff, w.seed, mode="per_event", outputs=("compact",),
-                                    cell_capacity=cap, out=out, **tuning)
+        def step_sync():
+            t0 = time.perf_counter()
+            r = sim.simulate_events(dp, doff, w.seed, outputs=("compact",), cell_capacity=cap,
+                                    out=out, hit_energy_scale=w.hit_energy_scale, **tuning)
+            wall.append(time.perf_counter() - t0)
             return r["stats"]["n_hits"]
 
-        t_pe, res = _time_steps(torch, step_per_event, pe_steps, 1)
-        assert all(h == hits_per_step for h in res)
-        line["per_event_launch"] = {"ms_per_step": t_pe * 1e3,
-                                    "hits_per_s": hits_per_step / t_pe,
-                                    "events_per_s": w.n_events / t_pe, "steps": pe_steps}
-        line["batched_over_per_event"] = t_pe / t_step
-        print(f"bench: per-event {t_pe * 1e3:.1f} ms/step -> batched is "
-              f"{t_pe / t_step:.1f}x faster", flush=True)
+        t_sync, _ = _time_steps(torch, step_sync, args.steps, 1)
+        wall_ms = np.array(wall[-args.steps:]) * 1e3
+        line["synchronous_calls"] = {"ms_per_step": t_sync * 1e3,
+                                     "hits_per_s": hits_per_step / t_sync,
+                                     "median_ms": float(np.median(wall_ms)),
+                                     "std_ms": float(np.std(wall_ms))}
+        t_pe = per_event(w, dp, doff, out, cap, tuning)
+        line["per_event_launch"] = {"ms_per_step": t_pe * 1e3, "hits_per_s": hits_per_step / t_pe,
+                                    "events_per_s": w.n_events / t_pe, "steps": 2,
+                                    "outputs": "compact, device memory"}
+        line["batched_over_per_event"] = t_pe / t_dev
+        print(f"bench: per-event {t_pe * 1e3:.2f} ms/step -> batched (device lists) is "
+              f"{t_pe / t_dev:.2f}x faster", flush=True)
 
-        line["per_task_launch"] = run_per_task(torch, sim, prepare, w, 500, value)
-
-        line["fwd_bwd"] = run_fwd_bwd(torch, sim, geo, par, dev, args.steps, args.warmup)
-
-        # ---------------------------------------- multi-particle workloads
+        # -------------------------------------------- the other two batches
         others = {}
-        for wo in (W.hard_scatter(), W.pileup()):
+        for key_o, wo in (("hard_scatter", W.hard_scatter()),
+                          ("single_particle_sweep", W.single_particle_sweep())):
             dpo, doffo, outo, capo, qo = prepare(wo)
-
-            tun_o = {}
-            if not args.no_autotune:
-                from paper_2103_14737_amd import autotune
-                tun_o = autotune.tune(sim, dpo, doffo, wo.seed, out=outo, cell_capacity=capo,
-                                      hit_energy_scale=wo.hit_energy_scale)
-
-            def step_o():
-                sim.simulate_events(dpo, doffo, wo.seed, outputs=("compact",),
-                                    cell_capacity=capo, out=outo,
-                                    hit_energy_scale=wo.hit_energy_scale, async_launch=True,
-                                    **tun_o)
-
-            n_o = max(2, args.steps // 2)
-            step_o()
-            sim.synchronize()
-            _sync(torch)
-            t0 = time.perf_counter()
-            for _ in range(n_o):
-                step_o()
-            st_o = sim.synchronize()
-            _sync(torch)
-            t_o = (time.perf_counter() - t0) / n_o
-            assert st_o["n_hits"] == n_o * qo["n_hits"], st_o
-
-            # the per-event launch form of the same batch
-            def step_o_pe():
-                r = sim.simulate_events(dpo, doffo, wo.seed, mode="per_event", outputs=("compact",),
-                                        cell_capacity=capo, out=outo,
-                                        hit_energy_scale=wo.hit_energy_scale, **tun_o)
-                return r["stats"]["n_hits"]
-
-            t_pe_o, res_o = _time_steps(torch, step_o_pe, 2, 1)
-            assert all(h == qo["n_hits"] for h in res_o)
-            others[wo.name] = {"hits_per_step": qo["n_hits"], "ms_per_step": t_o * 1e3,
-                               "hits_per_s": qo["n_hits"] / t_o,
-                               "events_per_s": wo.n_events / t_o,
-                               "hit_energy_scale_MeV": wo.hit_energy_scale,
-                               "tuning": tun_o or "library defaults",
-                               "per_event_launch": {"ms_per_step": t_pe_o * 1e3,
-                                                    "hits_per_s": qo["n_hits"] / t_pe_o,
-                                                    "events_per_s": wo.n_events / t_pe_o,
-                                                    "steps": 2},
-                               "batched_over_per_event": t_pe_o / t_o}
-            if wo.name.startswith("hard_scatter"):
-                others[wo.name]["per_task_launch"] = run_per_task(
-                    torch, sim, prepare, wo, 5, qo["n_hits"] / t_o)
-            print(f"bench: {wo.name} {qo['n_hits'] / t_o:.4g} hits/s; per-event "
-                  f"{t_pe_o * 1e3:.1f} ms/step -> batched is {t_pe_o / t_o:.1f}x faster", flush=True)
-            del dpo, doffo, outo
+            q_hits[wo.name] = qo["n_hits"]
+            tun_o = tune_for(wo, dpo, doffo, outo, capo)
+            n_o = max(2, args.steps)
+            t_h, k_h, st_h, _ = batched(wo, dpo, doffo, outo, capo, tun_o, n_o, args.warmup, True)
+            t_d, k_d, _, _ = batched(wo, dpo, doffo, outo, capo, tun_o, n_o, args.warmup, False)
+            t_pe_o = per_event(wo, dpo, doffo, outo, capo, tun_o)
+            rec = {"hits_per_step": qo["n_hits"], "ms_per_step": t_h * 1e3,
+                   "hits_per_s": qo["n_hits"] / t_h, "events_per_s": wo.n_events / t_h,
+                   "outputs": "compact, copied to pinned host buffers",
+                   "device_resident": {"ms_per_step": t_d * 1e3, "hits_per_s": qo["n_hits"] / t_d},
+                   "hit_energy_scale_MeV": wo.hit_energy_scale,
+                   "tuning": tun_o or "library defaults",
+                   "per_event_launch": {"ms_per_step": t_pe_o * 1e3,
+                                        "hits_per_s": qo["n_hits"] / t_pe_o,
+                                        "events_per_s": wo.n_events / t_pe_o, "steps": 2},
+                   "batched_over_per_event": t_pe_o / t_d,
+                   "roofline": roofline(qo["n_hits"], k_d, key_o, tun_o)}
+            n_pt = 5 if wo.name.startswith("hard") else 500
+            rec["per_task_launch"] = run_per_task(torch, sim, prepare, wo, n_pt, qo["n_hits"] / t_d)
+            others[wo.name] = rec
+            print(f"bench: {wo.name} {qo['n_hits'] / t_h:.4g} hits/s with the copies "
+                  f"({qo['n_hits'] / t_d:.4g} device lists); per-event {t_pe_o * 1e3:.1f} ms/step "
+                  f"-> batched is {t_pe_o / t_d:.1f}x faster; hit step {k_d:.3f} ms", flush=True)
+            if wo.name.startswith("single_particle_sweep"):
+                sweep = (wo, dpo, doffo, outo, capo, tun_o, qo["n_hits"] / t_d)
+            else:
+                del dpo, doffo, outo
         line["other_workloads"] = others
+        line["fwd_bwd"] = run_fwd_bwd(torch, sim, geo, par, dev, args.steps, args.warmup)
         line["gpu_sharing"] = run_sharing(torch, geo, par, dev)
-        line["fine_tables"] = run_fine_tables(torch, geo, dev, w, tuning, args.steps, args.warmup)
-        line["placement_fp64"] = run_fp64_placement(torch, sim, w, dp, doff, out, cap, tuning,
-                                                    args.steps, args.warmup, value)
-        line["hit_energy_fluct"] = run_hit_fluct(torch, sim, w, dp, doff, out, cap, tuning,
-                                                 args.steps, args.warmup, value)
+        ws, dps, doffs, outs, caps, tuns, rate_s = sweep
+        line["fine_tables"] = run_fine_tables(torch, geo, dev, ws, tuns, args.steps, args.warmup)
+        line["placement_fp64"] = run_fp64_placement(torch, sim, ws, dps, doffs, outs, caps, tuns,
+                                                    args.steps, args.warmup, rate_s)
+        line["hit_energy_fluct"] = run_hit_fluct(torch, sim, ws, dps, doffs, outs, caps, tuns,
+                                                 args.steps, args.warmup, rate_s)
+        line["ceilings"] = run_ceilings()
+        ph = line["ceilings"]["philox"]
+        line["roofline"]["frac_at_measured_clock"] = (
+            line["roofline"]["achieved"] * 1e12 / ph["valu_peak_at_measured_clock"])
+        line["roofline"]["measured_ceiling"] = {
+            "philox_only_lane_slots_per_s": ph["lane_slots_per_s"], "clock_hz": ph["clock_hz"]}
 
     if args.copy_probe_mb:
         # a plain device copy of known size: the HBM counters of the profiled

@@ -86,6 +86,15 @@ typedef struct {
 
 int fcs_get_info(const fcs_ctx *ctx, fcs_info *info);
 
+/* Pinned host memory of `bytes` bytes on the context's device (its own
+ * allocation, device-writable through its mapping), for the outputs of
+ * asynchronous calls that leave their {cell_id, E} lists on the host (see
+ * fcs_sim_options.async_launch).  *ptr is NULL on failure (FCS_E_NOMEM,
+ * FCS_E_NO_DEVICE for a device-less context).  fcs_host_free waits for the
+ * context's copies to the host, then releases it; NULL is a no-op. */
+int fcs_host_alloc(fcs_ctx *ctx, int64_t bytes, void **ptr);
+int fcs_host_free(fcs_ctx *ctx, void *ptr);
+
 /* ------------------------------------------------------------------------
  * Geometry (CUDA Implementation section: the cell and region data are
  * flattened into arrays and copied to the GPU once).
@@ -224,9 +233,20 @@ typedef struct {
                                    event_offsets[n_events] back, one
                                    device-to-host round trip per call       */
     int32_t async_launch;       /* 1: enqueue the batch and return without
-                                   waiting (batched mode, device inputs and
-                                   outputs, n_particles given).  opt->stream
-                                   is made to wait for the results.  The
+                                   waiting (batched mode, device inputs,
+                                   n_particles given; device outputs, or
+                                   FCS_OUT_COMPACT alone into pinned host
+                                   buffers from fcs_host_alloc: then the
+                                   batch compacts into one of two device
+                                   staging sets used in turn, and the DMA
+                                   engine copies the event offsets and
+                                   cell_capacity entries of each list to
+                                   the host on a second stream while the
+                                   next batch runs: size cell_capacity to
+                                   the expected compacted total, the
+                                   entries past it are not meaningful).
+                                   opt->stream is made to wait for the
+                                   results.  The
                                    out->n_* fields are not known and are set
                                    to -1; event_cell_offsets[n_events] holds
                                    the compacted total on the device.
@@ -267,6 +287,21 @@ typedef struct {
                                    the task's hits of x g(cell), and the
                                    weight gradient takes each hit's own
                                    energy.  Default 0.                      */
+    int32_t window_pass;         /* how the (particle, layer) tasks below
+                                   big_task_hits are deposited: 0 = by cell
+                                   windows when the launch averages at least
+                                   64 particles per event, else in packed
+                                   tiles; 1 = by cell windows; -1 = in tiles.
+                                   The window pass takes an event, a window
+                                   of consecutive cells of one layer and a
+                                   range of particles per work item, sums
+                                   the hits landing in the window in LDS and
+                                   adds them with coalesced atomics.  Not
+                                   with placement_fp64, hit_energy_fluct or
+                                   FCS_MODE_PER_TASK (tiles then).  Results
+                                   as in every other form.                  */
+    int32_t window_particles;    /* tuning, 0 = default (1024): particles per
+                                   work item of the window pass, 64..65536  */
 } fcs_sim_options;
 
 /* Fill *opt with the defaults: seed 0, batched, compact output, 100 MeV per

@@ -1,5 +1,6 @@
 """Autotuner for the batched launch: picks chunk size, large-task threshold,
-tile size and persistent workgroups per CU for a workload by timing the
+tile size (or, for events of many particles, the window pass's particles
+per work item) and persistent workgroups per CU for a workload by timing the
 candidates on the device, and caches the choice in a JSON file keyed by the
 device and a signature of the workload.
 
@@ -14,15 +15,27 @@ import time
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fcs_mi355x_tune.json")
 
-# (chunk_hits, big_task_hits, tile_hits, wg_per_cu)
+# (chunk_hits, big_task_hits, tile_hits, wg_per_cu, window_particles)
 CANDIDATES = [
-    (c, b, t, w)
+    (c, b, t, w, 0)
     for c in (1024, 2048, 4096, 8192)
     for b in (32, 64, 128, 256)
     for t in (256, 512)
     for w in (3, 4, 5, 8)
     if b <= t
 ]
+# batches of many particles per event deposit their small tasks by cell
+# windows (the tiles are not used): the window pass's particles per work item
+# replace the tile size
+WINDOW_CANDIDATES = [
+    (c, b, 512, w, p)
+    for c in (1024, 2048, 4096)
+    for b in (64, 128, 256)
+    for w in (4, 8)
+    for p in (1024, 2048)
+]
+# the library's rule for the window pass (particles per event on average)
+WINDOW_MIN_PARTICLES_PER_EVENT = 64
 
 
 def signature(n_events, n_particles, n_hits, n_cells, outputs):
@@ -65,11 +78,14 @@ def tune(sim, particles, event_offsets, seed, *, outputs=("compact",), hit_energ
     cache = _load(cache_path)
     if not force and key in cache:
         return dict(cache[key]["tuning"])
-    cands = candidates or CANDIDATES
+    dense = n_particles >= WINDOW_MIN_PARTICLES_PER_EVENT * n_events
+    cands = candidates or (WINDOW_CANDIDATES if dense else CANDIDATES)
     cap = q["max_cells"] if cell_capacity is None else cell_capacity
     results = []
-    for (c, b, t, w) in cands:
+    for (c, b, t, w, p) in cands:
         kw = dict(chunk_hits=c, big_task_hits=b, tile_hits=t, wg_per_cu=w)
+        if p:
+            kw["window_particles"] = p
         run = lambda: sim.simulate_events(particles, event_offsets, seed, outputs=outputs,  # noqa: E731
                                           hit_energy_scale=hit_energy_scale,
                                           cell_capacity=cap, out=out, **kw)

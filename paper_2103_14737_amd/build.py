@@ -11,6 +11,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "fcs_runtime.hip")
 LIB = os.path.join(PKG, "libfcs.so")
+# measured ceilings of the chip (atomics, HBM copy, VALU, launches): benchmark only
+CEIL_SRC = os.path.join(PKG, "csrc", "fcs_ceilings.hip")
+CEIL_LIB = os.path.join(PKG, "libfcs_ceilings.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -21,15 +24,22 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
+def _compile(src: str, lib: str, verbose: bool) -> str:
+    tmp = lib + ".tmp"
     cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-           SRC, "-o", tmp]
+           src, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libfcs.so (the C ABI) and libfcs_ceilings.so (the benchmark's
+    ceiling measurements); returns the path of libfcs.so."""
+    _compile(CEIL_SRC, CEIL_LIB, verbose)
+    return _compile(SRC, LIB, verbose)
 
 
 if __name__ == "__main__":

@@ -32,6 +32,10 @@ constexpr int kSegPerWave = 8;            // segments counted by one wave
 constexpr int kTileMax = 512;             // max hits of one packed tile (one wave)
 constexpr int kQueues = 8;                // work-queue ranges (one ticket each)
 constexpr int kQueueStride = 64;          // ints between tickets: one 256-byte line each
+// the queue block: kQueues tickets, kQueues drained flags, then the ticket of
+// the window pass (k_windows)
+constexpr int kWinTicket = 2 * kQueues;
+constexpr int kQueueInts = (2 * kQueues + 1) * kQueueStride;
 
 struct Particle {
     int32_t pdg;
@@ -52,6 +56,7 @@ struct Counters {
     int32_t error;        // bit set, see kErr*
     int32_t need_chunks;  // chunk entries required when over capacity
     uint32_t done;        // workgroups of the count-reset pass that finished
+    int32_t max_event_particles;  // window pass: particles of the largest event
     long long n_blk_list; // nonzero 64-cell blocks listed by the compaction
 };
 
@@ -127,6 +132,13 @@ struct Params {
     int32_t hit_fluct;     // per-hit energy fluctuation (chain variant)
     int32_t validate;      // check device-resident inputs in the setup
     int32_t n_seg_groups;  // groups of kSegGroup segments
+    // window pass (multi-particle events): the small tasks of each (event,
+    // cell window of a layer, range of win_parts particles) are deposited by
+    // k_windows instead of the tiles of k_hits
+    int32_t win_path;
+    int32_t win_parts;     // particles per work item of the window pass
+    int32_t n_windows;
+    const int4* geo_windows;  // [n_windows * 2] see WinRec
     // workspace
     int32_t* task_n;
     float* task_ehit;
@@ -152,7 +164,7 @@ struct Params {
     unsigned long long* blk_list;  // [n_events * n_seg * kSegBlocks] position << 32 | (event << blk_shift | block)
     Counters* ctr;
     AsyncAcc* fold_acc;   // asynchronous calls with compaction: k_seg_top folds the totals here
-    int32_t* queue;      // [kQueues * kQueueStride * 2]: tickets, then drained flags
+    int32_t* queue;      // [kQueueInts]: tickets, drained flags, window-pass ticket
     // outputs (device)
     float* out_elayer;
     int32_t* out_counts;
@@ -249,6 +261,19 @@ __device__ __forceinline__ void gor(FCS_AS_GLOBAL T* p, T v)
 {
     (void)__hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+template <typename T>
+__device__ __forceinline__ void gmax(FCS_AS_GLOBAL T* p, T v)
+{
+    (void)__hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// the window pass needs the particle count of the largest event: the first
+// particle of each event reports its event's count
+__device__ __forceinline__ void note_event_size(const Params& P, int ev, uint32_t pin)
+{
+    if (P.win_path && pin == 0)
+        gmax(&G(P.ctr)->max_event_particles, (int32_t)(G(P.ev_off)[ev + 1] - G(P.ev_off)[ev]));
+}
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
@@ -303,16 +328,18 @@ __device__ __forceinline__ int4 block_excl_scan4(int4 v, int4& total)
 }
 
 
+// sum over a workgroup of kThreads threads (every thread calls it)
+template <int kThreads = kBlock>
 __device__ __forceinline__ long long block_sum_ll(long long v)
 {
-    __shared__ long long red[kBlock / kWave];
+    __shared__ long long red[kThreads / kWave];
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
     if (lane_id() == 0) red[threadIdx.x / kWave] = v;
     __syncthreads();
     long long t = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
+    for (int w = 0; w < kThreads / kWave; ++w) t += red[w];
     __syncthreads();
     return t;
 }
@@ -485,6 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_one(const Params* __restrict__
         ev = find_event(G(P.ev_off), P.n_events, P.part_base + gp);
         pin = (uint32_t)(P.part_base + gp - G(P.ev_off)[ev]);
         evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
+        if (l == 0) note_event_size(P, ev, pin);
         set = select_set(P, pt.pdg, pt.e, pt.eta);
         if (set >= 0) {
             const int ty = set / (P.n_ebins * P.n_etabins);
@@ -633,6 +661,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
         const int ev = find_event(G(P.ev_off), P.n_events, P.part_base + gp);
         const uint32_t pin = (uint32_t)(P.part_base + gp - G(P.ev_off)[ev]);
         const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)ev);
+        note_event_size(P, ev, pin);
         const int set = select_set(P, pt.pdg, pt.e, pt.eta);
         s_set[lp] = set;
         s_pin[lp] = pin;
@@ -819,7 +848,7 @@ __device__ __forceinline__ void scan1024(long long h, int4 r, long long& ho, int
 __device__ __forceinline__ void scan_totals(const Params& P, long long htot, int4 rtot)
 {
     const int tid = threadIdx.x;
-    if (tid < 2 * kQueues) G(P.queue)[tid * kQueueStride] = 0;
+    if (tid <= kWinTicket) G(P.queue)[tid * kQueueStride] = 0;
     if (tid == 0) {
         auto cc = G(P.ctr);
         cc->hits_total = htot;
@@ -955,7 +984,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_write(const Params* __restrict_
         const int cnt = min(P.chunk_hits, n - first);
         store_i4(P.chunks, run.y + c, make_int4(key, first, cnt, 0));
     }
-    if (d.w) {
+    if (d.w && !P.win_path) {
         // two 16-byte records per small task: (first small hit, task key,
         // Ehit bits, histogram) and (eta_p, phi_p, global event, particle
         // in event)
@@ -1051,8 +1080,8 @@ __device__ __forceinline__ GeoLds stage_geometry(const Params& P, v4i* s_geo)
     const int nr = 2 * P.n_layers * P.n_regions;
     const FCS_AS_GLOBAL v4i* gl = (const FCS_AS_GLOBAL v4i*)P.geo_layers;
     const FCS_AS_GLOBAL v4i* gr = (const FCS_AS_GLOBAL v4i*)P.geo_regions;
-    for (int i = threadIdx.x; i < nl; i += kBlock) s_geo[i] = gl[i];
-    for (int i = threadIdx.x; i < nr; i += kBlock) s_geo[nl + i] = gr[i];
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) s_geo[i] = gl[i];
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) s_geo[nl + i] = gr[i];
     return GeoLds{s_geo, s_geo + nl, P.n_regions};
 }
 
@@ -1522,7 +1551,8 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
     const auto ctr = G(P.ctr);
     if (ctr->error & (kErrTooManyHits | kErrChunkCap)) return;
     const int n_chunks = ctr->n_chunks;
-    const int n_items = n_chunks + ctr->n_tiles;
+    // with the window pass the small tasks are deposited by k_windows
+    const int n_items = n_chunks + (P.win_path ? 0 : ctr->n_tiles);
     const int active_wg = active_workgroups(n_items);
     if ((int)blockIdx.x >= active_wg) return;
     const float dr = P.r_max / 32.0f;
@@ -1645,6 +1675,213 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
         }
     }
     const long long tot = block_sum_ll(n_out);
+    if (threadIdx.x == 0 && tot) (void)gfetch_add(&G(P.ctr)->hits_out, tot);
+}
+
+// --------------------------------- small tasks by cell window (a8, a11) ---
+// Events of many particles (hard scatter, pile-up) put most of their hits in
+// (particle, layer) tasks of a few hits each, scattered over the event's
+// cells; depositing them with one device atomic per distinct cell of a tile
+// step is bound by the memory-side atomic unit, which handles one cache line
+// per operation.  This pass instead takes, per work item, one event, one
+// window of at most kWinCells consecutive cells of one layer and a range of
+// win_parts particles: the small tasks of those particles in that layer are
+// simulated (particles whose hits cannot reach the window are skipped), the
+// hits landing in the window are summed in a dense LDS copy of it, and the
+// touched rows are added to the event's cells with coalesced atomics (64
+// consecutive cells per wave instruction, 16 per cache line).  Hits are
+// counted out of acceptance, and written to the hit list, by the particle's
+// home window (the one whose eta band holds it) only.
+constexpr int kWinThreads = 512;
+constexpr int kWinWaves = kWinThreads / kWave;
+constexpr int kWinCells = 14336;  // 56 KB of LDS: two workgroups per CU
+constexpr int kFlushWords = 4;    // count words (1,024 cells) per wave and flush round
+static_assert(kWinCells % 64 == 0, "windows are whole 64-cell rows of LDS");
+
+// window record, two int4 per window: (layer, first cell, end cell, index of
+// the layer's first window), (eta band low, eta band high (float bits),
+// windows of the layer, -)
+struct WinRec {
+    int layer, c_lo, c_hi, first;
+    float b_lo, b_hi;
+    int n_layer;
+};
+
+// from the copy staged in LDS after the geometry records
+__device__ __forceinline__ WinRec load_window(const v4i* s_win, int w)
+{
+    const v4i a = s_win[2 * w];
+    const v4i b = s_win[2 * w + 1];
+    return WinRec{a.x, a.y, a.z, a.w, __int_as_float(b.x), __int_as_float(b.y), b.z};
+}
+
+__global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restrict__ Pp)
+{
+    const Params& P = *Pp;
+    extern __shared__ v4i s_geo[];
+    __shared__ float s_acc[kWinCells];
+    __shared__ int s_end[kWinThreads];    // inclusive prefix of the staged tasks' hits
+    __shared__ v4i s_pa[kWinThreads];     // (histogram | home << 31, Ehit, eta, phi)
+    __shared__ int2 s_pb[kWinThreads];    // (particle in event, task)
+    __shared__ int s_wsum[kWinWaves];
+    __shared__ int s_item;
+
+    const auto ctr = G(P.ctr);
+    if (!P.win_path || (ctr->error & (kErrTooManyHits | kErrChunkCap))) return;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int L = P.n_layers;
+    const long long E = P.n_events;
+    const long long n_cells = P.n_cells;
+    const int max_np = ctr->max_event_particles;
+    const int n_pr = (max_np + P.win_parts - 1) / P.win_parts;  // particle ranges per event
+    const long long n_items = (long long)P.n_windows * E * n_pr;
+    if (n_items == 0) return;
+    const float dr = P.r_max / 32.0f;
+    const uint32_t k0 = P.key0, k1 = P.key1;
+    long long n_out = 0;
+
+    const GeoLds geo = stage_geometry(P, s_geo);
+    // the window records follow the geometry records in the dynamic LDS
+    v4i* s_win = s_geo + 3 * P.n_layers + 2 * P.n_layers * P.n_regions;
+    for (int i = tid; i < 2 * P.n_windows; i += kWinThreads) s_win[i] = ((const FCS_AS_GLOBAL v4i*)P.geo_windows)[i];
+    for (int c = tid; c < kWinCells; c += kWinThreads) s_acc[c] = 0.0f;
+    const auto ticket = G(P.queue) + kWinTicket * kQueueStride;
+    if (tid == 0) s_item = gfetch_add(ticket, 1);
+    for (;;) {
+        __syncthreads();  // the previous item's flush is complete; s_item is set
+        const long long item = s_item;
+        __syncthreads();  // every thread has read it
+        if (item >= n_items) break;
+        // the next item's ticket is taken now, its latency hidden behind this one
+        if (tid == 0) s_item = gfetch_add(ticket, 1);
+        // window-major order: the windows of the first layers (the most hits)
+        // are handed out first
+        const int r = (int)(item % n_pr);
+        const long long e = (item / n_pr) % E;
+        const int w = (int)(item / ((long long)n_pr * E));
+        const WinRec win = load_window(s_win, w);
+        const int l = win.layer;
+        const LayerRec lrec = layer_rec(geo, l);
+        // particles of this launch in event e, this item's range of them
+        const long long ev0 = G(P.ev_off)[e] - P.part_base, ev1 = G(P.ev_off)[e + 1] - P.part_base;
+        const long long a = ev0 + (long long)r * P.win_parts;
+        const long long b = min(ev1, a + (long long)P.win_parts);
+        if (a >= b) continue;
+        const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)e);
+        // a hit lands at most r_max / R_l away in eta (margins for rounding)
+        const float reach = P.r_max * f_of(lrec.a.z) * 1.001f + 1e-3f;
+        for (long long pb = a; pb < b; pb += kWinThreads) {
+            const long long p = pb + tid;
+            int n = 0;
+            if (p < b) {
+                const long long t = p * L + l;
+                const int nt = G(P.task_n)[t];
+                if (nt > 0 && nt < P.big_thr) {
+                    const Particle pt = load_particle(P.particles, p);
+                    // home window: the one of this layer whose band holds eta
+                    int home = win.first;
+                    for (int k = win.first; k < win.first + win.n_layer - 1; ++k) {
+                        const WinRec wk = load_window(s_win, k);
+                        home += pt.eta >= wk.b_hi ? 1 : 0;
+                    }
+                    const bool is_home = home == w;
+                    if (is_home || (pt.eta >= win.b_lo - reach && pt.eta <= win.b_hi + reach)) {
+                        n = nt;
+                        const int H = G(P.part_set)[p] * L + l;
+                        s_pa[tid] = v4i{H | (is_home ? (int)0x80000000u : 0),
+                                        __float_as_int(G(P.task_ehit)[t]), __float_as_int(pt.eta),
+                                        __float_as_int(pt.phi)};
+                        s_pb[tid] = make_int2((int)G(P.part_p)[p], (int)t);
+                    }
+                }
+            }
+            // inclusive block prefix of the staged hits
+            const int inc = wave_incl_scan(n);
+            if (lane == kWave - 1) s_wsum[wave] = inc;
+            __syncthreads();
+            int before = 0, total = 0;
+#pragma unroll
+            for (int k = 0; k < kWinWaves; ++k) {
+                const int v = s_wsum[k];
+                before += k < wave ? v : 0;
+                total += v;
+            }
+            s_end[tid] = before + inc;
+            __syncthreads();
+            for (int q0 = 0; q0 < total; q0 += kWinThreads) {
+                const int q = q0 + tid;
+                if (q < total) {
+                    // owner: the first staged slot whose prefix end exceeds q
+                    int lo = 0, hi = kWinThreads - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_end[mid] > q) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    const int j = lo;
+                    const int i = q - (j ? s_end[j - 1] : 0);  // hit index within its task
+                    const v4i pa = s_pa[j];
+                    const int2 pbk = s_pb[j];
+                    const int H = pa.x & 0x7fffffff;
+                    const float ehit = __int_as_float(pa.y);
+                    const HitOut h = simulate_hit<false>(geo, lrec, G(P.cum) + (long long)H * kBins,
+                                                         G(P.guide) + (long long)H * kGuide, dr, k0, k1,
+                                                         (uint32_t)i, (uint32_t)l, (uint32_t)pbk.x, evg,
+                                                         __int_as_float(pa.z), __int_as_float(pa.w));
+                    if (h.cell >= win.c_lo && h.cell < win.c_hi) atomicAdd(&s_acc[h.cell - win.c_lo], ehit);
+                    if (pa.x < 0) {  // home window
+                        n_out += h.cell < 0 ? 1 : 0;
+                        if (P.want_hits) write_hit(P, (long long)G(P.task_hoff)[pbk.y] + i, h, ehit);
+                    }
+                }
+            }
+            __syncthreads();  // the staged slots are reused by the next range
+        }
+        // flush the window: each wave takes kFlushWords count words (four
+        // 64-cell blocks of the event's cells each) per round, issues the
+        // coalesced atomic adds of all their nonzero rows, and only then
+        // reads the returned values: the adds that find a cell at zero count
+        // it, one count-word atomic per word
+        {
+            constexpr int kFW = kFlushWords, kR = 4 * kFlushWords;
+            const long long g0 = win.c_lo, g1 = win.c_hi;  // [g0, g1)
+            const auto cells = G(P.cells) + e * n_cells;
+            const long long wlast = (g1 - 1) >> 8;
+            for (long long wd = (g0 >> 8) + (long long)wave * kFW; wd <= wlast; wd += (long long)kWinWaves * kFW) {
+                float v[kR], old[kR];
+#pragma unroll
+                for (int k = 0; k < kR; ++k) {
+                    const long long g = wd * 256 + k * 64 + lane;
+                    const bool in = g >= g0 && g < g1;
+                    const float a = s_acc[in ? (int)(g - g0) : 0];
+                    v[k] = in ? a : 0.0f;
+                }
+#pragma unroll
+                for (int k = 0; k < kR; ++k) {
+                    old[k] = 1.0f;
+                    if (v[k] != 0.0f) {
+                        const long long g = wd * 256 + k * 64 + lane;
+                        [[clang::atomic(ignore_denormal_mode)]] {
+                            old[k] = __hip_atomic_fetch_add(cells + g, v[k], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        s_acc[g - g0] = 0.0f;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kFW; ++q) {
+                    uint32_t word = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        word |= (uint32_t)__popcll(__ballot(old[4 * q + k] == 0.0f)) << (8 * k);
+                    if (lane == 0 && word)
+                        (void)gfetch_add(
+                            (FCS_AS_GLOBAL uint32_t*)(G(P.flags) + ((e << P.blk_shift) + (wd + q) * 4)), word);
+                }
+            }
+        }
+    }
+    const long long tot = block_sum_ll<kWinThreads>(n_out);
     if (threadIdx.x == 0 && tot) (void)gfetch_add(&G(P.ctr)->hits_out, tot);
 }
 

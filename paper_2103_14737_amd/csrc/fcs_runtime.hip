@@ -35,11 +35,11 @@ struct DevBuf {
 
 struct GraphKey {
     long long n_particles, n_events;
-    int mode, grid, part, f64;
+    int mode, grid, part, f64, win;
     bool operator<(const GraphKey& o) const
     {
-        return std::tie(n_particles, n_events, mode, grid, part, f64) <
-               std::tie(o.n_particles, o.n_events, o.mode, o.grid, o.part, o.f64);
+        return std::tie(n_particles, n_events, mode, grid, part, f64, win) <
+               std::tie(o.n_particles, o.n_events, o.mode, o.grid, o.part, o.f64, o.win);
     }
 };
 
@@ -50,6 +50,11 @@ constexpr size_t kBlockBytes = kCtrOffset + ((sizeof(Counters) + 255) & ~(size_t
 }  // namespace
 
 constexpr int kRing = 16;      // pinned parameter blocks
+constexpr int kMaxWindows = 256;  // cell windows of the window pass per geometry (staged in LDS)
+// the window pass is used for launches of at least this many particles per
+// event on average (hard-scatter and pile-up events; single-particle events
+// keep the packed tiles)
+constexpr long long kWinMinParticlesPerEvent = 64;
 constexpr int kProfRing = 64;  // event pairs of profiled asynchronous calls
 
 struct fcs_ctx {
@@ -71,6 +76,8 @@ struct fcs_ctx {
     DevBuf g_eta_lo, g_eta_hi, g_inv_deta, g_inv_dphi, g_phi_lo, g_neta, g_nphi, g_offset,
         g_inv_r, g_cell_id;
     DevBuf g_layers, g_regions;  // lookup records staged in LDS by the hit kernels
+    DevBuf g_windows;            // cell windows of the window pass (fcsk::WinRec)
+    int n_windows = 0;
 
     // parametrization
     bool has_param = false;
@@ -108,6 +115,14 @@ struct fcs_ctx {
     int prof_head = 0, prof_count = 0;
     double async_kernel_ms = 0.0;
     std::map<GraphKey, hipGraphExec_t> graphs;
+    // asynchronous calls with pinned host outputs: the batch compacts into
+    // one of two device staging sets (used in turn) and a copy kernel on
+    // copy_stream writes the lists to the host while the next batch runs
+    hipStream_t copy_stream = nullptr;
+    DevBuf hs_ids[2], hs_e[2], hs_off[2];
+    hipEvent_t ev_staged[2] = {}, ev_copied[2] = {};
+    bool copy_pending[2] = {};
+    int hs_next = 0;
     // the work queue in the workspace: the device inputs and options it was
     // built from and its parameter block; an adjoint call with
     // reuse_forward_queue and the same inputs skips the setup and the scans.
@@ -231,6 +246,18 @@ void drop_graphs(fcs_ctx* c)
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
 
+// pinned host memory that the device can write through its mapping
+bool pinned_host(const void* p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeHost && a.devicePointer != nullptr;
+}
+
 // ------------------------------------------ no-allocation scratch array ---
 // fcs_simulate_events_noalloc keeps every device buffer of a call other than
 // its inputs, outputs and the loaded tables (parameter block, counters,
@@ -327,6 +354,11 @@ int fcs_create(fcs_ctx** out, int device)
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_staged[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_staged[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_copied[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_copied[1], hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void**)&c->h_ring, kRing * kBlockBytes) != hipSuccess) {
         fcs_destroy(c);
         return fail(nullptr, FCS_E_HIP, "stream/event/pinned allocation failed");
@@ -348,7 +380,7 @@ int fcs_create(fcs_ctx** out, int device)
         return fail(nullptr, FCS_E_HIP, "hipGetSymbolAddress of the scratch array failed");
     }
     if (ensure(c, c->w_params, kBlockBytes) ||
-        ensure(c, c->w_queue, 2 * fcsk::kQueues * fcsk::kQueueStride * sizeof(int32_t)) ||
+        ensure(c, c->w_queue, fcsk::kQueueInts * sizeof(int32_t)) ||
         ensure(c, c->w_async, sizeof(fcsk::AsyncAcc)) ||
         hipMemset(c->w_async.p, 0, sizeof(fcsk::AsyncAcc)) != hipSuccess) {
         fcs_destroy(c);
@@ -367,6 +399,7 @@ void fcs_destroy(fcs_ctx* c)
     }
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
     drop_graphs(c);
     c->q_valid = false;
     DevBuf* bufs[] = {&c->g_eta_lo, &c->g_eta_hi, &c->g_inv_deta, &c->g_inv_dphi, &c->g_phi_lo,
@@ -376,10 +409,12 @@ void fcs_destroy(fcs_ctx* c)
                       &c->w_task_ehit, &c->w_part_ev, &c->w_part_p, &c->w_part_set,
                       &c->w_blk_sums, &c->w_blk_offs, &c->w_grp, &c->w_task_hoff, &c->w_chunks,
                       &c->w_small_rec, &c->w_tile_first, &c->w_cells, &c->g_layers, &c->g_regions,
+                      &c->g_windows,
                       &c->w_flags, &c->w_seg_off, &c->w_seg_blk, &c->w_blk_list, &c->w_queue,
                       &c->w_params, &c->w_acc_el, &c->w_acc_bins, &c->w_hist_mark, &c->o_cells, &c->o_ids,
                       &c->o_e, &c->o_evoff, &c->o_heta, &c->o_hphi, &c->o_he, &c->o_hcell,
-                      &c->o_thoff, &c->o_counts, &c->o_elayer, &c->w_async};
+                      &c->o_thoff, &c->o_counts, &c->o_elayer, &c->w_async, &c->hs_ids[0],
+                      &c->hs_ids[1], &c->hs_e[0], &c->hs_e[1], &c->hs_off[0], &c->hs_off[1]};
     for (DevBuf* b : bufs) release(c, *b);
     if (c->h_ring) (void)hipHostFree(c->h_ring);
     for (int i = 0; i < kRing; ++i)
@@ -388,6 +423,11 @@ void fcs_destroy(fcs_ctx* c)
         for (int k = 0; k < 2; ++k)
             if (c->prof_ev[i][k]) (void)hipEventDestroy(c->prof_ev[i][k]);
     if (c->ev_done) (void)hipEventDestroy(c->ev_done);
+    for (int i = 0; i < 2; ++i) {
+        if (c->ev_staged[i]) (void)hipEventDestroy(c->ev_staged[i]);
+        if (c->ev_copied[i]) (void)hipEventDestroy(c->ev_copied[i]);
+    }
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
@@ -409,6 +449,33 @@ int fcs_get_info(const fcs_ctx* c, fcs_info* info)
     info->n_regions = c->has_geom ? c->n_regions : 0;
     info->n_histograms = c->has_param ? c->n_hist : 0;
     info->device_bytes = c->held;
+    return FCS_OK;
+}
+
+int fcs_host_alloc(fcs_ctx* c, int64_t bytes, void** ptr)
+{
+    if (!c || !ptr) return FCS_E_INVALID_ARG;
+    *ptr = nullptr;
+    if (bytes < 1) return fail(c, FCS_E_INVALID_ARG, "bytes = %lld, must be >= 1", (long long)bytes);
+    if (c->dry) return fail(c, FCS_E_NO_DEVICE, "context has no device");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (hipHostMalloc(ptr, (size_t)bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        *ptr = nullptr;
+        return fail(c, FCS_E_NOMEM, "pinned host allocation of %lld bytes failed", (long long)bytes);
+    }
+    return FCS_OK;
+}
+
+int fcs_host_free(fcs_ctx* c, void* ptr)
+{
+    if (!c) return FCS_E_INVALID_ARG;
+    if (!ptr) return FCS_OK;
+    if (c->dry) return fail(c, FCS_E_NO_DEVICE, "context has no device");
+    HIPCHK(c, hipSetDevice(c->device));
+    // the copy stream may still write into it
+    HIPCHK(c, hipStreamSynchronize(c->copy_stream));
+    HIPCHK(c, hipHostFree(ptr));
     return FCS_OK;
 }
 
@@ -509,6 +576,44 @@ int fcs_load_geometry(fcs_ctx* c, const fcs_geometry* g)
         if ((rc = upload(c, c->g_layers, lay.data(), lay.size())) ||
             (rc = upload(c, c->g_regions, reg.data(), reg.size())))
             return rc;
+    }
+    {
+        // cell windows of the window pass: each layer's cells cut into runs
+        // of at most kWinCells, each with the eta band its cells cover
+        std::vector<int32_t> win;
+        int nw = 0;
+        for (int l = 0; l < L; ++l) {
+            const long long lo = g->reg_offset[l * R];
+            const long long hi = (long long)g->reg_offset[l * R + R - 1] +
+                                 (long long)g->reg_neta[l * R + R - 1] * g->reg_nphi[l * R + R - 1];
+            const int first = nw;
+            const int n_l = (int)((hi - lo + fcsk::kWinCells - 1) / fcsk::kWinCells);
+            for (int k = 0; k < n_l; ++k) {
+                const long long c0 = lo + (long long)k * fcsk::kWinCells;
+                const long long c1 = std::min(hi, c0 + fcsk::kWinCells);
+                double b0 = INFINITY, b1 = -INFINITY;
+                for (int q = 0; q < R; ++q) {
+                    const int r = l * R + q;
+                    const long long o0 = g->reg_offset[r];
+                    const long long o1 = o0 + (long long)g->reg_neta[r] * g->reg_nphi[r];
+                    if (o1 <= c0 || o0 >= c1) continue;
+                    const long long ie0 = (std::max(c0, o0) - o0) / g->reg_nphi[r];
+                    const long long ie1 = (std::min(c1, o1) - 1 - o0) / g->reg_nphi[r];
+                    const double inv = (double)g->reg_inv_deta[r];
+                    b0 = std::min(b0, (double)g->reg_eta_lo[r] + (double)ie0 / inv);
+                    b1 = std::max(b1, (double)g->reg_eta_lo[r] + (double)(ie1 + 1) / inv);
+                }
+                const float f0 = (float)b0, f1 = (float)b1;
+                int32_t b0i, b1i;
+                std::memcpy(&b0i, &f0, 4);
+                std::memcpy(&b1i, &f1, 4);
+                const int32_t rec[8] = {l, (int32_t)c0, (int32_t)c1, first, b0i, b1i, n_l, 0};
+                win.insert(win.end(), rec, rec + 8);
+                ++nw;
+            }
+        }
+        c->n_windows = nw <= kMaxWindows ? nw : 0;  // very fine geometries: no window pass
+        if (c->n_windows && (rc = upload(c, c->g_windows, win.data(), win.size()))) return rc;
     }
     const bool changed = !c->has_geom || c->n_cells != g->n_cells;
     c->n_cells = g->n_cells;
@@ -618,7 +723,7 @@ struct Shape {
 };
 
 struct Tuning {
-    int chunk, big, tile, wg_per_cu;
+    int chunk, big, tile, wg_per_cu, win_parts;
 };
 
 int check_tuning(fcs_ctx* c, const fcs_sim_options* o, Tuning* t)
@@ -627,6 +732,11 @@ int check_tuning(fcs_ctx* c, const fcs_sim_options* o, Tuning* t)
     t->big = o->big_task_hits ? o->big_task_hits : 128;
     t->tile = o->tile_hits ? o->tile_hits : 512;
     t->wg_per_cu = o->wg_per_cu ? o->wg_per_cu : 4;
+    t->win_parts = o->window_particles ? o->window_particles : 1024;
+    if (t->win_parts < 64 || t->win_parts > 65536)
+        return fail(c, FCS_E_INVALID_ARG, "window_particles = %d outside [64, 65536]", t->win_parts);
+    if (o->window_pass < -1 || o->window_pass > 1)
+        return fail(c, FCS_E_INVALID_ARG, "window_pass = %d: use -1, 0 or 1", o->window_pass);
     if (t->chunk < 1 || t->chunk > fcsk::kChunkMax)
         return fail(c, FCS_E_INVALID_ARG, "chunk_hits = %d outside [1, %d]", t->chunk, fcsk::kChunkMax);
     if (t->tile < fcsk::kWave || t->tile > fcsk::kTileMax || t->tile % fcsk::kWave)
@@ -718,7 +828,7 @@ struct Carver {
 int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
             const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
             float* dense_out, const fcs_sim_output* dout, bool want_hits, bool async, Params* P,
-            char* scratch = nullptr)
+            char* scratch = nullptr, bool allow_win = false)
 {
     const int L = c->n_layers;
     const long long N = sh.n_particles;
@@ -754,7 +864,7 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
         // the parameter block first (kernels and uploads address it), then
         // the tickets, then the buffers that must start at zero
         if ((rc = cv.take(c->w_params, kBlockBytes, &p_params)) ||
-            (rc = cv.take(c->w_queue, 2 * fcsk::kQueues * fcsk::kQueueStride * sizeof(int32_t), &p_queue)) ||
+            (rc = cv.take(c->w_queue, fcsk::kQueueInts * sizeof(int32_t), &p_queue)) ||
             (rc = cv.take(c->w_flags, (size_t)E * n_blk, &p_flags)) ||
             (!dense_out && (rc = cv.take(c->w_cells, (size_t)E * c->n_cells * 4, &p_cells))))
             return rc;
@@ -905,6 +1015,13 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     }
     P->hit_base = sh.hit_base;
     P->out_base = sh.out_base;
+    // the window pass (small tasks of many-particle events by cell windows)
+    const bool dense_events = sh.n_particles >= kWinMinParticlesPerEvent * sh.n_events;
+    P->win_path = allow_win && c->n_windows > 0 && !o->placement_fp64 && !o->hit_energy_fluct &&
+                  (o->window_pass == 1 || (o->window_pass == 0 && dense_events)) ? 1 : 0;
+    P->win_parts = tu.win_parts;
+    P->n_windows = c->n_windows;
+    P->geo_windows = (const int4*)c->g_windows.p;
     return FCS_OK;
 }
 
@@ -934,6 +1051,9 @@ void enqueue_batch(fcs_ctx* c, const Params& P, int mode, int grid, int part)
             hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(fcsk::kScanThreads), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
     }
+    if ((part == kAll || part == kHits) && P.win_path)
+        hipLaunchKernelGGL(fcsk::k_windows, dim3(c->n_cu * 2), dim3(fcsk::kWinThreads),
+                           geo_lds_bytes(P) + (size_t)P.n_windows * 32, s, dP);
     if ((part == kAll || part == kHits) && P.placement_f64)
         hipLaunchKernelGGL((fcsk::k_hits<true, false>), dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
     else if ((part == kAll || part == kHits) && P.hit_fluct)
@@ -1017,7 +1137,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         Params* P = (Params*)blk;
         Counters* hc = (Counters*)(blk + kCtrOffset);
         int rc = prepare(c, o, tu, sh, d_particles, d_evoff, d_override, dense_out, dout, want_hits,
-                         async, P, scratch);
+                         async, P, scratch, !per_task);
         if (rc) return rc;
         const int mode = !dense_out ? kPrivate : (P->out_ids ? kDenseCompact : kDenseOnly);
         // asynchronous calls fold their totals into the context's running
@@ -1028,7 +1148,8 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         std::memset(hc, 0, sizeof(Counters));
         HIPCHK(c, hipMemcpyAsync(c->cur_params, blk, kBlockBytes, hipMemcpyHostToDevice, c->stream));
         if ((rc = ring_sent(c))) return rc;
-        GraphKey key{sh.n_particles, sh.n_events, mode, grid, kAll, P->placement_f64 + 2 * P->hit_fluct};
+        GraphKey key{sh.n_particles, sh.n_events, mode, grid, kAll, P->placement_f64 + 2 * P->hit_fluct,
+                     P->win_path};
         hipEvent_t k0 = c->ev_k0, k1 = c->ev_k1;
         if (profile && async) {
             // a free event pair for this call; the oldest pending one is read
@@ -1099,7 +1220,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
         }
         if (async) {
             HIPCHK(c, hipGetLastError());
-            if (keep) {
+            if (keep && !P->win_path) {
                 c->q_key = queue_key(o, tu, d_particles, d_evoff, sh.n_events, sh.n_particles, P->ev_base);
                 c->q_params = *P;
                 c->q_valid = true;
@@ -1125,7 +1246,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             *kernel_ms += ms;
         }
         const int rc2 = counters_error(c, *res);
-        if (rc2 == FCS_OK && keep) {
+        if (rc2 == FCS_OK && keep && !P->win_path) {
             c->q_key = queue_key(o, tu, d_particles, d_evoff, sh.n_events, sh.n_particles, P->ev_base);
             c->q_params = *P;
             c->q_valid = true;
@@ -1300,9 +1421,21 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
     const bool per_event = o->mode != FCS_MODE_BATCHED;  // per event, or per task within events
     const bool per_task = o->mode == FCS_MODE_PER_TASK;
     const bool async = o->async_launch != 0;
-    if (async && (per_event || !o->inputs_on_device || !o->outputs_on_device || o->n_particles <= 0))
+    // an asynchronous call may leave its compacted lists in pinned host
+    // buffers (fcs_host_alloc): they are copied there after the batch by the
+    // DMA engine, cell_capacity entries of each list
+    const bool async_host = async && !o->outputs_on_device;
+    if (async && (per_event || !o->inputs_on_device || o->n_particles <= 0 || (async_host && noalloc)))
         return fail(c, FCS_E_INVALID_ARG,
-                    "async_launch needs batched mode, device inputs and outputs and n_particles");
+                    "async_launch needs batched mode, device inputs and n_particles (and device "
+                    "outputs for fcs_simulate_events_noalloc)");
+    if (async_host && f != FCS_OUT_COMPACT)
+        return fail(c, FCS_E_INVALID_ARG, "async_launch with host outputs takes FCS_OUT_COMPACT alone");
+    if (async_host && !c->dry &&
+        (!pinned_host(out->cell_ids) || !pinned_host(out->cell_e) || !pinned_host(out->event_cell_offsets)))
+        return fail(c, FCS_E_INVALID_ARG,
+                    "async_launch with host outputs needs pinned cell_ids, cell_e and "
+                    "event_cell_offsets (fcs_host_alloc)");
     Inputs in;
     if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, per_event, &in))) return rc;
     char* const scratch = noalloc ? c->scratch : nullptr;
@@ -1313,7 +1446,24 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
 
     // device-side output views (the caller's, or staging for host outputs)
     fcs_sim_output d = *out;
-    const bool host_out = !o->outputs_on_device;
+    const bool host_out = !o->outputs_on_device && !async_host;
+    int hs = -1;  // staging set of an asynchronous call with host outputs
+    if (async_host) {
+        hs = c->hs_next;
+        c->hs_next ^= 1;
+        // the set is free once its last copy to the host has completed
+        if (c->copy_pending[hs]) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_copied[hs], 0));
+        const size_t cap = (size_t)std::max<int64_t>(out->cell_capacity, 1);
+        if (c->hs_ids[hs].bytes < cap * 8 || c->hs_e[hs].bytes < cap * 4 ||
+            c->hs_off[hs].bytes < (size_t)(n_events + 1) * 8)
+            HIPCHK(c, hipStreamSynchronize(c->copy_stream));  // a grown set frees the old one
+        if ((rc = ensure(c, c->hs_ids[hs], cap * 8)) || (rc = ensure(c, c->hs_e[hs], cap * 4)) ||
+            (rc = ensure(c, c->hs_off[hs], (size_t)(n_events + 1) * 8)))
+            return rc;
+        d.cell_ids = (int64_t*)c->hs_ids[hs].p;
+        d.cell_e = (float*)c->hs_e[hs].p;
+        d.event_cell_offsets = (int64_t*)c->hs_off[hs].p;
+    }
     if (host_out) {
         if ((f & FCS_OUT_DENSE) && (rc = ensure(c, c->o_cells, (size_t)n_events * C * 4))) return rc;
         if (f & FCS_OUT_COMPACT) {
@@ -1416,6 +1566,24 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
         if (d.task_hit_offsets)
             HIPCHK(c, hipMemcpyAsync(d.task_hit_offsets + N * L, &hits, 8, hipMemcpyHostToDevice, c->stream));
     }
+    if (async_host) {
+        // the copy of this batch's lists runs on the copy stream, beside the
+        // next batch; the caller's stream waits for it
+        HIPCHK(c, hipEventRecord(c->ev_staged[hs], c->stream));
+        HIPCHK(c, hipStreamWaitEvent(c->copy_stream, c->ev_staged[hs], 0));
+        // DMA copies (no compute units: they run beside the next batch's
+        // kernels) of the offsets and of cell_capacity entries of each list
+        const size_t m = (size_t)std::max<int64_t>(out->cell_capacity, 0);
+        HIPCHK(c, hipMemcpyAsync(out->event_cell_offsets, d.event_cell_offsets, (size_t)(n_events + 1) * 8,
+                                 hipMemcpyDeviceToHost, c->copy_stream));
+        if (m) {
+            HIPCHK(c, hipMemcpyAsync(out->cell_ids, d.cell_ids, m * 8, hipMemcpyDeviceToHost, c->copy_stream));
+            HIPCHK(c, hipMemcpyAsync(out->cell_e, d.cell_e, m * 4, hipMemcpyDeviceToHost, c->copy_stream));
+        }
+        HIPCHK(c, hipEventRecord(c->ev_copied[hs], c->copy_stream));
+        c->copy_pending[hs] = true;
+        if (o->stream) HIPCHK(c, hipStreamWaitEvent((hipStream_t)o->stream, c->ev_copied[hs], 0));
+    }
     if (async) {
         // the caller's stream waits for the results; nothing is known yet
         HIPCHK(c, hipEventRecord(c->ev_done, c->stream));
@@ -1501,6 +1669,7 @@ int fcs_synchronize(fcs_ctx* c, fcs_async_stats* st)
     if (c->dry) return fail(c, FCS_E_NO_DEVICE, "context has no device");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->copy_stream));
     fcsk::AsyncAcc a;
     HIPCHK(c, hipMemcpy(&a, c->w_async.p, sizeof a, hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemset(c->w_async.p, 0, sizeof a));
@@ -1666,7 +1835,7 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
         HIPCHK(c, hipMemcpyAsync(c->w_params.p, blk, sizeof(Params), hipMemcpyHostToDevice, s));
         if ((rc = ring_sent(c))) return rc;
         hipLaunchKernelGGL(fcsk::k_fill_u32, dim3(1), dim3(256), 0, s, (uint32_t*)c->w_queue.p,
-                           (long long)(2 * fcsk::kQueues * fcsk::kQueueStride), 0u);
+                           (long long)fcsk::kQueueInts, 0u);
         if ((rc = launch_adjoint(*P))) return rc;
         if (async) return finish_async();
         HIPCHK(c, hipMemcpyAsync(hc, (char*)c->w_params.p + kCtrOffset, sizeof(Counters),

@@ -39,9 +39,10 @@ _OUT_NAMES = {"dense": FCS_OUT_DENSE, "compact": FCS_OUT_COMPACT, "hits": FCS_OU
               "counts": FCS_OUT_COUNTS, "elayer": FCS_OUT_ELAYER}
 
 # every symbol include/fcs.h declares
-EXPORTS = ("fcs_create", "fcs_destroy", "fcs_last_error", "fcs_get_info", "fcs_load_geometry",
-           "fcs_load_parametrization", "fcs_default_options", "fcs_simulate_events",
-           "fcs_simulate_events_noalloc", "fcs_query_sizes", "fcs_backward", "fcs_synchronize")
+EXPORTS = ("fcs_create", "fcs_destroy", "fcs_last_error", "fcs_get_info", "fcs_host_alloc",
+           "fcs_host_free", "fcs_load_geometry", "fcs_load_parametrization", "fcs_default_options",
+           "fcs_simulate_events", "fcs_simulate_events_noalloc", "fcs_query_sizes", "fcs_backward",
+           "fcs_synchronize")
 
 _vp = C.c_void_p
 
@@ -78,7 +79,8 @@ class FcsSimOptions(C.Structure):
                 ("profile", C.c_int32), ("elayer_override", _vp), ("stream", _vp),
                 ("n_particles", C.c_int64), ("async_launch", C.c_int32),
                 ("reuse_forward_queue", C.c_int32), ("placement_fp64", C.c_int32),
-                ("hit_energy_fluct", C.c_int32)]
+                ("hit_energy_fluct", C.c_int32), ("window_pass", C.c_int32),
+                ("window_particles", C.c_int32)]
 
 
 class FcsSimOutput(C.Structure):
@@ -127,6 +129,8 @@ def lib():
         L.fcs_last_error.argtypes = [_vp]
         L.fcs_last_error.restype = C.c_char_p
         L.fcs_get_info.argtypes = [_vp, C.POINTER(FcsInfo)]
+        L.fcs_host_alloc.argtypes = [_vp, C.c_int64, C.POINTER(_vp)]
+        L.fcs_host_free.argtypes = [_vp, _vp]
         L.fcs_load_geometry.argtypes = [_vp, C.POINTER(FcsGeometry)]
         L.fcs_load_parametrization.argtypes = [_vp, C.POINTER(FcsParam)]
         L.fcs_default_options.argtypes = [C.POINTER(FcsSimOptions)]
@@ -139,7 +143,8 @@ def lib():
         L.fcs_backward.argtypes = [_vp, _vp, _vp, C.c_int64, C.POINTER(FcsSimOptions), _vp, _vp,
                                    _vp]
         L.fcs_synchronize.argtypes = [_vp, C.POINTER(FcsAsyncStats)]
-        for f in ("fcs_get_info", "fcs_load_geometry", "fcs_load_parametrization",
+        for f in ("fcs_get_info", "fcs_host_alloc", "fcs_host_free", "fcs_load_geometry",
+                  "fcs_load_parametrization",
                   "fcs_simulate_events", "fcs_simulate_events_noalloc", "fcs_query_sizes",
                   "fcs_backward", "fcs_synchronize"):
             getattr(L, f).restype = C.c_int
@@ -174,6 +179,7 @@ class Simulator:
         if rc != FCS_OK:
             raise FcsError(rc, self._L.fcs_last_error(None).decode())
         self._h = h
+        self._pinned = []
         self.device = device
         self.n_cells = 0
         self.n_layers = 0
@@ -181,8 +187,22 @@ class Simulator:
 
     def close(self):
         if getattr(self, "_h", None):
+            for p in self._pinned:
+                self._L.fcs_host_free(self._h, p)
+            self._pinned = []
             self._L.fcs_destroy(self._h)
             self._h = None
+
+    def host_empty(self, shape, dtype):
+        """A numpy array in pinned host memory from fcs_host_alloc (freed with
+        the context): the host outputs of asynchronous calls."""
+        dt = np.dtype(dtype)
+        n = int(np.prod(shape)) * dt.itemsize
+        p = _vp()
+        self._check(self._L.fcs_host_alloc(self._h, max(n, 16), C.byref(p)))
+        self._pinned.append(p.value)
+        buf = (C.c_char * max(n, 16)).from_address(p.value)
+        return np.frombuffer(buf, dtype=dt, count=int(np.prod(shape))).reshape(shape)
 
     def __del__(self):
         try:
@@ -281,7 +301,8 @@ class Simulator:
                         tile_hits=0, wg_per_cu=0, use_graph=True, elayer_override=None,
                         cell_capacity=None, hit_capacity=None, n_particles=None, out=None,
                         profile=False, async_launch=False, placement_fp64=False,
-                        hit_energy_fluct=False, noalloc=False):
+                        hit_energy_fluct=False, noalloc=False, window_pass=0,
+                        window_particles=0, host_outputs=False):
         """Run fcs_simulate_events.  Returns a dict of the requested outputs
         (numpy for host inputs, torch CUDA tensors for device inputs) and the
         statistics.  Capacities default to the sizes fcs_query_sizes
@@ -298,7 +319,14 @@ class Simulator:
 
         noalloc: call fcs_simulate_events_noalloc (batched mode, device inputs
         and outputs; pass `out` buffers and capacities so that the binding
-        allocates nothing either)."""
+        allocates nothing either).
+
+        window_pass: 0 automatic, 1 always, -1 never deposit the small tasks
+        by cell windows (see fcs_sim_options); window_particles tunes it.
+
+        host_outputs (device inputs, async_launch, compact output): `out`
+        holds pinned host arrays from host_empty(); the lists are copied
+        there after the batch, beside the next one."""
         p, off, ov, dev, stream, n_events = self._inputs(particles, event_offsets, elayer_override)
         N = (int(p.shape[0]) if dev else len(p)) if n_particles is None else n_particles
         o = self._options(seed, event_index_base, mode, outputs, hit_energy_scale, nhit_cap,
@@ -308,6 +336,10 @@ class Simulator:
         o.profile = 1 if profile else 0
         o.placement_fp64 = 1 if placement_fp64 else 0
         o.hit_energy_fluct = 1 if hit_energy_fluct else 0
+        o.window_pass = int(window_pass)
+        o.window_particles = int(window_particles)
+        if host_outputs:
+            o.outputs_on_device = 0
         L = self.n_layers
         need_sizes = (("compact" in outputs and cell_capacity is None) or
                       ("hits" in outputs and hit_capacity is None))

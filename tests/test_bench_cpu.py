@@ -19,11 +19,18 @@ def test_more_than_one_gpu_is_refused():
 def test_oracle_baseline_threads_cover_the_workload():
     sys.path.insert(0, ROOT)
     import bench
+    import oracle
     w = W.subset_events(W.single_particle_sweep(), 100, 240)
-    rec = bench.oracle_baseline(w, W.make_geometry(), W.make_param(), max_threads=4,
+    geo, par = W.make_geometry(), W.make_param()
+    rec = bench.oracle_baseline(w, geo, par, max_threads=4, one_core_events=30,
                                 budget_one=0.0, budget_all=0.0)
-    # the threads' event ranges sum to the one-thread pass (checked inside)
+    # the threads' event ranges cover the workload: their hits sum to one
+    # pass over the whole of it
+    whole = oracle.simulate(oracle.Geometry(geo), oracle.Param(par), w.particles,
+                            w.event_offsets, w.seed, event_index_base=100)
+    assert rec["hits_per_pass"] == whole["n_hits_total"]
     assert rec["kind"] == "oracle" and rec["unit"] == "hits/s"
     assert rec["cores"] == min(4, len(os.sched_getaffinity(0)))
+    assert rec["nproc"] == len(os.sched_getaffinity(0))
     assert rec["value"] > 0 and rec["one_core"]["value"] > 0 and rec["one_core"]["cores"] == 1
-    assert "event ranges" in rec["sample"]
+    assert "events 0-29" in rec["one_core"]["sample"] and "event ranges" in rec["sample"]

@@ -214,3 +214,57 @@ def test_override_errors_reach_synchronize(sim, torch_cuda):
     assert st["n_calls"] == 1 and st["n_hits"] == base["stats"]["n_hits"]
     assert torch.count_nonzero(r["cells"]).item() == base["stats"]["n_cells_nonzero"]
     assert torch.isfinite(ge).all().item()
+
+
+def test_async_calls_into_pinned_host_buffers(sim, torch_cuda, oracle_lib, geom_full, param_full):
+    """Asynchronous calls that leave their {cell_id, E} lists in pinned host
+    buffers (fcs_host_alloc): several batches back to back (the two device
+    staging sets used in turn, each copied while the next batch runs), each
+    into its own host buffers, all equal to the oracle after the
+    synchronization; the last call's buffers overflow and that is reported."""
+    from paper_2103_14737_amd.fcs import FCS_E_CAPACITY, FCS_E_INVALID_ARG, FcsError
+    torch = torch_cuda
+    geo = W.make_geometry()
+    ws = [W.subset_events(W.hard_scatter(), 5 * k, 4) for k in range(3)] + \
+         [W.subset_events(W.single_particle_sweep(), 100, 200)]
+    bufs, refs = [], []
+    for w in ws:
+        dp, doff = _dev(w, torch)
+        q = sim.query_sizes(dp, doff, w.seed, event_index_base=w.notes["event_index_base"])
+        cap = q["max_cells"]
+        out = {"cell_ids": sim.host_empty((cap,), np.int64),
+               "cell_e": sim.host_empty((cap,), np.float32),
+               "event_cell_offsets": sim.host_empty((w.n_events + 1,), np.int64)}
+        bufs.append((w, dp, doff, out, cap))
+        refs.append(oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
+                                        event_index_base=w.notes["event_index_base"]))
+    for _ in range(2):  # every batch twice: the staging sets alternate
+        for w, dp, doff, out, cap in bufs:
+            for a in out.values():
+                a.fill(-1)
+            sim.simulate_events(dp, doff, w.seed, event_index_base=w.notes["event_index_base"],
+                                outputs=("compact",), out=out, cell_capacity=cap, async_launch=True,
+                                host_outputs=True)
+        st = sim.synchronize()
+        assert st["n_calls"] == len(bufs)
+        for (w, _, _, out, _), ref in zip(bufs, refs):
+            nnz = ref["n_cells_nonzero"]
+            print(f"[async host] {w.name}: {nnz} cells", flush=True)
+            assert np.array_equal(out["event_cell_offsets"], ref["ev_cell_off"])
+            assert np.array_equal(out["cell_ids"][:nnz], geo["cell_id"][ref["cell_idx"]])
+            e = out["cell_e"][:nnz].astype(np.float64)
+            assert np.all(np.abs(e - ref["cell_e"]) <= np.maximum(REL * ref["cell_e"], ABS))
+    # too small a capacity: the copy stops at the capacity, synchronize reports it
+    w, dp, doff, out, cap = bufs[0]
+    sim.simulate_events(dp, doff, w.seed, event_index_base=w.notes["event_index_base"],
+                        outputs=("compact",), out=out, cell_capacity=10, async_launch=True,
+                        host_outputs=True)
+    with pytest.raises(FcsError) as e:
+        sim.synchronize()
+    assert e.value.code == FCS_E_CAPACITY
+    # pageable host arrays are refused
+    plain = {k: np.empty_like(v) for k, v in out.items()}
+    with pytest.raises(FcsError) as e:
+        sim.simulate_events(dp, doff, w.seed, outputs=("compact",), out=plain, cell_capacity=cap,
+                            async_launch=True, host_outputs=True)
+    assert e.value.code == FCS_E_INVALID_ARG and "pinned" in str(e.value)
