@@ -160,6 +160,24 @@ typedef struct {
 
 int fcs_load_parametrization(fcs_ctx *ctx, const fcs_param *param);
 
+/* The same load without waiting for the device (the paper's tables were
+ * loaded synchronously between calls; here a table change overlaps the
+ * batches already running).  The arguments are checked and copied into the
+ * library's pinned staging before the call returns, so the caller's arrays
+ * may be reused at once.  Upload and table build run on the context's
+ * second stream into a second table set, after every call already enqueued
+ * on the context; the next fcs_simulate_events / fcs_query_sizes /
+ * fcs_backward call makes its stream wait for them (the host does not wait)
+ * and uses the new tables, while calls enqueued before keep the old ones
+ * (the upload waits only for the calls that may still read the set it
+ * overwrites: those enqueued before that set was last switched out).
+ * A second asynchronous load first takes the previous one into use; an
+ * fcs_load_parametrization supersedes a load not yet taken into use.  The
+ * call waits on the host only when the previous asynchronous load's copies
+ * are still running or the second set has to grow.  Errors as
+ * fcs_load_parametrization. */
+int fcs_load_parametrization_async(fcs_ctx *ctx, const fcs_param *param);
+
 /* ------------------------------------------------------------------------
  * Simulation
  * ------------------------------------------------------------------------ */
@@ -238,15 +256,17 @@ typedef struct {
                                    FCS_OUT_COMPACT alone into pinned host
                                    buffers from fcs_host_alloc: then the
                                    batch compacts into one of two device
-                                   staging sets used in turn, and the DMA
-                                   engine copies the event offsets and
-                                   cell_capacity entries of each list to
-                                   the host on a second stream while the
-                                   next batch runs: size cell_capacity to
-                                   the expected compacted total, the
-                                   entries past it are not meaningful).
-                                   opt->stream is made to wait for the
-                                   results.  The
+                                   staging sets used in turn, and a second
+                                   stream copies the event offsets and the
+                                   lists to the host beside the next
+                                   batch's hit kernels (see
+                                   host_copy_workgroups): size
+                                   cell_capacity to the expected compacted
+                                   total.  Host lists are complete after
+                                   fcs_synchronize; the copy of a batch is
+                                   enqueued by the next call into the
+                                   context).  opt->stream is made to wait
+                                   for the device results.  The
                                    out->n_* fields are not known and are set
                                    to -1; event_cell_offsets[n_events] holds
                                    the compacted total on the device.
@@ -302,6 +322,19 @@ typedef struct {
                                    as in every other form.                  */
     int32_t window_particles;    /* tuning, 0 = default (1024): particles per
                                    work item of the window pass, 64..65536  */
+    int32_t host_copy_workgroups; /* async_launch with host outputs: how the
+                                   lists reach the host.  n > 0: a copy
+                                   kernel of n workgroups on the second
+                                   stream stores the offsets and the
+                                   entries the batch wrote (at most
+                                   cell_capacity) through the buffers'
+                                   device mapping; each workgroup moves
+                                   about 12 GB/s, and the link's traffic
+                                   slows the kernels beside it, so a batch
+                                   whose compute outlasts its copy wants
+                                   few.  -1: the runtime's hipMemcpyAsync
+                                   of cell_capacity entries.  0 = default
+                                   (4 workgroups).  At most 4096.           */
 } fcs_sim_options;
 
 /* Fill *opt with the defaults: seed 0, batched, compact output, 100 MeV per

@@ -129,3 +129,40 @@ def tune(sim, particles, event_offsets, seed, *, outputs=("compact",), hit_energ
     cache[key] = {"tuning": best, "ms": best_t * 1e3, "n_candidates": len(results)}
     _store(cache_path, cache)
     return dict(best)
+
+
+HOST_COPY_CANDIDATES = (2, 3, 4, 6, 8, 16, 32)
+
+
+def tune_host_copy(sim, particles, event_offsets, seed, host_sets, cell_capacity, *,
+                   hit_energy_scale=100.0, tuning=None, candidates=HOST_COPY_CANDIDATES,
+                   calls=8, reps=3):
+    """Workgroups of the copy kernel that writes the lists of asynchronous
+    calls to pinned host buffers (`host_sets`: two dicts of host_empty
+    arrays): each candidate is timed over `calls` back-to-back calls, `reps`
+    times, and the fastest median wins.  A batch whose compute outlasts its
+    copy wants few (the link's traffic slows the kernels beside it); one
+    whose copy dominates wants the link's full rate."""
+    import numpy as np
+    tuning = dict(tuning or {})
+
+    def run(wgs, n):
+        for i in range(n):
+            sim.simulate_events(particles, event_offsets, seed, outputs=("compact",),
+                                out=host_sets[i % 2], cell_capacity=cell_capacity,
+                                hit_energy_scale=hit_energy_scale, async_launch=True,
+                                host_outputs=True, host_copy_workgroups=wgs, **tuning)
+        sim.synchronize()
+
+    best, best_t = None, None
+    for wgs in candidates:
+        run(wgs, 2)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            run(wgs, calls)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        if best_t is None or t < best_t:
+            best, best_t = wgs, t
+    return best

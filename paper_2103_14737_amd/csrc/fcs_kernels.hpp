@@ -380,6 +380,40 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, long long n, uint32_t v)
         p[i] = v;
 }
 
+// Copy of an asynchronous call's compacted lists to pinned host memory by a
+// few workgroups of the copy stream: the event offsets, then of each list
+// the entries the batch wrote (the total in offsets[n_events], at most
+// `cap`).  The stores cross the host link; with few waves in flight the
+// kernels beside them keep the rest of the chip.  16-byte moves where the
+// source and destination are both 16-byte aligned, element moves otherwise.
+template <typename T>
+__device__ void copy_to_host(const T* __restrict__ src, T* __restrict__ dst, long long n, long long gid,
+                             long long stride)
+{
+    constexpr long long kPer = 16 / sizeof(T);
+    if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0) {
+        const long long nv = n / kPer;
+        const v4i* s4 = reinterpret_cast<const v4i*>(src);
+        v4i* d4 = reinterpret_cast<v4i*>(dst);
+        for (long long i = gid; i < nv; i += stride) __builtin_nontemporal_store(s4[i], d4 + i);
+        for (long long i = nv * kPer + gid; i < n; i += stride) dst[i] = src[i];
+    } else {
+        for (long long i = gid; i < n; i += stride) dst[i] = src[i];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_out(const int64_t* __restrict__ ids, const float* __restrict__ e,
+                                                     const int64_t* __restrict__ off, int64_t* h_ids, float* h_e,
+                                                     int64_t* h_off, long long n_events, long long cap)
+{
+    const long long gid = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long stride = (long long)gridDim.x * kBlock;
+    const long long m = min(max(off[n_events], 0LL), cap);
+    copy_to_host(off, h_off, n_events + 1, gid, stride);
+    copy_to_host(ids, h_ids, m, gid, stride);
+    copy_to_host(e, h_e, m, gid, stride);
+}
+
 __global__ void k_fill_u8(uint8_t* __restrict__ p, long long n)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -401,42 +435,60 @@ __global__ void k_fill_dense(const Params* __restrict__ Pp)
 
 // ---------------------------------------------- parametrization tables ---
 // cumulative FP32 table per histogram: FP64 running sum over the FP64 total,
-// last entry forced to 1
-__global__ void k_build_cum(const float* __restrict__ w, float* __restrict__ cum, long long n_hist)
+// last entry forced to 1.  A workgroup of 64 threads takes 64 histograms:
+// their weights are loaded into LDS with coalesced reads (rows padded to 257
+// words, so that the threads' row walks fall into distinct banks), each
+// thread sums its own histogram left to right, and the tables are stored
+// back coalesced.
+constexpr int kCumHist = 64;
+constexpr int kCumPad = kBins + 1;
+__global__ __launch_bounds__(kCumHist) void k_build_cum(const float* __restrict__ w, float* __restrict__ cum,
+                                                        long long n_hist)
 {
-    const long long h = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= n_hist) return;
-    const float* wh = w + h * kBins;
-    double tot = 0.0;
-    for (int b = 0; b < kBins; ++b) tot = tot + (double)wh[b];
-    double acc = 0.0;
-    for (int b = 0; b < kBins; ++b) {
-        acc = acc + (double)wh[b];
-        cum[h * kBins + b] = (float)(acc / tot);
+    __shared__ float s_w[kCumHist * kCumPad];
+    const long long h0 = (long long)blockIdx.x * kCumHist;
+    const int nh = (int)min((long long)kCumHist, n_hist - h0);
+    for (int i = threadIdx.x; i < nh * kBins; i += kCumHist)
+        s_w[(i / kBins) * kCumPad + (i % kBins)] = w[h0 * kBins + i];
+    __syncthreads();
+    if ((int)threadIdx.x < nh) {
+        float* row = s_w + threadIdx.x * kCumPad;
+        double tot = 0.0;
+        for (int b = 0; b < kBins; ++b) tot = tot + (double)row[b];
+        double acc = 0.0;
+        for (int b = 0; b < kBins; ++b) {
+            acc = acc + (double)row[b];
+            row[b] = (float)(acc / tot);
+        }
+        row[kBins - 1] = 1.0f;
     }
-    cum[h * kBins + kBins - 1] = 1.0f;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nh * kBins; i += kCumHist)
+        cum[h0 * kBins + i] = s_w[(i / kBins) * kCumPad + (i % kBins)];
 }
 
-// guide table: g[j] = first bin with cum > j/256, so a draw u with
-// floor(256 u) = j lies in bins [g[j], g[j+1]] (g[256] := 255)
-// g[j] = first bin with cum > j / kGuide: a u0 in [j, j+1) / kGuide has its
-// bin in [g[j], g[j+1]] (the last entry's upper end is the last bin)
-__global__ void k_build_guide(const float* __restrict__ cum, uint8_t* __restrict__ guide,
-                              long long n_hist)
+// guide table: g[j] = first bin with cum > j / kGuide, so that a u0 in
+// [j, j+1) / kGuide has its bin in [g[j], g[j+1]] (the last entry's upper
+// end is the last bin).  j / kGuide is exact in FP32 and cum is
+// nondecreasing with cum[last] = 1, so bin b is g[j] exactly for
+// ceil(kGuide cum[b-1]) <= j < ceil(kGuide cum[b]) (cum[-1] = 0): one wave
+// per histogram, four bins per lane, each writing its run of entries.
+__global__ __launch_bounds__(kBlock) void k_build_guide(const float* __restrict__ cum,
+                                                        uint8_t* __restrict__ guide, long long n_hist)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_hist * kGuide) return;
-    const long long h = i / kGuide;
-    const int j = (int)(i - h * kGuide);
-    const float thr = (float)j * (1.0f / kGuide);
+    const long long h = (long long)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (h >= n_hist) return;
+    const int lane = lane_id();
     const float* c = cum + h * kBins;
-    int lo = 0, hi = kBins - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (c[mid] > thr) hi = mid;
-        else lo = mid + 1;
+    uint8_t* g = guide + h * kGuide;
+#pragma unroll
+    for (int k = 0; k < kBins / kWave; ++k) {
+        const int b = lane * (kBins / kWave) + k;
+        const float lo = b ? c[b - 1] : 0.0f;
+        const int j0 = (int)ceilf(lo * (float)kGuide);
+        const int j1 = min((int)ceilf(c[b] * (float)kGuide), kGuide);
+        for (int j = j0; j < j1; ++j) g[j] = (uint8_t)b;
     }
-    guide[i] = (uint8_t)lo;
 }
 
 // Input checks of device-resident inputs, made by the setup kernels: each

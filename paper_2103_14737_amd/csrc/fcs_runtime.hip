@@ -55,7 +55,8 @@ constexpr int kMaxWindows = 256;  // cell windows of the window pass per geometr
 // event on average (hard-scatter and pile-up events; single-particle events
 // keep the packed tiles)
 constexpr long long kWinMinParticlesPerEvent = 64;
-constexpr int kProfRing = 64;  // event pairs of profiled asynchronous calls
+constexpr int kProfRing = 64;     // event pairs of profiled asynchronous calls
+constexpr int kHostCopyWgs = 4;   // workgroups of the copy kernel to host buffers (~50 GB/s)
 
 struct fcs_ctx {
     int device = 0;
@@ -79,12 +80,25 @@ struct fcs_ctx {
     DevBuf g_windows;            // cell windows of the window pass (fcsk::WinRec)
     int n_windows = 0;
 
-    // parametrization
+    // parametrization (the tables calls use)
     bool has_param = false;
     int n_types = 0, n_ebins = 0, n_etabins = 0;
     float r_max = 0.f;
     long long n_hist = 0;
     DevBuf p_e_edges, p_eta_edges, p_alpha, p_weights, p_cum, p_guide;
+    // a second table set filled by fcs_load_parametrization_async on the copy
+    // stream; the next call switches to it (its stream waits for ev_loaded)
+    bool pending = false;
+    int s_types = 0, s_ebins = 0, s_etabins = 0;
+    float s_rmax = 0.f;
+    long long s_hist = 0;
+    DevBuf s_e_edges, s_eta_edges, s_alpha, s_weights, s_cum, s_guide;
+    char* h_tab = nullptr;  // pinned host staging of the tables being loaded
+    size_t h_tab_bytes = 0;
+    // ev_spare_free: recorded when a set becomes the spare, after every call
+    // that may read it
+    hipEvent_t ev_loaded = nullptr, ev_spare_free = nullptr;
+    bool load_in_flight = false;
 
     // workspace
     DevBuf w_particles, w_evoff, w_override, w_task_n, w_task_ehit, w_part_ev, w_part_p,
@@ -123,6 +137,17 @@ struct fcs_ctx {
     hipEvent_t ev_staged[2] = {}, ev_copied[2] = {};
     bool copy_pending[2] = {};
     int hs_next = 0;
+    // the copy of the last such call, not yet enqueued: it waits for the
+    // next call's setup pass (ev_pre), so that it runs beside that call's
+    // hit kernels; every other entry point enqueues it first
+    struct HostCopy {
+        int hs, wgs;
+        int64_t *h_ids, *h_off;
+        float* h_e;
+        long long n_events, m;
+    } dc{};
+    bool copy_deferred = false;
+    hipEvent_t ev_pre = nullptr;
     // the work queue in the workspace: the device inputs and options it was
     // built from and its parameter block; an adjoint call with
     // reuse_forward_queue and the same inputs skips the setup and the scans.
@@ -246,6 +271,44 @@ void drop_graphs(fcs_ctx* c)
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
 
+// Enqueue the copy of an asynchronous call's compacted lists (staging set
+// dc.hs) to its pinned host buffers on the copy stream, after `after`.
+int enqueue_host_copy(fcs_ctx* c, const fcs_ctx::HostCopy& dc, hipEvent_t after)
+{
+    const int hs = dc.hs;
+    HIPCHK(c, hipStreamWaitEvent(c->copy_stream, after, 0));
+    const int64_t* d_ids = (const int64_t*)c->hs_ids[hs].p;
+    const float* d_e = (const float*)c->hs_e[hs].p;
+    const int64_t* d_off = (const int64_t*)c->hs_off[hs].p;
+    if (dc.wgs > 0) {
+        // a copy kernel of a few workgroups stores what the batch wrote
+        // through the buffers' device mapping
+        hipLaunchKernelGGL(fcsk::k_copy_out, dim3(dc.wgs), dim3(fcsk::kBlock), 0, c->copy_stream, d_ids, d_e,
+                           d_off, dc.h_ids, dc.h_e, dc.h_off, dc.n_events, dc.m);
+        HIPCHK(c, hipGetLastError());
+    } else {
+        // the runtime's copies of the offsets and of m entries of each list
+        HIPCHK(c, hipMemcpyAsync(dc.h_off, d_off, (size_t)(dc.n_events + 1) * 8, hipMemcpyDeviceToHost,
+                                 c->copy_stream));
+        if (dc.m) {
+            HIPCHK(c, hipMemcpyAsync(dc.h_ids, d_ids, (size_t)dc.m * 8, hipMemcpyDeviceToHost, c->copy_stream));
+            HIPCHK(c, hipMemcpyAsync(dc.h_e, d_e, (size_t)dc.m * 4, hipMemcpyDeviceToHost, c->copy_stream));
+        }
+    }
+    HIPCHK(c, hipEventRecord(c->ev_copied[hs], c->copy_stream));
+    c->copy_pending[hs] = true;
+    return FCS_OK;
+}
+
+// Enqueue a deferred copy: after `after` (recorded on the context's stream
+// after the next batch's setup pass), else after the batch that staged it.
+int flush_host_copy(fcs_ctx* c, hipEvent_t after = nullptr)
+{
+    if (!c->copy_deferred) return FCS_OK;
+    c->copy_deferred = false;
+    return enqueue_host_copy(c, c->dc, after ? after : c->ev_staged[c->dc.hs]);
+}
+
 // pinned host memory that the device can write through its mapping
 bool pinned_host(const void* p)
 {
@@ -355,10 +418,13 @@ int fcs_create(fcs_ctx** out, int device)
         hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_loaded, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_spare_free, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_staged[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_staged[1], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_copied[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_copied[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_pre, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void**)&c->h_ring, kRing * kBlockBytes) != hipSuccess) {
         fcs_destroy(c);
         return fail(nullptr, FCS_E_HIP, "stream/event/pinned allocation failed");
@@ -398,6 +464,7 @@ void fcs_destroy(fcs_ctx* c)
         return;
     }
     (void)hipSetDevice(c->device);
+    if (c->copy_stream) (void)flush_host_copy(c);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
     drop_graphs(c);
@@ -414,9 +481,14 @@ void fcs_destroy(fcs_ctx* c)
                       &c->w_params, &c->w_acc_el, &c->w_acc_bins, &c->w_hist_mark, &c->o_cells, &c->o_ids,
                       &c->o_e, &c->o_evoff, &c->o_heta, &c->o_hphi, &c->o_he, &c->o_hcell,
                       &c->o_thoff, &c->o_counts, &c->o_elayer, &c->w_async, &c->hs_ids[0],
-                      &c->hs_ids[1], &c->hs_e[0], &c->hs_e[1], &c->hs_off[0], &c->hs_off[1]};
+                      &c->hs_ids[1], &c->hs_e[0], &c->hs_e[1], &c->hs_off[0], &c->hs_off[1],
+                      &c->s_e_edges, &c->s_eta_edges, &c->s_alpha, &c->s_weights, &c->s_cum,
+                      &c->s_guide};
     for (DevBuf* b : bufs) release(c, *b);
     if (c->h_ring) (void)hipHostFree(c->h_ring);
+    if (c->h_tab) (void)hipHostFree(c->h_tab);
+    if (c->ev_loaded) (void)hipEventDestroy(c->ev_loaded);
+    if (c->ev_spare_free) (void)hipEventDestroy(c->ev_spare_free);
     for (int i = 0; i < kRing; ++i)
         if (c->ring_ev[i]) (void)hipEventDestroy(c->ring_ev[i]);
     for (int i = 0; i < kProfRing; ++i)
@@ -427,6 +499,7 @@ void fcs_destroy(fcs_ctx* c)
         if (c->ev_staged[i]) (void)hipEventDestroy(c->ev_staged[i]);
         if (c->ev_copied[i]) (void)hipEventDestroy(c->ev_copied[i]);
     }
+    if (c->ev_pre) (void)hipEventDestroy(c->ev_pre);
     if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
@@ -474,6 +547,8 @@ int fcs_host_free(fcs_ctx* c, void* ptr)
     if (c->dry) return fail(c, FCS_E_NO_DEVICE, "context has no device");
     HIPCHK(c, hipSetDevice(c->device));
     // the copy stream may still write into it
+    int rc = flush_host_copy(c);
+    if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->copy_stream));
     HIPCHK(c, hipHostFree(ptr));
     return FCS_OK;
@@ -533,6 +608,7 @@ int fcs_load_geometry(fcs_ctx* c, const fcs_geometry* g)
         return FCS_OK;
     }
     HIPCHK(c, hipSetDevice(c->device));
+    if (int rcf = flush_host_copy(c)) return rcf;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const size_t nr = (size_t)L * R;
     int rc = 0;
@@ -633,13 +709,19 @@ int fcs_load_geometry(fcs_ctx* c, const fcs_geometry* g)
         c->flag_events = 0;
     }
     if (c->has_param && c->n_layers != L) c->has_param = false;
+    // tables loading asynchronously for another layer count are not used
+    if (c->pending && c->s_hist != 3LL * c->s_ebins * c->s_etabins * L) c->pending = false;
     return FCS_OK;
 }
 
 // ------------------------------------------------------ parametrization ---
-int fcs_load_parametrization(fcs_ctx* c, const fcs_param* p)
+}  // extern "C"
+
+namespace {
+
+// host-side checks of a parametrization; *n_hist receives its histogram count
+int check_param(fcs_ctx* c, const fcs_param* p, long long* n_hist_out)
 {
-    if (!c) return FCS_E_INVALID_ARG;
     if (!p) return fail(c, FCS_E_INVALID_ARG, "param is NULL");
     if (!c->has_geom) return fail(c, FCS_E_NOT_LOADED, "load the geometry first");
     if (p->n_types != 3) return fail(c, FCS_E_INVALID_ARG, "n_types = %d, must be 3", p->n_types);
@@ -663,18 +745,67 @@ int fcs_load_parametrization(fcs_ctx* c, const fcs_param* p)
     for (int i = 0; i < 3 * L; ++i)
         if (!finite_pos(p->dirichlet_alpha[i]))
             return fail(c, FCS_E_INVALID_ARG, "dirichlet_alpha[%d] not finite and positive", i);
-    const long long n_sets = 3LL * p->n_ebins * p->n_etabins;
-    const long long n_hist = n_sets * L;
+    const long long n_hist = 3LL * p->n_ebins * p->n_etabins * L;
+    // weights finite and >= 0, and at least one positive per histogram (then
+    // its FP64 total is positive); branch-free per histogram so that the
+    // loop vectorizes (tables at full-sample volume hold ~10^8 weights)
     for (long long h = 0; h < n_hist; ++h) {
-        double tot = 0.0;
+        const float* wh = p->weights + h * 256;
+        int bad = 0, pos = 0;
         for (int b = 0; b < 256; ++b) {
-            const float w = p->weights[h * 256 + b];
-            if (!(w >= 0.f) || !std::isfinite(w))
-                return fail(c, FCS_E_INVALID_ARG, "weights[%lld] negative or not finite", h * 256 + b);
-            tot += w;
+            const float w = wh[b];
+            bad |= !(w >= 0.f && w <= FLT_MAX);
+            pos |= w > 0.f;
         }
-        if (!(tot > 0.0)) return fail(c, FCS_E_INVALID_ARG, "histogram %lld has no weight", h);
+        if (bad) {
+            int b = 0;
+            while (wh[b] >= 0.f && wh[b] <= FLT_MAX) ++b;
+            return fail(c, FCS_E_INVALID_ARG, "weights[%lld] negative or not finite", h * 256 + b);
+        }
+        if (!pos) return fail(c, FCS_E_INVALID_ARG, "histogram %lld has no weight", h);
     }
+    *n_hist_out = n_hist;
+    return FCS_OK;
+}
+
+// Switch to the tables of a finished-or-running asynchronous load: the
+// context's stream waits for it (no host wait), the second set becomes the
+// one calls use, the former one is the spare.  Called by every call that
+// enqueues work reading the tables.
+int activate_tables(fcs_ctx* c)
+{
+    if (!c->pending) return FCS_OK;
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_loaded, 0));
+    std::swap(c->p_e_edges, c->s_e_edges);
+    std::swap(c->p_eta_edges, c->s_eta_edges);
+    std::swap(c->p_alpha, c->s_alpha);
+    std::swap(c->p_weights, c->s_weights);
+    std::swap(c->p_cum, c->s_cum);
+    std::swap(c->p_guide, c->s_guide);
+    std::swap(c->n_types, c->s_types);
+    std::swap(c->n_ebins, c->s_ebins);
+    std::swap(c->n_etabins, c->s_etabins);
+    std::swap(c->r_max, c->s_rmax);
+    std::swap(c->n_hist, c->s_hist);
+    c->pending = false;
+    c->has_param = true;
+    c->q_valid = false;  // a kept work queue refers to the former tables
+    // the former set is the spare now; the calls enqueued so far may read it
+    HIPCHK(c, hipEventRecord(c->ev_spare_free, c->stream));
+    return FCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fcs_load_parametrization(fcs_ctx* c, const fcs_param* p)
+{
+    if (!c) return FCS_E_INVALID_ARG;
+    long long n_hist = 0;
+    int rc = check_param(c, p, &n_hist);
+    if (rc) return rc;
+    const int L = p->n_layers;
     if (c->dry) {
         c->n_types = p->n_types;
         c->n_ebins = p->n_ebins;
@@ -685,11 +816,15 @@ int fcs_load_parametrization(fcs_ctx* c, const fcs_param* p)
         return FCS_OK;
     }
     HIPCHK(c, hipSetDevice(c->device));
+    if (int rcf = flush_host_copy(c)) return rcf;
+    // this load supersedes an asynchronous one not yet taken into use
+    if (c->load_in_flight) HIPCHK(c, hipEventSynchronize(c->ev_loaded));
+    c->pending = false;
+    c->load_in_flight = false;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     // a kept work queue refers to the old tables (their pointers and
     // histogram count): an adjoint may not reuse it after a reload
     c->q_valid = false;
-    int rc = 0;
     if ((rc = upload(c, c->p_e_edges, p->e_edges, (size_t)p->n_ebins + 1)) ||
         (rc = upload(c, c->p_eta_edges, p->eta_edges, (size_t)p->n_etabins + 1)) ||
         (rc = upload(c, c->p_alpha, p->dirichlet_alpha, (size_t)3 * L)) ||
@@ -697,9 +832,9 @@ int fcs_load_parametrization(fcs_ctx* c, const fcs_param* p)
         (rc = ensure(c, c->p_cum, (size_t)n_hist * 256 * sizeof(float))) ||
         (rc = ensure(c, c->p_guide, (size_t)n_hist * fcsk::kGuide)))
         return rc;
-    hipLaunchKernelGGL(fcsk::k_build_cum, dim3(grid_for(n_hist, 64)), dim3(64), 0, c->stream,
+    hipLaunchKernelGGL(fcsk::k_build_cum, dim3(grid_for(n_hist, fcsk::kCumHist)), dim3(fcsk::kCumHist), 0, c->stream,
                        (const float*)c->p_weights.p, (float*)c->p_cum.p, n_hist);
-    hipLaunchKernelGGL(fcsk::k_build_guide, dim3(grid_for(n_hist * fcsk::kGuide, 256)), dim3(256), 0,
+    hipLaunchKernelGGL(fcsk::k_build_guide, dim3(grid_for(n_hist, fcsk::kBlock / fcsk::kWave)), dim3(fcsk::kBlock), 0,
                        c->stream, (const float*)c->p_cum.p, (uint8_t*)c->p_guide.p, n_hist);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -709,6 +844,74 @@ int fcs_load_parametrization(fcs_ctx* c, const fcs_param* p)
     c->r_max = p->r_max_mm;
     c->n_hist = n_hist;
     c->has_param = true;
+    return FCS_OK;
+}
+
+int fcs_load_parametrization_async(fcs_ctx* c, const fcs_param* p)
+{
+    if (!c) return FCS_E_INVALID_ARG;
+    long long n_hist = 0;
+    int rc = check_param(c, p, &n_hist);
+    if (rc) return rc;
+    if (c->dry) return fcs_load_parametrization(c, p);
+    const int L = p->n_layers;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (int rcf = flush_host_copy(c)) return rcf;
+    // a load not yet taken into use is taken into use now: this one goes to
+    // the set it replaces
+    if ((rc = activate_tables(c))) return rc;
+    // the spare set may still be read by the calls enqueued before it was
+    // retired (ev_spare_free), and the pinned staging by the previous load's
+    // copies
+    if (c->load_in_flight) HIPCHK(c, hipEventSynchronize(c->ev_loaded));
+    const size_t b_e = (size_t)(p->n_ebins + 1) * 4, b_h = (size_t)(p->n_etabins + 1) * 4,
+                 b_a = (size_t)3 * L * 4, b_w = (size_t)n_hist * 256 * 4;
+    const size_t o_h = (b_e + 255) & ~(size_t)255, o_a = o_h + ((b_h + 255) & ~(size_t)255),
+                 o_w = o_a + ((b_a + 255) & ~(size_t)255), need = o_w + b_w;
+    if (c->h_tab_bytes < need) {
+        if (c->h_tab) HIPCHK(c, hipHostFree(c->h_tab));
+        c->h_tab = nullptr;
+        c->h_tab_bytes = 0;
+        if (hipHostMalloc((void**)&c->h_tab, need, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->h_tab = nullptr;
+            return fail(c, FCS_E_NOMEM, "pinned staging of %zu bytes failed", need);
+        }
+        c->h_tab_bytes = need;
+    }
+    std::memcpy(c->h_tab, p->e_edges, b_e);
+    std::memcpy(c->h_tab + o_h, p->eta_edges, b_h);
+    std::memcpy(c->h_tab + o_a, p->dirichlet_alpha, b_a);
+    std::memcpy(c->h_tab + o_w, p->weights, b_w);
+    // growing the spare set frees its old buffers: wait for the calls that
+    // may read them
+    const bool grow = c->s_weights.bytes < b_w || c->s_cum.bytes < b_w ||
+                      c->s_guide.bytes < (size_t)n_hist * fcsk::kGuide || c->s_e_edges.bytes < b_e ||
+                      c->s_eta_edges.bytes < b_h || c->s_alpha.bytes < b_a;
+    if (grow) HIPCHK(c, hipEventSynchronize(c->ev_spare_free));
+    if ((rc = ensure(c, c->s_e_edges, b_e)) || (rc = ensure(c, c->s_eta_edges, b_h)) ||
+        (rc = ensure(c, c->s_alpha, b_a)) || (rc = ensure(c, c->s_weights, b_w)) ||
+        (rc = ensure(c, c->s_cum, b_w)) || (rc = ensure(c, c->s_guide, (size_t)n_hist * fcsk::kGuide)))
+        return rc;
+    hipStream_t cs = c->copy_stream;
+    HIPCHK(c, hipStreamWaitEvent(cs, c->ev_spare_free, 0));
+    HIPCHK(c, hipMemcpyAsync(c->s_e_edges.p, c->h_tab, b_e, hipMemcpyHostToDevice, cs));
+    HIPCHK(c, hipMemcpyAsync(c->s_eta_edges.p, c->h_tab + o_h, b_h, hipMemcpyHostToDevice, cs));
+    HIPCHK(c, hipMemcpyAsync(c->s_alpha.p, c->h_tab + o_a, b_a, hipMemcpyHostToDevice, cs));
+    HIPCHK(c, hipMemcpyAsync(c->s_weights.p, c->h_tab + o_w, b_w, hipMemcpyHostToDevice, cs));
+    hipLaunchKernelGGL(fcsk::k_build_cum, dim3(grid_for(n_hist, fcsk::kCumHist)), dim3(fcsk::kCumHist), 0, cs,
+                       (const float*)c->s_weights.p, (float*)c->s_cum.p, n_hist);
+    hipLaunchKernelGGL(fcsk::k_build_guide, dim3(grid_for(n_hist, fcsk::kBlock / fcsk::kWave)), dim3(fcsk::kBlock), 0, cs,
+                       (const float*)c->s_cum.p, (uint8_t*)c->s_guide.p, n_hist);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(c->ev_loaded, cs));
+    c->s_types = p->n_types;
+    c->s_ebins = p->n_ebins;
+    c->s_etabins = p->n_etabins;
+    c->s_rmax = p->r_max_mm;
+    c->s_hist = n_hist;
+    c->pending = true;
+    c->load_in_flight = true;
     return FCS_OK;
 }
 
@@ -737,6 +940,9 @@ int check_tuning(fcs_ctx* c, const fcs_sim_options* o, Tuning* t)
         return fail(c, FCS_E_INVALID_ARG, "window_particles = %d outside [64, 65536]", t->win_parts);
     if (o->window_pass < -1 || o->window_pass > 1)
         return fail(c, FCS_E_INVALID_ARG, "window_pass = %d: use -1, 0 or 1", o->window_pass);
+    if (o->host_copy_workgroups < -1 || o->host_copy_workgroups > 4096)
+        return fail(c, FCS_E_INVALID_ARG, "host_copy_workgroups = %d outside [-1, 4096]",
+                    o->host_copy_workgroups);
     if (t->chunk < 1 || t->chunk > fcsk::kChunkMax)
         return fail(c, FCS_E_INVALID_ARG, "chunk_hits = %d outside [1, %d]", t->chunk, fcsk::kChunkMax);
     if (t->tile < fcsk::kWave || t->tile > fcsk::kTileMax || t->tile % fcsk::kWave)
@@ -1196,16 +1402,23 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             if (profile) HIPCHK(c, hipEventRecord(k1, c->stream));
             enqueue_batch(c, *P, mode, grid, kPost);
             HIPCHK(c, hipGetLastError());
-        } else if (use_graph && !profile) {
+        } else if (use_graph && !profile && !(async && c->copy_deferred)) {
             if ((rc = launch_graph(c, *P, key, mode, grid, kAll))) return rc;
         } else {
-            // profiled: the hit kernel is launched on its own between two event
-            // records (graphs for the parts before and after it)
+            // profiled, or a copy to the host waits for the setup pass: the
+            // hit kernels are launched on their own between the parts before
+            // and after them (graphs)
             if (use_graph) {
                 key.part = kPre;
                 if ((rc = launch_graph(c, *P, key, mode, grid, kPre))) return rc;
             } else {
                 enqueue_batch(c, *P, mode, grid, kPre);
+            }
+            // the previous batch's copy to the host starts beside this one's
+            // window pass (the hit kernel leaves its workgroups no room)
+            if (async && c->copy_deferred) {
+                HIPCHK(c, hipEventRecord(c->ev_pre, c->stream));
+                if ((rc = flush_host_copy(c, c->ev_pre))) return rc;
             }
             if (profile) HIPCHK(c, hipEventRecord(k0, c->stream));
             enqueue_batch(c, *P, mode, grid, kHits);
@@ -1294,6 +1507,11 @@ struct Inputs {
 int stage_inputs(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
                  int64_t n_events, const fcs_sim_options* o, bool need_host_offsets, Inputs* in)
 {
+    if (!c->dry) {
+        HIPCHK(c, hipSetDevice(c->device));
+        int rc = activate_tables(c);  // tables of an asynchronous load, if any
+        if (rc) return rc;
+    }
     if (!c->has_geom || !c->has_param)
         return fail(c, FCS_E_NOT_LOADED, "load the geometry and the parametrization first");
     if (!o) return fail(c, FCS_E_INVALID_ARG, "options are NULL");
@@ -1422,8 +1640,7 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
     const bool per_task = o->mode == FCS_MODE_PER_TASK;
     const bool async = o->async_launch != 0;
     // an asynchronous call may leave its compacted lists in pinned host
-    // buffers (fcs_host_alloc): they are copied there after the batch by the
-    // DMA engine, cell_capacity entries of each list
+    // buffers (fcs_host_alloc): they are copied there beside the next batch
     const bool async_host = async && !o->outputs_on_device;
     if (async && (per_event || !o->inputs_on_device || o->n_particles <= 0 || (async_host && noalloc)))
         return fail(c, FCS_E_INVALID_ARG,
@@ -1436,6 +1653,9 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
         return fail(c, FCS_E_INVALID_ARG,
                     "async_launch with host outputs needs pinned cell_ids, cell_e and "
                     "event_cell_offsets (fcs_host_alloc)");
+    // a deferred copy to the host waits for this call's setup pass only if
+    // this call is one of the same kind
+    if (!c->dry && !async_host && (rc = flush_host_copy(c))) return rc;
     Inputs in;
     if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, per_event, &in))) return rc;
     char* const scratch = noalloc ? c->scratch : nullptr;
@@ -1452,6 +1672,7 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
         hs = c->hs_next;
         c->hs_next ^= 1;
         // the set is free once its last copy to the host has completed
+        if (c->copy_deferred && c->dc.hs == hs && (rc = flush_host_copy(c))) return rc;
         if (c->copy_pending[hs]) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_copied[hs], 0));
         const size_t cap = (size_t)std::max<int64_t>(out->cell_capacity, 1);
         if (c->hs_ids[hs].bytes < cap * 8 || c->hs_e[hs].bytes < cap * 4 ||
@@ -1567,22 +1788,35 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
             HIPCHK(c, hipMemcpyAsync(d.task_hit_offsets + N * L, &hits, 8, hipMemcpyHostToDevice, c->stream));
     }
     if (async_host) {
-        // the copy of this batch's lists runs on the copy stream, beside the
-        // next batch; the caller's stream waits for it
+        // the copy of this batch's lists to the host is enqueued by the next
+        // call, to start after its setup pass: it then runs beside that
+        // batch's window pass and hit kernel.  The setup pass's memory
+        // accesses slow down the most under the host link's traffic, the
+        // hit kernel's arithmetic the least; a copy kernel of a few
+        // workgroups keeps that traffic low.  Any other entry point enqueues
+        // it first.
         HIPCHK(c, hipEventRecord(c->ev_staged[hs], c->stream));
-        HIPCHK(c, hipStreamWaitEvent(c->copy_stream, c->ev_staged[hs], 0));
-        // DMA copies (no compute units: they run beside the next batch's
-        // kernels) of the offsets and of cell_capacity entries of each list
-        const size_t m = (size_t)std::max<int64_t>(out->cell_capacity, 0);
-        HIPCHK(c, hipMemcpyAsync(out->event_cell_offsets, d.event_cell_offsets, (size_t)(n_events + 1) * 8,
-                                 hipMemcpyDeviceToHost, c->copy_stream));
-        if (m) {
-            HIPCHK(c, hipMemcpyAsync(out->cell_ids, d.cell_ids, m * 8, hipMemcpyDeviceToHost, c->copy_stream));
-            HIPCHK(c, hipMemcpyAsync(out->cell_e, d.cell_e, m * 4, hipMemcpyDeviceToHost, c->copy_stream));
+        if ((rc = flush_host_copy(c))) return rc;  // one the run above did not take
+        fcs_ctx::HostCopy dc{};
+        dc.hs = hs;
+        dc.wgs = o->host_copy_workgroups > 0 ? o->host_copy_workgroups
+                                             : (o->host_copy_workgroups == 0 ? kHostCopyWgs : 0);
+        dc.n_events = n_events;
+        dc.m = std::max<int64_t>(out->cell_capacity, 0);
+        dc.h_ids = out->cell_ids;
+        dc.h_e = out->cell_e;
+        dc.h_off = out->event_cell_offsets;
+        if (dc.wgs > 0) {  // the kernel stores through the device mapping
+            void *h_ids = nullptr, *h_e = nullptr, *h_off = nullptr;
+            HIPCHK(c, hipHostGetDevicePointer(&h_ids, out->cell_ids, 0));
+            HIPCHK(c, hipHostGetDevicePointer(&h_e, out->cell_e, 0));
+            HIPCHK(c, hipHostGetDevicePointer(&h_off, out->event_cell_offsets, 0));
+            dc.h_ids = (int64_t*)h_ids;
+            dc.h_e = (float*)h_e;
+            dc.h_off = (int64_t*)h_off;
         }
-        HIPCHK(c, hipEventRecord(c->ev_copied[hs], c->copy_stream));
-        c->copy_pending[hs] = true;
-        if (o->stream) HIPCHK(c, hipStreamWaitEvent((hipStream_t)o->stream, c->ev_copied[hs], 0));
+        c->dc = dc;
+        c->copy_deferred = true;
     }
     if (async) {
         // the caller's stream waits for the results; nothing is known yet
@@ -1668,6 +1902,8 @@ int fcs_synchronize(fcs_ctx* c, fcs_async_stats* st)
     if (st) std::memset(st, 0, sizeof *st);
     if (c->dry) return fail(c, FCS_E_NO_DEVICE, "context has no device");
     HIPCHK(c, hipSetDevice(c->device));
+    int rc0 = flush_host_copy(c);
+    if (rc0) return rc0;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipStreamSynchronize(c->copy_stream));
     fcsk::AsyncAcc a;
@@ -1710,6 +1946,7 @@ int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* ev
     Tuning tu;
     int rc = o ? check_tuning(c, o, &tu) : fail(c, FCS_E_INVALID_ARG, "options are NULL");
     if (rc) return rc;
+    if (!c->dry && (rc = flush_host_copy(c))) return rc;
     Inputs in;
     if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, false, &in))) return rc;
     std::memset(s, 0, sizeof *s);
@@ -1761,6 +1998,7 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
     if (o->placement_fp64)
         return fail(c, FCS_E_INVALID_ARG, "placement_fp64 is a forward-only variant: the adjoint "
                                           "recomputes hits with the FP32 placement");
+    if (!c->dry && (rc = flush_host_copy(c))) return rc;
     Inputs in;
     if ((rc = stage_inputs(c, particles, event_offsets, n_events, o, false, &in))) return rc;
     const long long nt = in.N * c->n_layers;

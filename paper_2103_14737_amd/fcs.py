@@ -40,7 +40,8 @@ _OUT_NAMES = {"dense": FCS_OUT_DENSE, "compact": FCS_OUT_COMPACT, "hits": FCS_OU
 
 # every symbol include/fcs.h declares
 EXPORTS = ("fcs_create", "fcs_destroy", "fcs_last_error", "fcs_get_info", "fcs_host_alloc",
-           "fcs_host_free", "fcs_load_geometry", "fcs_load_parametrization", "fcs_default_options",
+           "fcs_host_free", "fcs_load_geometry", "fcs_load_parametrization",
+           "fcs_load_parametrization_async", "fcs_default_options",
            "fcs_simulate_events", "fcs_simulate_events_noalloc", "fcs_query_sizes", "fcs_backward",
            "fcs_synchronize")
 
@@ -80,7 +81,7 @@ class FcsSimOptions(C.Structure):
                 ("n_particles", C.c_int64), ("async_launch", C.c_int32),
                 ("reuse_forward_queue", C.c_int32), ("placement_fp64", C.c_int32),
                 ("hit_energy_fluct", C.c_int32), ("window_pass", C.c_int32),
-                ("window_particles", C.c_int32)]
+                ("window_particles", C.c_int32), ("host_copy_workgroups", C.c_int32)]
 
 
 class FcsSimOutput(C.Structure):
@@ -133,6 +134,7 @@ def lib():
         L.fcs_host_free.argtypes = [_vp, _vp]
         L.fcs_load_geometry.argtypes = [_vp, C.POINTER(FcsGeometry)]
         L.fcs_load_parametrization.argtypes = [_vp, C.POINTER(FcsParam)]
+        L.fcs_load_parametrization_async.argtypes = [_vp, C.POINTER(FcsParam)]
         L.fcs_default_options.argtypes = [C.POINTER(FcsSimOptions)]
         L.fcs_default_options.restype = None
         L.fcs_simulate_events.argtypes = [_vp, _vp, _vp, C.c_int64, C.POINTER(FcsSimOptions),
@@ -144,7 +146,7 @@ def lib():
                                    _vp]
         L.fcs_synchronize.argtypes = [_vp, C.POINTER(FcsAsyncStats)]
         for f in ("fcs_get_info", "fcs_host_alloc", "fcs_host_free", "fcs_load_geometry",
-                  "fcs_load_parametrization",
+                  "fcs_load_parametrization", "fcs_load_parametrization_async",
                   "fcs_simulate_events", "fcs_simulate_events_noalloc", "fcs_query_sizes",
                   "fcs_backward", "fcs_synchronize"):
             getattr(L, f).restype = C.c_int
@@ -240,13 +242,18 @@ class Simulator:
         self.n_cells = int(g["n_cells"])
         self.n_layers = int(g["n_layers"])
 
-    def load_parametrization(self, p: dict):
+    def load_parametrization(self, p: dict, async_load: bool = False):
+        """fcs_load_parametrization, or with async_load
+        fcs_load_parametrization_async (the next call uses the new tables;
+        calls already enqueued keep the old ones)."""
         arrs = [_host(p["e_edges"], np.float32), _host(p["eta_edges"], np.float32),
                 _host(p["alpha"], np.float32), _host(p["weights"], np.float32)]
         s = FcsParam(int(p["n_types"]), int(p["n_ebins"]), int(p["n_etabins"]),
                      int(p["n_layers"]), int(p["n_rbins"]), int(p["n_abins"]),
                      float(p["r_max_mm"]), *[_ptr(a) for a in arrs])
-        self._check(self._L.fcs_load_parametrization(self._h, C.byref(s)))
+        call = (self._L.fcs_load_parametrization_async if async_load
+                else self._L.fcs_load_parametrization)
+        self._check(call(self._h, C.byref(s)))
         self.n_hist = arrs[3].size // 256
 
     # ------------------------------------------------------------ options
@@ -302,7 +309,7 @@ class Simulator:
                         cell_capacity=None, hit_capacity=None, n_particles=None, out=None,
                         profile=False, async_launch=False, placement_fp64=False,
                         hit_energy_fluct=False, noalloc=False, window_pass=0,
-                        window_particles=0, host_outputs=False):
+                        window_particles=0, host_outputs=False, host_copy_workgroups=0):
         """Run fcs_simulate_events.  Returns a dict of the requested outputs
         (numpy for host inputs, torch CUDA tensors for device inputs) and the
         statistics.  Capacities default to the sizes fcs_query_sizes
@@ -326,7 +333,9 @@ class Simulator:
 
         host_outputs (device inputs, async_launch, compact output): `out`
         holds pinned host arrays from host_empty(); the lists are copied
-        there after the batch, beside the next one."""
+        there after the batch, beside the next one, by a copy kernel of
+        host_copy_workgroups workgroups (0: the default; -1: the runtime's
+        copy of cell_capacity entries)."""
         p, off, ov, dev, stream, n_events = self._inputs(particles, event_offsets, elayer_override)
         N = (int(p.shape[0]) if dev else len(p)) if n_particles is None else n_particles
         o = self._options(seed, event_index_base, mode, outputs, hit_energy_scale, nhit_cap,
@@ -338,6 +347,7 @@ class Simulator:
         o.hit_energy_fluct = 1 if hit_energy_fluct else 0
         o.window_pass = int(window_pass)
         o.window_particles = int(window_particles)
+        o.host_copy_workgroups = int(host_copy_workgroups)
         if host_outputs:
             o.outputs_on_device = 0
         L = self.n_layers

@@ -216,12 +216,16 @@ def test_override_errors_reach_synchronize(sim, torch_cuda):
     assert torch.isfinite(ge).all().item()
 
 
-def test_async_calls_into_pinned_host_buffers(sim, torch_cuda, oracle_lib, geom_full, param_full):
+@pytest.mark.parametrize("wgs", [0, 1, 64, -1])
+def test_async_calls_into_pinned_host_buffers(sim, torch_cuda, oracle_lib, geom_full, param_full,
+                                              wgs):
     """Asynchronous calls that leave their {cell_id, E} lists in pinned host
     buffers (fcs_host_alloc): several batches back to back (the two device
     staging sets used in turn, each copied while the next batch runs), each
     into its own host buffers, all equal to the oracle after the
-    synchronization; the last call's buffers overflow and that is reported."""
+    synchronization; the last call's buffers overflow and that is reported.
+    The copy kernel at the default, one and 64 workgroups, and the
+    runtime's copies (-1)."""
     from paper_2103_14737_amd.fcs import FCS_E_CAPACITY, FCS_E_INVALID_ARG, FcsError
     torch = torch_cuda
     geo = W.make_geometry()
@@ -244,7 +248,7 @@ def test_async_calls_into_pinned_host_buffers(sim, torch_cuda, oracle_lib, geom_
                 a.fill(-1)
             sim.simulate_events(dp, doff, w.seed, event_index_base=w.notes["event_index_base"],
                                 outputs=("compact",), out=out, cell_capacity=cap, async_launch=True,
-                                host_outputs=True)
+                                host_outputs=True, host_copy_workgroups=wgs)
         st = sim.synchronize()
         assert st["n_calls"] == len(bufs)
         for (w, _, _, out, _), ref in zip(bufs, refs):
@@ -258,7 +262,7 @@ def test_async_calls_into_pinned_host_buffers(sim, torch_cuda, oracle_lib, geom_
     w, dp, doff, out, cap = bufs[0]
     sim.simulate_events(dp, doff, w.seed, event_index_base=w.notes["event_index_base"],
                         outputs=("compact",), out=out, cell_capacity=10, async_launch=True,
-                        host_outputs=True)
+                        host_outputs=True, host_copy_workgroups=wgs)
     with pytest.raises(FcsError) as e:
         sim.synchronize()
     assert e.value.code == FCS_E_CAPACITY
@@ -268,3 +272,55 @@ def test_async_calls_into_pinned_host_buffers(sim, torch_cuda, oracle_lib, geom_
         sim.simulate_events(dp, doff, w.seed, outputs=("compact",), out=plain, cell_capacity=cap,
                             async_launch=True, host_outputs=True)
     assert e.value.code == FCS_E_INVALID_ARG and "pinned" in str(e.value)
+
+
+def test_host_copy_flushed_by_other_calls(sim, torch_cuda, oracle_lib, geom_full, param_full):
+    """The copy of an asynchronous call's lists to the host is enqueued by the
+    next call into the context: a synchronous call, a query and an adjoint
+    call in between each take it along, and lists whose host views start
+    8 bytes into a pinned allocation (no 16-byte moves) and a capacity equal
+    to the compacted total arrive whole."""
+    torch = torch_cuda
+    geo = W.make_geometry()
+    w = W.subset_events(W.hard_scatter(), 7, 3)
+    base = w.notes["event_index_base"]
+    dp, doff = _dev(w, torch)
+    ref = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
+                              event_index_base=base)
+    nnz = ref["n_cells_nonzero"]
+    raw = {"cell_ids": sim.host_empty((nnz + 1,), np.int64),
+           "cell_e": sim.host_empty((nnz + 2,), np.float32),
+           "event_cell_offsets": sim.host_empty((w.n_events + 2,), np.int64)}
+    out = {"cell_ids": raw["cell_ids"][1:], "cell_e": raw["cell_e"][2:],
+           "event_cell_offsets": raw["event_cell_offsets"][1:]}
+
+    def check(label):
+        print(f"[host copy] {label}", flush=True)
+        assert np.array_equal(out["event_cell_offsets"], ref["ev_cell_off"]), label
+        assert np.array_equal(out["cell_ids"], geo["cell_id"][ref["cell_idx"]]), label
+        e = out["cell_e"].astype(np.float64)
+        assert np.all(np.abs(e - ref["cell_e"]) <= np.maximum(REL * ref["cell_e"], ABS)), label
+
+    def launch(wgs):
+        for a in raw.values():
+            a.fill(-1)
+        sim.simulate_events(dp, doff, w.seed, event_index_base=base, outputs=("compact",),
+                            out=out, cell_capacity=nnz, async_launch=True, host_outputs=True,
+                            host_copy_workgroups=wgs)
+
+    for wgs in (0, 3, -1):
+        launch(wgs)
+        r = sim.simulate_events(dp, doff, w.seed, event_index_base=base, outputs=("compact",))
+        torch.cuda.synchronize()
+        assert r["stats"]["n_cells_nonzero"] == nnz
+        sim.synchronize()
+        check(f"{wgs} workgroups, then a synchronous call")
+        launch(wgs)
+        sim.query_sizes(dp, doff, w.seed, event_index_base=base)
+        sim.synchronize()
+        check(f"{wgs} workgroups, then a query")
+        launch(wgs)
+        sim.backward(dp, doff, w.seed, torch.zeros(w.n_events, geo["n_cells"], device="cuda"),
+                     event_index_base=base)
+        sim.synchronize()
+        check(f"{wgs} workgroups, then an adjoint call")

@@ -563,6 +563,55 @@ def test_fine_binned_tables(torch_cuda, oracle_lib, geom_full, geo, fine_tables)
         s.close()
 
 
+def _edge_weights(n_hist, seed=7):
+    """Histograms whose cumulative tables sit on the sampler's guide
+    thresholds (multiples of 1/1024) or leave runs of guide entries to a
+    single bin: equal weights (cum = (b + 1) / 256), one nonzero bin, random
+    integer weights summing to 1024 with zero runs, powers of two over 60
+    octaves, and a zero first half."""
+    rng = np.random.default_rng(seed)
+    w = np.zeros((n_hist, 256), np.float32)
+    for h in range(n_hist):
+        k = h % 5
+        if k == 0:
+            w[h] = 4.0
+        elif k == 1:
+            w[h, rng.integers(0, 256)] = 1.0
+        elif k == 2:
+            live = rng.random(256) < 0.3
+            live[rng.integers(0, 256)] = True
+            idx = np.flatnonzero(live)
+            cuts = np.sort(rng.integers(0, 1025, len(idx) - 1))
+            w[h, idx] = np.diff(np.concatenate(([0], cuts, [1024]))).astype(np.float32)
+        elif k == 3:
+            w[h] = np.exp2((np.arange(256) % 61) - 30.0).astype(np.float32)
+        else:
+            w[h, 128:] = rng.random(128).astype(np.float32) + 0.5
+    return w
+
+
+def test_edge_histogram_tables(torch_cuda, oracle_lib, geom_full, geo):
+    """Sampling tables built on the GPU from histograms with exact guide
+    boundaries, empty bins and single-bin mass: every hit's sampled bin, hence
+    its position and cell, against the oracle's plain inverse CDF."""
+    from paper_2103_14737_amd.fcs import Simulator
+    par = W.make_param()
+    n_hist = par["weights"].size // 256
+    par["weights"] = _edge_weights(n_hist).reshape(-1)
+    par_o = oracle_lib.Param(par)
+    s = Simulator(0)
+    try:
+        s.load_geometry(geo)
+        s.load_parametrization(par)
+        for w in (W.subset_events(W.single_particle_sweep(), 0, 40),
+                  W.subset_events(W.hard_scatter(), 0, 1)):
+            base = w.notes.get("event_index_base", 0)
+            r, ref = run_both(s, oracle_lib, geom_full, par_o, geo, w, torch_cuda, base=base)
+            check_parity(r, ref, geo, label=f"{w.name}, edge tables")
+    finally:
+        s.close()
+
+
 # --------------------------------------------------- FP64 placement variant ---
 @pytest.mark.parametrize("case,mode", [("sweep", "batched"), ("hard_scatter", "batched"),
                                        ("sweep", "per_event"), ("hard_scatter", "per_task")])

@@ -147,3 +147,68 @@ def test_override_giving_subnormal_hit_energies_is_rejected(torch_cuda, device_i
         assert run(bad)["stats"]["n_hits"] == int(n.sum())   # normal again: accepted
     finally:
         s.close()
+
+
+def test_tables_loaded_while_batches_run(torch_cuda, oracle_lib):
+    """fcs_load_parametrization_async between asynchronous batches: the
+    batches enqueued before it use the old tables, the ones after it the new
+    ones (other weights of the same shape, then the 64 x 64-bin family),
+    each equal to the oracle on its own tables; a synchronous call after a
+    second asynchronous load takes it into use as well."""
+    from paper_2103_14737_amd.fcs import Simulator, particles_to_device
+    torch = torch_cuda
+    geo = W.make_geometry()
+    par1 = W.make_param()
+    par2 = dict(par1)
+    rng = np.random.default_rng(8)
+    par2["weights"] = (par1["weights"] * rng.uniform(0.1, 3.0, par1["weights"].shape)).astype(np.float32)
+    par3 = W.make_param(n_ebins=64, n_etabins=64)
+    w = W.subset_events(W.single_particle_sweep(), 4000, 300)
+    base = w.notes["event_index_base"]
+    dp = particles_to_device(w.particles)
+    doff = torch.from_numpy(w.event_offsets).cuda()
+    go = oracle_lib.Geometry(geo)
+    s = Simulator(0)
+    try:
+        s.load_geometry(geo)
+        s.load_parametrization(par1)
+        q = s.query_sizes(dp, doff, w.seed, event_index_base=base)
+        cap = q["max_cells"] * 2
+
+        def buffers():
+            return {"cell_ids": torch.empty(cap, dtype=torch.int64, device="cuda"),
+                    "cell_e": torch.empty(cap, dtype=torch.float32, device="cuda"),
+                    "event_cell_offsets": torch.empty(w.n_events + 1, dtype=torch.int64,
+                                                      device="cuda")}
+
+        outs = [buffers() for _ in range(5)]
+
+        def call(i):
+            s.simulate_events(dp, doff, w.seed, event_index_base=base, outputs=("compact",),
+                              out=outs[i], cell_capacity=cap, async_launch=True)
+
+        call(0)
+        call(1)
+        s.load_parametrization(par2, async_load=True)   # while 0 and 1 run
+        call(2)
+        s.load_parametrization(par3, async_load=True)
+        call(3)
+        s.load_parametrization(par1, async_load=True)
+        r4 = s.simulate_events(dp, doff, w.seed, event_index_base=base, outputs=("compact",),
+                               cell_capacity=cap)        # synchronous: takes par1 in again
+        s.synchronize()
+        torch.cuda.synchronize()
+        assert s.info()["n_histograms"] == 11520
+        for i, par in ((0, par1), (1, par1), (2, par2), (3, par3), (4, par1)):
+            ref = oracle_lib.simulate(go, oracle_lib.Param(par), w.particles, w.event_offsets,
+                                      w.seed, event_index_base=base)
+            o = r4 if i == 4 else outs[i]
+            nnz = ref["n_cells_nonzero"]
+            print(f"[async tables] call {i}: {ref['n_hits_total']} hits, {nnz} cells", flush=True)
+            off = _np(o["event_cell_offsets"])
+            assert np.array_equal(off, ref["ev_cell_off"]), i
+            assert np.array_equal(_np(o["cell_ids"][:nnz]), geo["cell_id"][ref["cell_idx"]]), i
+            e = _np(o["cell_e"][:nnz]).astype(np.float64)
+            assert np.all(np.abs(e - ref["cell_e"]) <= np.maximum(REL * ref["cell_e"], ABS)), i
+    finally:
+        s.close()
