@@ -49,7 +49,7 @@ constexpr size_t kBlockBytes = kCtrOffset + ((sizeof(Counters) + 255) & ~(size_t
 
 }  // namespace
 
-constexpr int kRing = 16;      // pinned parameter blocks
+constexpr int kRing = 256;     // pinned parameter blocks: how many calls the host may run ahead
 constexpr int kMaxWindows = 256;  // cell windows of the window pass per geometry (staged in LDS)
 // the window pass is used for launches of at least this many particles per
 // event on average (hard-scatter and pile-up events; single-particle events
