@@ -1576,7 +1576,10 @@ __device__ __forceinline__ bool next_item(const Params& P, WaveQueue& q, int& it
 // once as count * Ehit, one rounding per cell and chunk.  Tile hits that share an
 // (event, cell) with a leading lane are summed across the wave first; each
 // remaining sum goes to the event's cell with one device atomic.
-template <bool kF64, bool kFluct>
+// kTiles: the instantiation that also deposits the packed tiles of small
+// tasks (the window pass takes them otherwise; without that path the chunk
+// loop has the registers to itself)
+template <bool kF64, bool kFluct, bool kTiles = true>
 __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
@@ -1644,28 +1647,26 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
                     continue;
                 }
                 if (P.want_hits) write_hit(P, hbase + i, h, ck.ehit);
-                bool pending = h.cell >= 0;
-                // the lanes in the first pending lane's cell (often the
-                // shower core) are counted with one insert
-                const unsigned long long act = __ballot(pending);
+                // the lanes in the first valid lane's cell (often the shower
+                // core) are counted by that lane's insert, which runs beside
+                // the other lanes' inserts of one hit each
+                const bool valid = h.cell >= 0;
+                const unsigned long long act = __ballot(valid);
                 if (act) {
                     const int leader = __ffsll((long long)act) - 1;
                     const int lk = __builtin_amdgcn_readlane(h.cell, leader);
-                    const bool same = pending && h.cell == lk;
+                    const bool same = valid && h.cell == lk;
                     const unsigned long long sm = __ballot(same);
-                    if (lane == leader)
-                        wave_hash_add(P, hkey, hcnt2, hbits, (uint32_t)lk, (uint32_t)__popcll(sm),
-                                      ck.ev, ck.ehit);
-                    pending = pending && !same;
+                    if (lane == leader || (valid && !same))
+                        wave_hash_add(P, hkey, hcnt2, hbits, (uint32_t)h.cell,
+                                      lane == leader ? (uint32_t)__popcll(sm) : 1u, ck.ev, ck.ehit);
                 }
-                if (pending)
-                    wave_hash_add(P, hkey, hcnt2, hbits, (uint32_t)h.cell, 1u, ck.ev, ck.ehit);
             }
             wave_sync();
             if constexpr (kFluct) wave_hash_flush_e(P, hkey, hsum, hbits, ck.ev);
             else wave_hash_flush(P, hkey, hcnt2, hbits, ck.ev, ck.ehit);
             wave_sync();
-        } else {
+        } else if constexpr (kTiles) {
             // ------------------------------------------ tile of small tasks
             int s0, h0, hcount;
             wave_tile_owners(P, ctr, item - n_chunks, owners, s0, h0, hcount);

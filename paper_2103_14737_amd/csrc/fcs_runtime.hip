@@ -1264,6 +1264,9 @@ void enqueue_batch(fcs_ctx* c, const Params& P, int mode, int grid, int part)
         hipLaunchKernelGGL((fcsk::k_hits<true, false>), dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
     else if ((part == kAll || part == kHits) && P.hit_fluct)
         hipLaunchKernelGGL((fcsk::k_hits<false, true>), dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
+    else if ((part == kAll || part == kHits) && P.win_path)
+        hipLaunchKernelGGL((fcsk::k_hits<false, false, false>), dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s,
+                           dP);
     else if (part == kAll || part == kHits)
         hipLaunchKernelGGL((fcsk::k_hits<false, false>), dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
     if ((part == kAll || part == kPost) && mode == kDenseOnly) {
