@@ -139,6 +139,7 @@ struct Params {
     int32_t win_parts;     // particles per work item of the window pass
     int32_t n_windows;
     const int4* geo_windows;  // [n_windows * 2] see WinRec
+    unsigned long long* task_nT;  // window pass: hits | Ehit bits << 32 of task (p, l) at l * n_particles + p
     // workspace
     int32_t* task_n;
     float* task_ehit;
@@ -534,6 +535,12 @@ __device__ __forceinline__ int4 task_terms(const Params& P, int n)
 // Batches too small to give every CU several workgroups of several scan
 // blocks: one thread per task, one scan block (kBlock / L particles) per
 // workgroup.
+// a task's (hits, Ehit) pair as the window pass reads it
+__device__ __forceinline__ unsigned long long task_pair(int n, float ehit)
+{
+    return (unsigned long long)(uint32_t)n | ((unsigned long long)__float_as_uint(ehit) << 32);
+}
+
 __global__ __launch_bounds__(kBlock) void k_setup_one(const Params* __restrict__ Pp)
 {
     const Params& P = *Pp;
@@ -636,6 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_one(const Params* __restrict__
     if (active) {
         G(P.task_n)[t] = n;
         G(P.task_ehit)[t] = ehit;
+        if (P.win_path) G(P.task_nT)[(long long)l * P.n_particles + gp] = task_pair(n, ehit);
         if (G(P.out_elayer)) G(P.out_elayer)[t] = (float)el;
         if (G(P.out_counts)) G(P.out_counts)[t] = n;
         if (l == 0) {
@@ -825,6 +833,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
         G(P.task_ehit)[gt] = ehit;
         if (G(P.out_elayer)) G(P.out_elayer)[gt] = (float)el;
         if (G(P.out_counts)) G(P.out_counts)[gt] = n;
+        if (P.win_path) s_w[t] = __float_as_uint(ehit);
+    }
+    // the window pass reads (hits, Ehit) layer-major: consecutive lanes
+    // write consecutive particles of one layer
+    if (P.win_path) {
+        __syncthreads();
+        for (int k = tid; k < nt; k += kBlock) {
+            const int l = k / np, lp = k - l * np;
+            const int t = lp * L + l;
+            G(P.task_nT)[(long long)l * P.n_particles + p0 + lp] = task_pair(s_n[t], __uint_as_float(s_w[t]));
+        }
     }
     // the task scan's sums of (hits, chunks, small hits, small tasks), one
     // wave per scan block of this workgroup
@@ -1828,7 +1847,8 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
             int n = 0;
             if (p < b) {
                 const long long t = p * L + l;
-                const int nt = G(P.task_n)[t];
+                const unsigned long long ne = G(P.task_nT)[(long long)l * P.n_particles + p];
+                const int nt = (int)(uint32_t)ne;
                 if (nt > 0 && nt < P.big_thr) {
                     const Particle pt = load_particle(P.particles, p);
                     // home window: the one of this layer whose band holds eta
@@ -1841,9 +1861,8 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
                     if (is_home || (pt.eta >= win.b_lo - reach && pt.eta <= win.b_hi + reach)) {
                         n = nt;
                         const int H = G(P.part_set)[p] * L + l;
-                        s_pa[tid] = v4i{H | (is_home ? (int)0x80000000u : 0),
-                                        __float_as_int(G(P.task_ehit)[t]), __float_as_int(pt.eta),
-                                        __float_as_int(pt.phi)};
+                        s_pa[tid] = v4i{H | (is_home ? (int)0x80000000u : 0), (int)(uint32_t)(ne >> 32),
+                                        __float_as_int(pt.eta), __float_as_int(pt.phi)};
                         s_pb[tid] = make_int2((int)G(P.part_p)[p], (int)t);
                     }
                 }

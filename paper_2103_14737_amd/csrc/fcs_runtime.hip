@@ -1228,6 +1228,9 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
     P->win_parts = tu.win_parts;
     P->n_windows = c->n_windows;
     P->geo_windows = (const int4*)c->g_windows.p;
+    // the window pass has no small-task records: their buffer holds the
+    // layer-major (hits, Ehit) pairs it reads instead
+    P->task_nT = P->win_path ? (unsigned long long*)P->small_rec : nullptr;
     return FCS_OK;
 }
 
