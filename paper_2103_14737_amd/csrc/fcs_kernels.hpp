@@ -1766,7 +1766,8 @@ __global__ __launch_bounds__(kBlock) void k_hits(const Params* __restrict__ Pp)
 // home window (the one whose eta band holds it) only.
 constexpr int kWinThreads = 512;
 constexpr int kWinWaves = kWinThreads / kWave;
-constexpr int kWinCells = 14336;  // 56 KB of LDS: two workgroups per CU
+constexpr int kWinCells = 8192;   // 32 KB of LDS: three workgroups per CU
+constexpr int kWinPerCu = 3;      // resident workgroups of the window pass per CU
 constexpr int kFlushWords = 4;    // count words (1,024 cells) per wave and flush round
 static_assert(kWinCells % 64 == 0, "windows are whole 64-cell rows of LDS");
 

@@ -1261,7 +1261,7 @@ void enqueue_batch(fcs_ctx* c, const Params& P, int mode, int grid, int part)
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
     }
     if ((part == kAll || part == kHits) && P.win_path)
-        hipLaunchKernelGGL(fcsk::k_windows, dim3(c->n_cu * 2), dim3(fcsk::kWinThreads),
+        hipLaunchKernelGGL(fcsk::k_windows, dim3(c->n_cu * fcsk::kWinPerCu), dim3(fcsk::kWinThreads),
                            geo_lds_bytes(P) + (size_t)P.n_windows * 32, s, dP);
     if ((part == kAll || part == kHits) && P.placement_f64)
         hipLaunchKernelGGL((fcsk::k_hits<true, false>), dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
