@@ -668,26 +668,6 @@ constexpr int kSetupSubMax = 4;
 constexpr int kSetupTaskCap = kSetupSubMax * kBlock;
 constexpr int kSetupPartCap = kBlock;
 
-// the next task of a lane with a set from t on (tasks of particles without
-// a set get g = 0), and its Gamma constants
-__device__ __forceinline__ void gamma_next(const Params& P, const int* s_set, double* s_g, int L,
-                                           int nt, int& t, double& alpha, double& d, double& c,
-                                           uint32_t& j)
-{
-    while (t < nt && s_set[t / L] < 0) {
-        s_g[t] = 0.0;
-        t += kBlock;
-    }
-    if (t < nt) {
-        const int ty = s_set[t / L] / (P.n_ebins * P.n_etabins);
-        alpha = (double)G(P.alpha)[ty * L + t % L];
-        const double a = alpha < 1.0 ? alpha + 1.0 : alpha;
-        d = a - 1.0 / 3.0;
-        c = 1.0 / sqrt(9.0 * d);
-        j = 0;
-    }
-}
-
 // Six waves per SIMD (at most 80 VGPRs): the FP64 samplers of large batches
 // are throughput-bound, and the extra waves outweigh the larger call frames.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_setup(
@@ -703,6 +683,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
     __shared__ int s_set[kSetupPartCap];
     __shared__ float s_e[kSetupPartCap];
     __shared__ int s_cnt[2];
+    __shared__ int s_pool;  // the Gamma loop's next unclaimed task
     const int L = P.n_layers;
     const int ppb = kBlock / L;
     const int sub = P.setup_sub;
@@ -732,28 +713,60 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
         G(P.part_set)[gp] = set;
     }
     if (tid < 2) s_cnt[tid] = 0;
+    if (tid == 0) s_pool = kBlock;
     __syncthreads();
     {
+        // Each lane starts on task tid; a lane whose task is done (accepted,
+        // or its 64 attempts spent) takes the workgroup's next unclaimed one,
+        // so the lanes stay busy until the pool is empty whatever the
+        // rejections.  A task's draws depend only on its counters.
+        const int lane = lane_id();
         int t = tid;
-        double alpha = 0.0, d = 0.0, c = 0.0;
+        double d = 0.0, c = 0.0;
         uint32_t j = 0;
-        gamma_next(P, s_set, s_g, L, nt, t, alpha, d, c, j);
+        bool fresh = true;  // t is a new task: its constants are due
         while (__ballot(t < nt) != 0) {
+            bool finished = false;
             if (t < nt) {
-                double g = 0.0;
-                uint32_t w = 0;
                 const int lp = t / L;
-                bool done = gamma_try<1>(d, c, j, P.key0, P.key1, (uint32_t)(t % L), s_pin[lp], s_evg[lp],
-                                      &g, &w);
-                const bool fallback = !done && ++j == 64;
-                if (done || fallback) {
-                    // the boost of alpha < 1 waits for the pass below, so that
-                    // a wave runs it once for all its lanes
-                    s_g[t] = fallback ? d : g;
-                    s_w[t] = w;
-                    s_n[t] = fallback ? 1 : 0;
-                    t += kBlock;
-                    gamma_next(P, s_set, s_g, L, nt, t, alpha, d, c, j);
+                const int set = s_set[lp];
+                if (set < 0) {  // particles without a set: g = 0
+                    s_g[t] = 0.0;
+                    finished = true;
+                } else {
+                    if (fresh) {
+                        const double alpha = (double)G(P.alpha)[(set / (P.n_ebins * P.n_etabins)) * L + t % L];
+                        const double a = alpha < 1.0 ? alpha + 1.0 : alpha;
+                        d = a - 1.0 / 3.0;
+                        c = 1.0 / sqrt(9.0 * d);
+                        j = 0;
+                        fresh = false;
+                    }
+                    double g = 0.0;
+                    uint32_t w = 0;
+                    const bool done = gamma_try<1>(d, c, j, P.key0, P.key1, (uint32_t)(t % L), s_pin[lp],
+                                                   s_evg[lp], &g, &w);
+                    const bool fallback = !done && ++j == 64;
+                    if (done || fallback) {
+                        // the boost of alpha < 1 waits for the pass below, so
+                        // that a wave runs it once for all its lanes
+                        s_g[t] = fallback ? d : g;
+                        s_w[t] = w;
+                        s_n[t] = fallback ? 1 : 0;
+                        finished = true;
+                    }
+                }
+            }
+            // the finished lanes claim the next tasks, one LDS atomic per wave
+            const unsigned long long fm = __ballot(finished);
+            if (fm) {
+                const int leader = __ffsll((long long)fm) - 1;
+                int base = 0;
+                if (lane == leader) base = atomicAdd(&s_pool, __popcll(fm));
+                base = __shfl(base, leader, kWave);
+                if (finished) {
+                    t = base + __popcll(fm & ((1ull << lane) - 1ull));
+                    fresh = true;
                 }
             }
         }
