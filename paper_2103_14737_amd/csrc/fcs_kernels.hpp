@@ -1185,6 +1185,17 @@ __device__ __forceinline__ int find_bin(CumT cum, GuideT guide, uint32_t x0, flo
         const int g1 = guide[j < kGuide - 1 ? j + 1 : j];
         hi = j < kGuide - 1 ? g1 : kBins - 1;
     }
+    // cum is nondecreasing, so the bin is lo plus the number of entries of
+    // [lo, hi) at or below u.  From global memory (the window pass and the
+    // tiles) the usual short ranges read their (at most three) entries at
+    // once instead of one dependent read per halving; from LDS the halving
+    // loop issues fewer instructions
+    if (!kPadded && hi - lo <= 3) {
+        const float c0 = cum[lo];
+        const float c1 = cum[min(lo + 1, kBins - 1)];
+        const float c2 = cum[min(lo + 2, kBins - 1)];
+        return lo + (int)(lo < hi && c0 <= u) + (int)(lo + 1 < hi && c1 <= u) + (int)(lo + 2 < hi && c2 <= u);
+    }
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (cum[mid] > u) hi = mid;
@@ -1861,10 +1872,14 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
             int n = 0;
             if (p < b) {
                 const long long t = p * L + l;
+                // the particle's records are loaded beside its task's pair
+                // (one memory round trip per range, not two), used or not
                 const unsigned long long ne = G(P.task_nT)[(long long)l * P.n_particles + p];
+                const Particle pt = load_particle(P.particles, p);
+                const int pset = G(P.part_set)[p];
+                const int ppin = (int)G(P.part_p)[p];
                 const int nt = (int)(uint32_t)ne;
                 if (nt > 0 && nt < P.big_thr) {
-                    const Particle pt = load_particle(P.particles, p);
                     // home window: the one of this layer whose band holds eta
                     int home = win.first;
                     for (int k = win.first; k < win.first + win.n_layer - 1; ++k) {
@@ -1874,10 +1889,10 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
                     const bool is_home = home == w;
                     if (is_home || (pt.eta >= win.b_lo - reach && pt.eta <= win.b_hi + reach)) {
                         n = nt;
-                        const int H = G(P.part_set)[p] * L + l;
+                        const int H = pset * L + l;
                         s_pa[tid] = v4i{H | (is_home ? (int)0x80000000u : 0), (int)(uint32_t)(ne >> 32),
                                         __float_as_int(pt.eta), __float_as_int(pt.phi)};
-                        s_pb[tid] = make_int2((int)G(P.part_p)[p], (int)t);
+                        s_pb[tid] = make_int2(ppin, (int)t);
                     }
                 }
             }
