@@ -1817,10 +1817,9 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
     const Params& P = *Pp;
     extern __shared__ v4i s_geo[];
     __shared__ float s_acc[kWinCells];
-    __shared__ int s_end[kWinThreads];    // inclusive prefix of the staged tasks' hits
+    __shared__ int s_end[kWinThreads];    // per wave: inclusive prefix of its staged tasks' hits
     __shared__ v4i s_pa[kWinThreads];     // (histogram | home << 31, Ehit, eta, phi)
     __shared__ int2 s_pb[kWinThreads];    // (particle in event, task)
-    __shared__ int s_wsum[kWinWaves];
     __shared__ int s_item;
 
     const auto ctr = G(P.ctr);
@@ -1867,13 +1866,18 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
         const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)e);
         // a hit lands at most r_max / R_l away in eta (margins for rounding)
         const float reach = P.r_max * f_of(lrec.a.z) * 1.001f + 1e-3f;
-        for (long long pb = a; pb < b; pb += kWinThreads) {
-            const long long p = pb + tid;
+        // each wave takes its own groups of 64 particles of the range: it
+        // stages their tasks in its 64 slots, scans them within the wave and
+        // simulates their hits 64 at a time (a task's hits on consecutive
+        // lanes); the waves meet only before the flush
+        const int wbase = wave * kWave;
+        for (long long pg = a + wbase; pg < b; pg += kWinThreads) {
+            const long long p = pg + lane;
             int n = 0;
             if (p < b) {
                 const long long t = p * L + l;
                 // the particle's records are loaded beside its task's pair
-                // (one memory round trip per range, not two), used or not
+                // (one memory round trip per group, not two), used or not
                 const unsigned long long ne = G(P.task_nT)[(long long)l * P.n_particles + p];
                 const Particle pt = load_particle(P.particles, p);
                 const int pset = G(P.part_set)[p];
@@ -1896,31 +1900,23 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
                     }
                 }
             }
-            // inclusive block prefix of the staged hits
+            // inclusive prefix of the wave's staged hits
             const int inc = wave_incl_scan(n);
-            if (lane == kWave - 1) s_wsum[wave] = inc;
-            __syncthreads();
-            int before = 0, total = 0;
-#pragma unroll
-            for (int k = 0; k < kWinWaves; ++k) {
-                const int v = s_wsum[k];
-                before += k < wave ? v : 0;
-                total += v;
-            }
-            s_end[tid] = before + inc;
-            __syncthreads();
-            for (int q0 = 0; q0 < total; q0 += kWinThreads) {
-                const int q = q0 + tid;
+            const int total = __shfl(inc, kWave - 1, kWave);
+            s_end[tid] = inc;
+            wave_sync();
+            for (int q0 = 0; q0 < total; q0 += kWave) {
+                const int q = q0 + lane;
                 if (q < total) {
-                    // owner: the first staged slot whose prefix end exceeds q
-                    int lo = 0, hi = kWinThreads - 1;
+                    // owner: the wave's first staged slot whose prefix end exceeds q
+                    int lo = 0, hi = kWave - 1;
                     while (lo < hi) {
                         const int mid = (lo + hi) >> 1;
-                        if (s_end[mid] > q) hi = mid;
+                        if (s_end[wbase + mid] > q) hi = mid;
                         else lo = mid + 1;
                     }
-                    const int j = lo;
-                    const int i = q - (j ? s_end[j - 1] : 0);  // hit index within its task
+                    const int j = wbase + lo;
+                    const int i = q - (lo ? s_end[j - 1] : 0);  // hit index within its task
                     const v4i pa = s_pa[j];
                     const int2 pbk = s_pb[j];
                     const int H = pa.x & 0x7fffffff;
@@ -1936,8 +1932,9 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
                     }
                 }
             }
-            __syncthreads();  // the staged slots are reused by the next range
+            wave_sync();  // the wave's slots are restaged by its next group
         }
+        __syncthreads();  // every wave's hits are in the accumulator
         // flush the window: each wave takes kFlushWords count words (four
         // 64-cell blocks of the event's cells each) per round, issues the
         // coalesced atomic adds of all their nonzero rows, and only then
