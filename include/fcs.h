@@ -232,8 +232,13 @@ typedef struct {
                                    device pointers (else host)              */
     int32_t outputs_on_device;  /* every output pointer is a device pointer
                                    (else host; copied back before return)   */
-    int32_t profile;            /* 1: time the hit kernel with HIP events on
-                                   the stream it runs on (out->kernel_ms)    */
+    int32_t profile;            /* 1: time the hit step (window pass and
+                                   hit kernel) with HIP events on the stream
+                                   it runs on (out->kernel_ms), and in
+                                   synchronous calls the setup before it and
+                                   the compaction after it (out->setup_ms,
+                                   out->compact_ms); the hit step is then
+                                   launched outside the captured graph      */
     const float *elayer_override; /* [N * n_layers] or NULL: energies used for
                                    Ehit; hit counts still come from the
                                    particle's own layer energies.  Values
@@ -377,7 +382,15 @@ typedef struct {
     int64_t n_work_items;           /* chunks + tiles of the last launch     */
     double device_ms;               /* GPU time of the call (hipEvents)      */
     double kernel_ms;               /* with opt->profile: summed duration of
-                                       the hit kernel launches              */
+                                       the hit step (window pass and hit
+                                       kernel; the per-task launches in
+                                       FCS_MODE_PER_TASK)                    */
+    double setup_ms;                /* with opt->profile, synchronous calls:
+                                       summed duration of the setup and scans
+                                       before the hit step (-1 for
+                                       asynchronous calls)                   */
+    double compact_ms;              /* the same for the compaction and reset
+                                       after it                              */
 } fcs_sim_output;
 
 /* Simulate n_events events.  particles[N] are grouped by event:
@@ -428,7 +441,7 @@ typedef struct {
     int64_t n_hits;
     int64_t n_hits_out_of_acceptance;
     int64_t n_cells_nonzero;
-    double kernel_ms;           /* summed hit-kernel time of profiled calls */
+    double kernel_ms;           /* summed hit-step time of profiled calls  */
 } fcs_async_stats;
 
 /* Wait for every call enqueued on the context, then report the first error

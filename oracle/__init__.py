@@ -18,13 +18,15 @@ CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-s
           "-Wall", "-Wno-unused-function"]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (contraction off, no fast math)."""
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+def build(force: bool = True, out: str | None = None, extra=()) -> str:
+    """Compile the oracle with gcc (contraction off, no fast math) into `out`
+    (default liboracle.so), with `extra` flags (the sanitizer test's)."""
+    lib = out or LIB
+    if force or not os.path.exists(lib):
+        tmp = lib + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, *extra, SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 class OgGeom(C.Structure):
@@ -66,9 +68,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        path = os.environ.get("FCS_ORACLE_LIB") or LIB  # another build of the same source
+        if path == LIB and not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(path)
         vp, i64, u64, f32, f64, i32, u32 = (C.c_void_p, C.c_int64, C.c_uint64, C.c_float,
                                             C.c_double, C.c_int32, C.c_uint32)
         L.oracle_philox.argtypes = [vp, vp, vp]

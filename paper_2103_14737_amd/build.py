@@ -24,10 +24,10 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, lib: str, verbose: bool) -> str:
+def _compile(src: str, lib: str, verbose: bool, libs=()) -> str:
     tmp = lib + ".tmp"
     cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-           src, "-o", tmp]
+           src, "-o", tmp, *libs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
@@ -39,7 +39,8 @@ def build(verbose: bool = False) -> str:
     """Compile libfcs.so (the C ABI) and libfcs_ceilings.so (the benchmark's
     ceiling measurements); returns the path of libfcs.so."""
     _compile(CEIL_SRC, CEIL_LIB, verbose)
-    return _compile(SRC, LIB, verbose)
+    # roctx ranges around the entry points (rocprofv3 --marker-trace)
+    return _compile(SRC, LIB, verbose, libs=("-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"))
 
 
 if __name__ == "__main__":

@@ -5,6 +5,7 @@
 //
 // One translation unit holds the whole library (no relocatable device code).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cfloat>
@@ -20,6 +21,17 @@
 
 #include "fcs.h"
 #include "fcs_kernels.hpp"
+
+namespace {
+// A roctx range around an entry point's work: rocprofv3 --marker-trace shows
+// each call of the library beside its kernels.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+}  // namespace
 
 using fcsk::Counters;
 using fcsk::Params;
@@ -67,6 +79,7 @@ struct fcs_ctx {
     std::vector<int32_t> h_task_n;  // per-task launch form: an event's hit counts
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_in = nullptr;
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the hit kernel
+    hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr;  // around a profiled launch sequence
     std::string err = "no error";
     long long held = 0;
 
@@ -416,6 +429,7 @@ int fcs_create(fcs_ctx** out, int device)
         hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_stop) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
+        hipEventCreate(&c->ev_p0) != hipSuccess || hipEventCreate(&c->ev_p1) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_loaded, hipEventDisableTiming) != hipSuccess ||
@@ -506,6 +520,8 @@ void fcs_destroy(fcs_ctx* c)
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_k0) (void)hipEventDestroy(c->ev_k0);
     if (c->ev_k1) (void)hipEventDestroy(c->ev_k1);
+    if (c->ev_p0) (void)hipEventDestroy(c->ev_p0);
+    if (c->ev_p1) (void)hipEventDestroy(c->ev_p1);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -557,6 +573,7 @@ int fcs_host_free(fcs_ctx* c, void* ptr)
 // ------------------------------------------------------------ geometry ---
 int fcs_load_geometry(fcs_ctx* c, const fcs_geometry* g)
 {
+    const Range range("fcs_load_geometry");
     if (!c) return FCS_E_INVALID_ARG;
     if (!g) return fail(c, FCS_E_INVALID_ARG, "geometry is NULL");
     if (g->n_layers < 1 || g->n_layers > 64)
@@ -801,6 +818,7 @@ extern "C" {
 
 int fcs_load_parametrization(fcs_ctx* c, const fcs_param* p)
 {
+    const Range range("fcs_load_parametrization");
     if (!c) return FCS_E_INVALID_ARG;
     long long n_hist = 0;
     int rc = check_param(c, p, &n_hist);
@@ -849,6 +867,7 @@ int fcs_load_parametrization(fcs_ctx* c, const fcs_param* p)
 
 int fcs_load_parametrization_async(fcs_ctx* c, const fcs_param* p)
 {
+    const Range range("fcs_load_parametrization_async");
     if (!c) return FCS_E_INVALID_ARG;
     long long n_hist = 0;
     int rc = check_param(c, p, &n_hist);
@@ -1322,13 +1341,19 @@ int counters_error(fcs_ctx* c, const Counters& k)
     return FCS_OK;
 }
 
+// GPU time of a profiled synchronous launch sequence in its three parts:
+// setup and scans, the hit step (window pass and hit kernel), compaction
+struct PhaseMs {
+    double setup = 0.0, hits = 0.0, compact = 0.0;
+};
+
 // Run one launch sequence over a range of events and wait for it; with
 // `async`, enqueue it followed by the fold of its counters into the
 // context's running totals and return at once (*res is then zero).
 int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
               const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
               float* dense_out, const fcs_sim_output* dout, bool want_hits, bool validate,
-              bool use_graph, bool profile, Counters* res, double* kernel_ms, bool small_launch,
+              bool use_graph, bool profile, Counters* res, PhaseMs* phase_ms, bool small_launch,
               bool async, bool per_task = false, char* scratch = nullptr)
 {
     // a launch over few particles (per-event mode) gets a grid sized to its
@@ -1380,6 +1405,9 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             k1 = c->prof_ev[slot][1];
             ++c->prof_count;
         }
+        // a profiled synchronous call also times its setup and compaction
+        const bool phases = profile && !async;
+        if (phases) HIPCHK(c, hipEventRecord(c->ev_p0, c->stream));
         if (per_task) {
             // the per-(particle, layer) launch form: setup and scans, the
             // tasks' hit counts to the host, one launch per task with hits,
@@ -1407,6 +1435,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             }
             if (profile) HIPCHK(c, hipEventRecord(k1, c->stream));
             enqueue_batch(c, *P, mode, grid, kPost);
+            if (phases) HIPCHK(c, hipEventRecord(c->ev_p1, c->stream));
             HIPCHK(c, hipGetLastError());
         } else if (use_graph && !profile && !(async && c->copy_deferred)) {
             if ((rc = launch_graph(c, *P, key, mode, grid, kAll))) return rc;
@@ -1435,6 +1464,7 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             } else {
                 enqueue_batch(c, *P, mode, grid, kPost);
             }
+            if (phases) HIPCHK(c, hipEventRecord(c->ev_p1, c->stream));
             HIPCHK(c, hipGetLastError());
         }
         if (async) {
@@ -1459,10 +1489,14 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             c->chunk_cap = (long long)res->need_chunks + 1024;
             continue;
         }
-        if (profile && kernel_ms) {
-            float ms = 0.f;
-            HIPCHK(c, hipEventElapsedTime(&ms, k0, k1));
-            *kernel_ms += ms;
+        if (profile && phase_ms) {
+            float ms0 = 0.f, ms1 = 0.f, ms2 = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms0, c->ev_p0, k0));
+            HIPCHK(c, hipEventElapsedTime(&ms1, k0, k1));
+            HIPCHK(c, hipEventElapsedTime(&ms2, k1, c->ev_p1));
+            phase_ms->setup += ms0;
+            phase_ms->hits += ms1;
+            phase_ms->compact += ms2;
         }
         const int rc2 = counters_error(c, *res);
         if (rc2 == FCS_OK && keep && !P->win_path) {
@@ -1739,7 +1773,7 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
 
     if (!async) HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
     long long hits = 0, hits_out = 0, nnz = 0, items = 0;
-    double kms = 0.0;
+    PhaseMs pm;
     const bool profile = o->profile != 0;
     if (N == 0) {
         // no particles: zero outputs only
@@ -1752,7 +1786,7 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
         Counters k;
         rc = run_range(c, o, tu, sh, in.d_particles, in.d_evoff, in.d_override, d.cells, &d,
                        want_hits, in.validate_on_device, o->use_graph != 0 && !scratch, profile, &k,
-                       &kms, false, async, false, scratch);
+                       &pm, false, async, false, scratch);
         if (rc) return rc;
         hits = k.hits_total;
         hits_out = k.hits_out;
@@ -1781,7 +1815,7 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
             const float* dov = in.d_override ? in.d_override + p0 * L : nullptr;
             Counters k;
             rc = run_range(c, o, tu, sh, dp, in.d_evoff + e, dov, de.cells, &de, want_hits,
-                           in.validate_on_device, false, profile, &k, &kms, true, false, per_task);
+                           in.validate_on_device, false, profile, &k, &pm, true, false, per_task);
             if (rc) return rc;
             hits += k.hits_total;
             hits_out += k.hits_out;
@@ -1832,7 +1866,7 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
         out->n_tasks = N * L;
         out->n_cells_nonzero = out->required_cell_capacity = out->required_hit_capacity = -1;
         out->n_work_items = -1;
-        out->device_ms = out->kernel_ms = -1.0;
+        out->device_ms = out->kernel_ms = out->setup_ms = out->compact_ms = -1.0;
         return FCS_OK;
     }
     HIPCHK(c, hipEventRecord(c->ev_stop, c->stream));
@@ -1848,7 +1882,9 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
     out->required_hit_capacity = hits;
     out->n_work_items = items;
     out->device_ms = ms;
-    out->kernel_ms = kms;
+    out->kernel_ms = pm.hits;
+    out->setup_ms = pm.setup;
+    out->compact_ms = pm.compact;
 
     if (host_out) {
         if (f & FCS_OUT_DENSE)
@@ -1893,17 +1929,20 @@ extern "C" {
 int fcs_simulate_events(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
                         int64_t n_events, const fcs_sim_options* o, fcs_sim_output* out)
 {
+    const Range range("fcs_simulate_events");
     return simulate_impl(c, particles, event_offsets, n_events, o, out, false);
 }
 
 int fcs_simulate_events_noalloc(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
                                 int64_t n_events, const fcs_sim_options* o, fcs_sim_output* out)
 {
+    const Range range("fcs_simulate_events_noalloc");
     return simulate_impl(c, particles, event_offsets, n_events, o, out, true);
 }
 
 int fcs_synchronize(fcs_ctx* c, fcs_async_stats* st)
 {
+    const Range range("fcs_synchronize");
     if (!c) return FCS_E_INVALID_ARG;
     if (st) std::memset(st, 0, sizeof *st);
     if (c->dry) return fail(c, FCS_E_NO_DEVICE, "context has no device");
@@ -1947,6 +1986,7 @@ int fcs_synchronize(fcs_ctx* c, fcs_async_stats* st)
 int fcs_query_sizes(fcs_ctx* c, const fcs_particle* particles, const int64_t* event_offsets,
                     int64_t n_events, const fcs_sim_options* o, fcs_sizes* s)
 {
+    const Range range("fcs_query_sizes");
     if (!c) return FCS_E_INVALID_ARG;
     if (!s) return fail(c, FCS_E_INVALID_ARG, "sizes struct is NULL");
     Tuning tu;
@@ -1991,6 +2031,7 @@ int fcs_backward(fcs_ctx* c, const fcs_particle* particles, const int64_t* event
                  int64_t n_events, const fcs_sim_options* o, const float* grad_cells,
                  float* grad_elayer, float* grad_weights)
 {
+    const Range range("fcs_backward");
     if (!c) return FCS_E_INVALID_ARG;
     if (!grad_cells) return fail(c, FCS_E_INVALID_ARG, "grad_cells is NULL");
     if ((uintptr_t)grad_weights & 15)

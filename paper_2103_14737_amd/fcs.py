@@ -93,7 +93,7 @@ class FcsSimOutput(C.Structure):
                 ("n_tasks", C.c_int64), ("n_cells_nonzero", C.c_int64),
                 ("required_cell_capacity", C.c_int64), ("required_hit_capacity", C.c_int64),
                 ("n_work_items", C.c_int64), ("device_ms", C.c_double),
-                ("kernel_ms", C.c_double)]
+                ("kernel_ms", C.c_double), ("setup_ms", C.c_double), ("compact_ms", C.c_double)]
 
 
 class FcsAsyncStats(C.Structure):
@@ -403,7 +403,7 @@ class Simulator:
             return res
         stats = {k: getattr(so, k) for k in ("n_hits", "n_hits_out_of_acceptance", "n_tasks",
                                              "n_cells_nonzero", "n_work_items", "device_ms",
-                                             "kernel_ms")}
+                                             "kernel_ms", "setup_ms", "compact_ms")}
         nnz = so.n_cells_nonzero
         if "compact" in outputs:
             res["cell_ids"] = res["cell_ids"][:nnz]

@@ -15,6 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.fixture(scope="module")
 def F():
     from paper_2103_14737_amd import fcs
+    if os.environ.get("FCS_TEST_LIB"):  # another build of the same source
+        fcs.LIB_PATH = os.environ["FCS_TEST_LIB"]
     return fcs
 
 

@@ -676,3 +676,27 @@ def test_dense_output_in_every_launch_form(sim, torch_cuda):
         assert n == nnz
         assert np.array_equal(d != 0, ref != 0)
         assert np.allclose(d, ref, rtol=REL, atol=ABS)
+
+
+@pytest.mark.parametrize("mode", ["batched", "per_event", "per_task"])
+def test_profiled_phase_times(sim, torch_cuda, mode):
+    """A profiled synchronous call reports its setup, hit-step and compaction
+    times; together they fit in the call's device time, and the results equal
+    an unprofiled call's."""
+    w = W.subset_events(W.hard_scatter(), 3, 2)
+    dp, doff = _dev(w, torch_cuda)
+    base = w.notes["event_index_base"]
+    r = sim.simulate_events(dp, doff, w.seed, event_index_base=base, mode=mode,
+                            outputs=("compact",), profile=True)
+    torch_cuda.cuda.synchronize()
+    st = r["stats"]
+    print(f"[phases] {mode}: setup {st['setup_ms']:.3f} hits {st['kernel_ms']:.3f} "
+          f"compact {st['compact_ms']:.3f} device {st['device_ms']:.3f} ms", flush=True)
+    assert st["setup_ms"] > 0 and st["kernel_ms"] > 0 and st["compact_ms"] > 0
+    assert st["setup_ms"] + st["kernel_ms"] + st["compact_ms"] <= st["device_ms"] * 1.05 + 0.05
+    r0 = sim.simulate_events(dp, doff, w.seed, event_index_base=base, mode=mode,
+                             outputs=("compact",))
+    torch_cuda.cuda.synchronize()
+    assert r0["stats"]["kernel_ms"] == 0 and r0["stats"]["setup_ms"] == 0
+    assert np.array_equal(_np(r["cell_ids"]), _np(r0["cell_ids"]))
+    assert np.array_equal(_np(r["event_cell_offsets"]), _np(r0["event_cell_offsets"]))
