@@ -290,6 +290,28 @@ __device__ __forceinline__ T wave_incl_scan(T v)
     return v;
 }
 
+// inclusive scan (sum, or max of values >= 0) over a wave with DPP moves:
+// shifts by 1, 2, 4 and 8 lanes within each row of 16 (lanes shifted in from
+// outside the row read 0), then the last lane of rows 0 and 2 into rows 1 and
+// 3, then lane 31 into rows 2 and 3.  No LDS round trips, unlike __shfl_up.
+template <bool kMax>
+__device__ __forceinline__ int wave_scan_dpp(int v)
+{
+#define FCS_DPP_STEP(ctrl, rows)                                              \
+    {                                                                          \
+        const int t = __builtin_amdgcn_update_dpp(0, v, ctrl, rows, 0xf, false); \
+        v = kMax ? (t > v ? t : v) : v + t;                                    \
+    }
+    FCS_DPP_STEP(0x111, 0xf)  // row_shr:1
+    FCS_DPP_STEP(0x112, 0xf)  // row_shr:2
+    FCS_DPP_STEP(0x114, 0xf)  // row_shr:4
+    FCS_DPP_STEP(0x118, 0xf)  // row_shr:8
+    FCS_DPP_STEP(0x142, 0xa)  // row_bcast:15 into rows 1 and 3
+    FCS_DPP_STEP(0x143, 0xc)  // row_bcast:31 into rows 2 and 3
+#undef FCS_DPP_STEP
+    return v;
+}
+
 __device__ __forceinline__ int4 add4(int4 a, int4 b) { return make_int4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
 __device__ __forceinline__ int4 sub4(int4 a, int4 b) { return make_int4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
 
@@ -1817,7 +1839,8 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
     const Params& P = *Pp;
     extern __shared__ v4i s_geo[];
     __shared__ float s_acc[kWinCells];
-    __shared__ int s_end[kWinThreads];    // per wave: inclusive prefix of its staged tasks' hits
+    __shared__ int s_st[kWinThreads];     // per wave: first position of each staged task's hits
+    __shared__ int s_mark[kWinThreads];   // per wave and round: owner marks (zero between rounds)
     __shared__ v4i s_pa[kWinThreads];     // (histogram | home << 31, Ehit, eta, phi)
     __shared__ int2 s_pb[kWinThreads];    // (particle in event, task)
     __shared__ int s_item;
@@ -1841,6 +1864,7 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
     v4i* s_win = s_geo + 3 * P.n_layers + 2 * P.n_layers * P.n_regions;
     for (int i = tid; i < 2 * P.n_windows; i += kWinThreads) s_win[i] = ((const FCS_AS_GLOBAL v4i*)P.geo_windows)[i];
     for (int c = tid; c < kWinCells; c += kWinThreads) s_acc[c] = 0.0f;
+    s_mark[tid] = 0;
     const auto ticket = G(P.queue) + kWinTicket * kQueueStride;
     if (tid == 0) s_item = gfetch_add(ticket, 1);
     for (;;) {
@@ -1900,23 +1924,23 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
                     }
                 }
             }
-            // inclusive prefix of the wave's staged hits
-            const int inc = wave_incl_scan(n);
-            const int total = __shfl(inc, kWave - 1, kWave);
-            s_end[tid] = inc;
-            wave_sync();
+            // the wave's staged hits in slot order: slot j holds [st, inc)
+            const int inc = wave_scan_dpp<false>(n);
+            const int total = __builtin_amdgcn_readlane(inc, kWave - 1);
+            const int st = inc - n;
+            s_st[tid] = st;
             for (int q0 = 0; q0 < total; q0 += kWave) {
+                // owner of hit q0 + k: every slot with hits in [q0, q0 + 64)
+                // marks its first position there (distinct positions, the
+                // slot holding q0 at position 0), a max-scan fills the gaps
+                if (n > 0 && st < q0 + kWave && inc > q0) s_mark[wbase + (st > q0 ? st - q0 : 0)] = lane;
+                wave_sync();
+                const int own = wave_scan_dpp<true>(s_mark[tid]);
+                s_mark[tid] = 0;
                 const int q = q0 + lane;
                 if (q < total) {
-                    // owner: the wave's first staged slot whose prefix end exceeds q
-                    int lo = 0, hi = kWave - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_end[wbase + mid] > q) hi = mid;
-                        else lo = mid + 1;
-                    }
-                    const int j = wbase + lo;
-                    const int i = q - (lo ? s_end[j - 1] : 0);  // hit index within its task
+                    const int j = wbase + own;
+                    const int i = q - s_st[j];  // hit index within its task
                     const v4i pa = s_pa[j];
                     const int2 pbk = s_pb[j];
                     const int H = pa.x & 0x7fffffff;
