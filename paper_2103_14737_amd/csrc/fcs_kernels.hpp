@@ -1844,6 +1844,7 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
     __shared__ v4i s_pa[kWinThreads];     // (histogram | home << 31, Ehit, eta, phi)
     __shared__ int2 s_pb[kWinThreads];    // (particle in event, task)
     __shared__ int s_item;
+    __shared__ int s_next;                // next group of 64 particles of the item's range
 
     const auto ctr = G(P.ctr);
     if (!P.win_path || (ctr->error & (kErrTooManyHits | kErrChunkCap))) return;
@@ -1868,6 +1869,7 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
     const auto ticket = G(P.queue) + kWinTicket * kQueueStride;
     if (tid == 0) s_item = gfetch_add(ticket, 1);
     for (;;) {
+        if (tid == 0) s_next = 0;  // every wave has left the previous item's groups
         __syncthreads();  // the previous item's flush is complete; s_item is set
         const long long item = s_item;
         __syncthreads();  // every thread has read it
@@ -1890,12 +1892,16 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
         const uint32_t evg = (uint32_t)(P.ev_base + (unsigned long long)e);
         // a hit lands at most r_max / R_l away in eta (margins for rounding)
         const float reach = P.r_max * f_of(lrec.a.z) * 1.001f + 1e-3f;
-        // each wave takes its own groups of 64 particles of the range: it
-        // stages their tasks in its 64 slots, scans them within the wave and
-        // simulates their hits 64 at a time (a task's hits on consecutive
-        // lanes); the waves meet only before the flush
+        // each wave claims groups of 64 particles of the range until none is
+        // left: it stages their tasks in its 64 slots, scans them within the
+        // wave and simulates their hits 64 at a time (a task's hits on
+        // consecutive lanes); the waves meet only before the flush
         const int wbase = wave * kWave;
-        for (long long pg = a + wbase; pg < b; pg += kWinThreads) {
+        for (;;) {
+            int g = 0;
+            if (lane == 0) g = atomicAdd(&s_next, kWave);
+            const long long pg = a + __builtin_amdgcn_readfirstlane(g);
+            if (pg >= b) break;
             const long long p = pg + lane;
             int n = 0;
             if (p < b) {
