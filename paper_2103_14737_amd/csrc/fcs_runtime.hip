@@ -161,6 +161,10 @@ struct fcs_ctx {
     } dc{};
     bool copy_deferred = false;
     hipEvent_t ev_pre = nullptr;
+    // the copy of an earlier batch out of the staging set this call reuses:
+    // the call's stream waits for it just before the compaction writes the
+    // set (its setup pass and hit kernels run beside the copy)
+    hipEvent_t post_wait = nullptr;
     // the work queue in the workspace: the device inputs and options it was
     // built from and its parameter block; an adjoint call with
     // reuse_forward_queue and the same inputs skips the setup and the scans.
@@ -1350,6 +1354,16 @@ struct PhaseMs {
 // Run one launch sequence over a range of events and wait for it; with
 // `async`, enqueue it followed by the fold of its counters into the
 // context's running totals and return at once (*res is then zero).
+// the stream waits for the copy out of the staging set the call reuses
+int wait_staged_copy(fcs_ctx* c)
+{
+    if (!c->post_wait) return FCS_OK;
+    const hipEvent_t ev = c->post_wait;
+    c->post_wait = nullptr;
+    HIPCHK(c, hipStreamWaitEvent(c->stream, ev, 0));
+    return FCS_OK;
+}
+
 int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
               const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
               float* dense_out, const fcs_sim_output* dout, bool want_hits, bool validate,
@@ -1434,10 +1448,12 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
                                        geo_lds_bytes(*P), c->stream, dP, (int)t);
             }
             if (profile) HIPCHK(c, hipEventRecord(k1, c->stream));
+            if ((rc = wait_staged_copy(c))) return rc;
             enqueue_batch(c, *P, mode, grid, kPost);
             if (phases) HIPCHK(c, hipEventRecord(c->ev_p1, c->stream));
             HIPCHK(c, hipGetLastError());
         } else if (use_graph && !profile && !(async && c->copy_deferred)) {
+            if ((rc = wait_staged_copy(c))) return rc;
             if ((rc = launch_graph(c, *P, key, mode, grid, kAll))) return rc;
         } else {
             // profiled, or a copy to the host waits for the setup pass: the
@@ -1458,6 +1474,9 @@ int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shap
             if (profile) HIPCHK(c, hipEventRecord(k0, c->stream));
             enqueue_batch(c, *P, mode, grid, kHits);
             if (profile) HIPCHK(c, hipEventRecord(k1, c->stream));
+            // the staging set this batch compacts into is free once the
+            // earlier copy out of it has ended
+            if ((rc = wait_staged_copy(c))) return rc;
             if (use_graph) {
                 key.part = kPost;
                 if ((rc = launch_graph(c, *P, key, mode, grid, kPost))) return rc;
@@ -1713,7 +1732,10 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
         c->hs_next ^= 1;
         // the set is free once its last copy to the host has completed
         if (c->copy_deferred && c->dc.hs == hs && (rc = flush_host_copy(c))) return rc;
-        if (c->copy_pending[hs]) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_copied[hs], 0));
+        if (c->copy_pending[hs]) {
+            if (!per_event && in.N > 0) c->post_wait = c->ev_copied[hs];
+            else HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_copied[hs], 0));
+        }
         const size_t cap = (size_t)std::max<int64_t>(out->cell_capacity, 1);
         if (c->hs_ids[hs].bytes < cap * 8 || c->hs_e[hs].bytes < cap * 4 ||
             c->hs_off[hs].bytes < (size_t)(n_events + 1) * 8)
@@ -1787,6 +1809,9 @@ int simulate_impl(fcs_ctx* c, const fcs_particle* particles, const int64_t* even
         rc = run_range(c, o, tu, sh, in.d_particles, in.d_evoff, in.d_override, d.cells, &d,
                        want_hits, in.validate_on_device, o->use_graph != 0 && !scratch, profile, &k,
                        &pm, false, async, false, scratch);
+        // a run that failed before its compaction still leaves the set's
+        // copy ahead of whatever the stream does next
+        if (int rcw = wait_staged_copy(c)) return rc ? rc : rcw;
         if (rc) return rc;
         hits = k.hits_total;
         hits_out = k.hits_out;
