@@ -597,9 +597,10 @@ def run_ceilings(n_cells=191338, n_events_big=100):
 
 def roofline(hits, kernel_ms, workload, tuning):
     """The roofline object of the hit step (window pass + hit kernel, the
-    dominant kernels) from its HIP-event time per launch: algorithmic VALU
-    instruction slots per launch over that time, against the chip's issue
-    rate at the nominal clock."""
+    dominant kernels; the task scans run beside the window pass and are
+    inside the timed span) from its HIP-event time per launch: algorithmic
+    VALU instruction slots per launch over that time, against the chip's
+    issue rate at the nominal clock."""
     achieved = SLOTS_PER_HIT * hits / (kernel_ms * 1e-3)
     return {"kernel": "hit step (k_windows + k_hits)", "bound": "alu",
             "achieved": achieved / 1e12, "peak": VALU_SLOT_PEAK / 1e12,

@@ -384,11 +384,15 @@ typedef struct {
     double kernel_ms;               /* with opt->profile: summed duration of
                                        the hit step (window pass and hit
                                        kernel; the per-task launches in
-                                       FCS_MODE_PER_TASK)                    */
+                                       FCS_MODE_PER_TASK).  When the window
+                                       pass runs without hit lists it runs
+                                       on a second stream beside the task
+                                       scans, which then open the hit step */
     double setup_ms;                /* with opt->profile, synchronous calls:
-                                       summed duration of the setup and scans
-                                       before the hit step (-1 for
-                                       asynchronous calls)                   */
+                                       summed duration of the setup pass
+                                       (and the task scans when they are not
+                                       in the hit step) before the hit step
+                                       (-1 for asynchronous calls)           */
     double compact_ms;              /* the same for the compaction and reset
                                        after it                              */
 } fcs_sim_output;

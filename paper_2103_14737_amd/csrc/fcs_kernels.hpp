@@ -580,6 +580,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_one(const Params* __restrict__
     const long long gp = (long long)blockIdx.x * ppb + lp;
     const bool active = lp < ppb && gp < P.n_particles;
     if (P.validate) check_offsets(P);
+    if (blockIdx.x == 0 && tid == 0) G(P.queue)[kWinTicket * kQueueStride] = 0;  // the window pass's ticket
     Particle pt = {0, 0.f, 0.f, 0.f};
     int set = -1, ev = 0;
     uint32_t pin = 0, evg = 0;
@@ -714,6 +715,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
     const int np = (int)min((long long)(ppb * sub), P.n_particles - p0);
     const int nt = np * L;
     if (P.validate) check_offsets(P);
+    if (blockIdx.x == 0 && tid == 0) G(P.queue)[kWinTicket * kQueueStride] = 0;  // the window pass's ticket
     for (int lp = tid; lp < np; lp += kBlock) {
         const long long gp = p0 + lp;
         const Particle pt = load_particle(P.particles, gp);
@@ -954,7 +956,9 @@ __device__ __forceinline__ void scan1024(long long h, int4 r, long long& ho, int
 __device__ __forceinline__ void scan_totals(const Params& P, long long htot, int4 rtot)
 {
     const int tid = threadIdx.x;
-    if (tid <= kWinTicket) G(P.queue)[tid * kQueueStride] = 0;
+    // the hit kernel's tickets and drained flags (the window pass's ticket is
+    // reset by the setup pass: the window pass may already be running)
+    if (tid < kWinTicket) G(P.queue)[tid * kQueueStride] = 0;
     if (tid == 0) {
         auto cc = G(P.ctr);
         cc->hits_total = htot;

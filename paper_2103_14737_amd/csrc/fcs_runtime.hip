@@ -146,6 +146,11 @@ struct fcs_ctx {
     // one of two device staging sets (used in turn) and a copy kernel on
     // copy_stream writes the lists to the host while the next batch runs
     hipStream_t copy_stream = nullptr;
+    // the window pass runs on win_stream beside the task scans (it needs
+    // only the setup pass's outputs); forked after the setup pass and
+    // joined before the compaction, also inside captured graphs
+    hipStream_t win_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     DevBuf hs_ids[2], hs_e[2], hs_off[2];
     hipEvent_t ev_staged[2] = {}, ev_copied[2] = {};
     bool copy_pending[2] = {};
@@ -436,6 +441,9 @@ int fcs_create(fcs_ctx** out, int device)
         hipEventCreate(&c->ev_p0) != hipSuccess || hipEventCreate(&c->ev_p1) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->win_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_loaded, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_spare_free, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_staged[0], hipEventDisableTiming) != hipSuccess ||
@@ -519,6 +527,9 @@ void fcs_destroy(fcs_ctx* c)
     }
     if (c->ev_pre) (void)hipEventDestroy(c->ev_pre);
     if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    if (c->win_stream) (void)hipStreamDestroy(c->win_stream);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
@@ -1275,17 +1286,34 @@ void enqueue_batch(fcs_ctx* c, const Params& P, int mode, int grid, int part)
     const bool dense = mode != kPrivate;
     const Params* dP = (const Params*)c->cur_params;
     hipStream_t s = c->stream;
-    if (part == kAll || part == kPre) {
-        if (dense) hipLaunchKernelGGL(fcsk::k_fill_dense, dim3(2048), dim3(256), 0, s, dP);
-        launch_setup(s, dP, P.n_particles, P.n_layers, c->n_cu);
+    // the window pass needs the setup pass's outputs only (and the task
+    // scans' hit offsets when it writes hit lists): it then runs on the
+    // second stream beside the scans, which open the hit step
+    const bool fork = P.win_path && !P.want_hits;
+    const auto scans = [&]() {
         hipLaunchKernelGGL(fcsk::k_scan_group, dim3(P.n_scan_groups), dim3(fcsk::kScanThreads), 0, s, dP);
         if (P.n_scan_groups > 1)
             hipLaunchKernelGGL(fcsk::k_scan_top, dim3(1), dim3(fcsk::kScanThreads), 0, s, dP);
         hipLaunchKernelGGL(fcsk::k_scan_write, dim3(P.n_scan_blocks), dim3(fcsk::kBlock), 0, s, dP);
-    }
-    if ((part == kAll || part == kHits) && P.win_path)
+    };
+    const auto windows = [&](hipStream_t ws) {
         hipLaunchKernelGGL(fcsk::k_windows, dim3(c->n_cu * fcsk::kWinPerCu), dim3(fcsk::kWinThreads),
-                           geo_lds_bytes(P) + (size_t)P.n_windows * 32, s, dP);
+                           geo_lds_bytes(P) + (size_t)P.n_windows * 32, ws, dP);
+    };
+    if (part == kAll || part == kPre) {
+        if (dense) hipLaunchKernelGGL(fcsk::k_fill_dense, dim3(2048), dim3(256), 0, s, dP);
+        launch_setup(s, dP, P.n_particles, P.n_layers, c->n_cu);
+        if (!fork) scans();
+    }
+    if ((part == kAll || part == kHits) && fork) {
+        (void)hipEventRecord(c->ev_fork, s);
+        (void)hipStreamWaitEvent(c->win_stream, c->ev_fork, 0);
+        windows(c->win_stream);
+        (void)hipEventRecord(c->ev_join, c->win_stream);
+        scans();
+    } else if ((part == kAll || part == kHits) && P.win_path) {
+        windows(s);
+    }
     if ((part == kAll || part == kHits) && P.placement_f64)
         hipLaunchKernelGGL((fcsk::k_hits<true, false>), dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
     else if ((part == kAll || part == kHits) && P.hit_fluct)
@@ -1295,6 +1323,7 @@ void enqueue_batch(fcs_ctx* c, const Params& P, int mode, int grid, int part)
                            dP);
     else if (part == kAll || part == kHits)
         hipLaunchKernelGGL((fcsk::k_hits<false, false>), dim3(grid), dim3(fcsk::kBlock), geo_lds_bytes(P), s, dP);
+    if ((part == kAll || part == kHits) && fork) (void)hipStreamWaitEvent(s, c->ev_join, 0);
     if ((part == kAll || part == kPost) && mode == kDenseOnly) {
         const long long words = P.n_events << (P.blk_shift - 4);
         hipLaunchKernelGGL(fcsk::k_flags_reset,
@@ -1351,9 +1380,6 @@ struct PhaseMs {
     double setup = 0.0, hits = 0.0, compact = 0.0;
 };
 
-// Run one launch sequence over a range of events and wait for it; with
-// `async`, enqueue it followed by the fold of its counters into the
-// context's running totals and return at once (*res is then zero).
 // the stream waits for the copy out of the staging set the call reuses
 int wait_staged_copy(fcs_ctx* c)
 {
@@ -1364,6 +1390,9 @@ int wait_staged_copy(fcs_ctx* c)
     return FCS_OK;
 }
 
+// Run one launch sequence over a range of events and wait for it; with
+// `async`, enqueue it followed by the fold of its counters into the
+// context's running totals and return at once (*res is then zero).
 int run_range(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape& sh,
               const fcsk::Particle* d_particles, const long long* d_evoff, const float* d_override,
               float* dense_out, const fcs_sim_output* dout, bool want_hits, bool validate,
