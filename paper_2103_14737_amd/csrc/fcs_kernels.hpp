@@ -829,19 +829,97 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
         }
         s_n[t] = 0;
     }
+    if (tid == 0) s_pool = 0;  // the Gamma loop is over: the pool now hands out rejection draws
     __syncthreads();  // every sum has read the draws: they make way for the layer energies
 #pragma unroll
     for (int k = 0; k < kSetupSubMax; ++k)
         if (tid + k * kBlock < nt) s_g[tid + k * kBlock] = el_t[k];
     {
         const int c0 = s_cnt[0], c1 = s_cnt[1];
-        for (int i = tid; i < c0 + c1; i += kBlock) {
-            const int t = i < c0 ? s_list[i] : s_list[kSetupTaskCap - 1 - (i - c0)];
+        // inversion draws (mu < 10), one per lane at a time
+        for (int i = tid; i < c0; i += kBlock) {
+            const int t = s_list[i];
             const int lp = t / L;
             long long k = poisson_draw<1>(s_mu[t], P.key0, P.key1, (uint32_t)(t % L), s_pin[lp], s_evg[lp]);
             if (k < 1) k = 1;
             if (k > P.cap) k = P.cap;
             s_n[t] = (int)k;
+        }
+        // transformed-rejection draws (mu >= 10): the same attempts in the
+        // same order as poisson_draw, taken one step at a time per lane so
+        // that the costly parts run with many lanes at once: idle lanes
+        // claim new draws (and compute their constants) together once half
+        // the wave is idle; an attempt that passes neither quick test waits
+        // for the full test until a quarter of the wave waits too, or no
+        // lane has a quick step left
+        const int lane = lane_id();
+        int t = -1;  // the lane's task, -1 when idle
+        double mu = 0.0, b = 0.0, a = 0.0, vr = 0.0, log_ia = 0.0, loglam = 0.0;
+        double kd = 0.0, us = 0.0, V = 0.0;
+        uint32_t att = 0;  // attempt 2j + h: words (x, y) or (z, w) of counter j
+        bool full = false; // attempt att awaits the full test
+        bool drained = false;
+        const auto finish = [&](long long k) {
+            if (k < 1) k = 1;
+            if (k > P.cap) k = P.cap;
+            s_n[t] = (int)k;
+            t = -1;
+        };
+        for (;;) {
+            const unsigned long long idle = __ballot(t < 0);
+            if (!drained && __popcll(idle) >= kWave / 2) {
+                const int leader = __ffsll((long long)idle) - 1;
+                int base = 0;
+                if (lane == leader) base = atomicAdd(&s_pool, __popcll(idle));
+                base = __shfl(base, leader, kWave);
+                drained = base + __popcll(idle) >= c1;
+                const int k = base + __popcll(idle & ((1ull << lane) - 1ull));
+                if (t < 0 && k < c1) {
+                    t = s_list[kSetupTaskCap - 1 - k];
+                    mu = s_mu[t];
+                    const double slam = sqrt(mu);
+                    loglam = dlog<1>(mu);
+                    b = 0.931 + 2.53 * slam;
+                    a = -0.059 + 0.02483 * b;
+                    const double invalpha = 1.1239 + 1.1328 / (b - 3.4);
+                    vr = 0.9277 - 3.6224 / (b - 2.0);
+                    log_ia = dlog<1>(invalpha);
+                    att = 0;
+                    full = false;
+                }
+            }
+            const unsigned long long quick = __ballot(t >= 0 && !full);
+            if (quick == 0 && __ballot(t >= 0) == 0) {
+                if (drained) break;
+                continue;  // fewer than half the lanes were idle: claim now
+            }
+            if (t >= 0 && !full) {
+                const int lp = t / L;
+                const U4 x = philox4x32_10(att >> 1, (uint32_t)(t % L) | (kTagPoisson << 8), s_pin[lp], s_evg[lp],
+                                           P.key0, P.key1);
+                const uint32_t wu = (att & 1) ? x.z : x.x;
+                const uint32_t wv = (att & 1) ? x.w : x.y;
+                const double U = unit_open(wu) - 0.5;
+                V = unit_open(wv);
+                us = 0.5 - fabs(U);
+                kd = floor((((2.0 * a) / us + b) * U + mu) + 0.43);
+                if (us >= 0.07 && V <= vr) finish((long long)kd);
+                else if (kd < 0.0 || (us < 0.013 && V > us)) {
+                    if (++att == 64) finish((long long)floor(mu));
+                } else {
+                    full = true;
+                }
+            }
+            const unsigned long long fm = __ballot(t >= 0 && full);
+            if (fm != 0 && (__popcll(fm) >= kWave / 4 || __ballot(t >= 0 && !full) == 0)) {
+                if (t >= 0 && full) {
+                    const double lhs = (dlog<1>(V) + log_ia) - dlog<1>(a / (us * us) + b);
+                    const double rhs = (-mu + kd * loglam) - dlnfact<1>((long long)kd);
+                    full = false;
+                    if (lhs <= rhs) finish((long long)kd);
+                    else if (++att == 64) finish((long long)floor(mu));
+                }
+            }
         }
     }
     __syncthreads();
