@@ -1922,7 +1922,9 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
     extern __shared__ v4i s_geo[];
     __shared__ float s_acc[kWinCells];
     __shared__ int s_st[kWinThreads];     // per wave: first position of each staged task's hits
-    __shared__ int s_mark[kWinThreads];   // per wave and round: owner marks (zero between rounds)
+    // per wave and round: owner marks, slot numbers below 64 (zero between
+    // rounds); bytes, so that three workgroups still fit a CU's LDS
+    __shared__ uint8_t s_mark[kWinThreads];
     __shared__ v4i s_pa[kWinThreads];     // (histogram | home << 31, Ehit, eta, phi)
     __shared__ int2 s_pb[kWinThreads];    // (particle in event, task)
     __shared__ int s_item;
@@ -2021,9 +2023,9 @@ __global__ __launch_bounds__(kWinThreads) void k_windows(const Params* __restric
                 // owner of hit q0 + k: every slot with hits in [q0, q0 + 64)
                 // marks its first position there (distinct positions, the
                 // slot holding q0 at position 0), a max-scan fills the gaps
-                if (n > 0 && st < q0 + kWave && inc > q0) s_mark[wbase + (st > q0 ? st - q0 : 0)] = lane;
+                if (n > 0 && st < q0 + kWave && inc > q0) s_mark[wbase + (st > q0 ? st - q0 : 0)] = (uint8_t)lane;
                 wave_sync();
-                const int own = wave_scan_dpp<true>(s_mark[tid]);
+                const int own = wave_scan_dpp<true>((int)s_mark[tid]);
                 s_mark[tid] = 0;
                 const int q = q0 + lane;
                 if (q < total) {
