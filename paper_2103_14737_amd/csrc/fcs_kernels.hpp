@@ -8,6 +8,10 @@
 //   k_scan_group / k_scan_top / k_scan_write
 //                  scans of the task hit counts -> work queue: chunks of
 //                  large tasks, packed tiles of small tasks
+//   k_windows      batches of many-particle events: the small tasks by cell
+//                  window, summed in LDS and added with coalesced atomics
+//                  (on a second stream beside the scans when it writes no
+//                  hit lists)
 //   k_hits         persistent: pulls work items from a ticket counter; per
 //                  hit Philox draw, inverse-CDF bin, placement, cell lookup,
 //                  deposit (sim_a of the CUDA Implementation section)
