@@ -334,12 +334,13 @@ typedef struct {
                                    entries the batch wrote (at most
                                    cell_capacity) through the buffers'
                                    device mapping; each workgroup moves
-                                   about 12 GB/s, and the link's traffic
+                                   about 25 GB/s (two come near the
+                                   link's 56 GB/s), and the link's traffic
                                    slows the kernels beside it, so a batch
                                    whose compute outlasts its copy wants
                                    few.  -1: the runtime's hipMemcpyAsync
                                    of cell_capacity entries.  0 = default
-                                   (4 workgroups).  At most 4096.           */
+                                   (2 workgroups).  At most 4096.           */
 } fcs_sim_options;
 
 /* Fill *opt with the defaults: seed 0, batched, compact output, 100 MeV per

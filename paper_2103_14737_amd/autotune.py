@@ -131,7 +131,7 @@ def tune(sim, particles, event_offsets, seed, *, outputs=("compact",), hit_energ
     return dict(best)
 
 
-HOST_COPY_CANDIDATES = (2, 3, 4, 6, 8, 16, 32)
+HOST_COPY_CANDIDATES = (1, 2, 3, 4, 6, 8, 16)
 
 
 def tune_host_copy(sim, particles, event_offsets, seed, host_sets, cell_capacity, *,

@@ -412,17 +412,28 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, long long n, uint32_t v)
 // the entries the batch wrote (the total in offsets[n_events], at most
 // `cap`).  The stores cross the host link; with few waves in flight the
 // kernels beside them keep the rest of the chip.  16-byte moves where the
-// source and destination are both 16-byte aligned, element moves otherwise.
+// source and destination are both 16-byte aligned (eight loads in flight per
+// thread before their stores: a workgroup's rate is set by how many bytes it
+// has in flight), element moves otherwise.
 template <typename T>
 __device__ void copy_to_host(const T* __restrict__ src, T* __restrict__ dst, long long n, long long gid,
                              long long stride)
 {
     constexpr long long kPer = 16 / sizeof(T);
+    constexpr int kUnroll = 8;
     if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0) {
         const long long nv = n / kPer;
         const v4i* s4 = reinterpret_cast<const v4i*>(src);
         v4i* d4 = reinterpret_cast<v4i*>(dst);
-        for (long long i = gid; i < nv; i += stride) __builtin_nontemporal_store(s4[i], d4 + i);
+        long long i = gid;
+        for (; i + (kUnroll - 1) * stride < nv; i += kUnroll * stride) {
+            v4i v[kUnroll];
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) v[k] = s4[i + k * stride];
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) __builtin_nontemporal_store(v[k], d4 + i + k * stride);
+        }
+        for (; i < nv; i += stride) __builtin_nontemporal_store(s4[i], d4 + i);
         for (long long i = nv * kPer + gid; i < n; i += stride) dst[i] = src[i];
     } else {
         for (long long i = gid; i < n; i += stride) dst[i] = src[i];

@@ -68,7 +68,7 @@ constexpr int kMaxWindows = 256;  // cell windows of the window pass per geometr
 // keep the packed tiles)
 constexpr long long kWinMinParticlesPerEvent = 64;
 constexpr int kProfRing = 64;     // event pairs of profiled asynchronous calls
-constexpr int kHostCopyWgs = 4;   // workgroups of the copy kernel to host buffers (~50 GB/s)
+constexpr int kHostCopyWgs = 2;   // workgroups of the copy kernel to host buffers (~50 GB/s)
 
 struct fcs_ctx {
     int device = 0;
