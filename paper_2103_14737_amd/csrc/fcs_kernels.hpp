@@ -414,7 +414,9 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, long long n, uint32_t v)
 // kernels beside them keep the rest of the chip.  16-byte moves where the
 // source and destination are both 16-byte aligned (eight loads in flight per
 // thread before their stores: a workgroup's rate is set by how many bytes it
-// has in flight), element moves otherwise.
+// has in flight; loads and stores marked streaming, so that the lists do not
+// displace the tables the batch beside them reads from L2), element moves
+// otherwise.
 template <typename T>
 __device__ void copy_to_host(const T* __restrict__ src, T* __restrict__ dst, long long n, long long gid,
                              long long stride)
@@ -429,7 +431,7 @@ __device__ void copy_to_host(const T* __restrict__ src, T* __restrict__ dst, lon
         for (; i + (kUnroll - 1) * stride < nv; i += kUnroll * stride) {
             v4i v[kUnroll];
 #pragma unroll
-            for (int k = 0; k < kUnroll; ++k) v[k] = s4[i + k * stride];
+            for (int k = 0; k < kUnroll; ++k) v[k] = __builtin_nontemporal_load(s4 + i + k * stride);
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) __builtin_nontemporal_store(v[k], d4 + i + k * stride);
         }
