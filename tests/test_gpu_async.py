@@ -324,3 +324,42 @@ def test_host_copy_flushed_by_other_calls(sim, torch_cuda, oracle_lib, geom_full
                      event_index_base=base)
         sim.synchronize()
         check(f"{wgs} workgroups, then an adjoint call")
+
+
+def test_staging_set_reused_while_its_copy_runs(sim, torch_cuda, oracle_lib, geom_full, param_full):
+    """A call that reuses a device staging set waits for the copy out of it
+    only before its own compaction: a pile-up pair of events (4 MB of lists,
+    copied by one workgroup) and then two single-particle events, the second
+    of which compacts into the pile-up call's set while that copy may still
+    run; after the synchronization every call's host lists equal the
+    oracle's, twice in a row."""
+    torch = torch_cuda
+    geo = W.make_geometry()
+    ws = [W.subset_events(W.pileup(), 0, 2)] + \
+         [W.subset_events(W.single_particle_sweep(), k, 1) for k in (11, 12)]
+    calls = []
+    for w in ws:
+        base = w.notes["event_index_base"]
+        dp, doff = _dev(w, torch)
+        ref = oracle_lib.simulate(geom_full, param_full, w.particles, w.event_offsets, w.seed,
+                                  event_index_base=base, hit_energy_scale=w.hit_energy_scale)
+        nnz = ref["n_cells_nonzero"]
+        out = {"cell_ids": sim.host_empty((nnz,), np.int64),
+               "cell_e": sim.host_empty((nnz,), np.float32),
+               "event_cell_offsets": sim.host_empty((w.n_events + 1,), np.int64)}
+        calls.append((w, base, dp, doff, ref, out))
+    for rep in range(2):
+        for w, base, dp, doff, ref, out in calls:
+            for a in out.values():
+                a.fill(-1)
+            sim.simulate_events(dp, doff, w.seed, event_index_base=base, outputs=("compact",),
+                                out=out, cell_capacity=ref["n_cells_nonzero"], async_launch=True,
+                                host_outputs=True, host_copy_workgroups=1,
+                                hit_energy_scale=w.hit_energy_scale)
+        sim.synchronize()
+        for w, base, dp, doff, ref, out in calls:
+            print(f"[staging reuse] pass {rep}: {w.name}, {ref['n_cells_nonzero']} cells", flush=True)
+            assert np.array_equal(out["event_cell_offsets"], ref["ev_cell_off"])
+            assert np.array_equal(out["cell_ids"], geo["cell_id"][ref["cell_idx"]])
+            e = out["cell_e"].astype(np.float64)
+            assert np.all(np.abs(e - ref["cell_e"]) <= np.maximum(REL * ref["cell_e"], ABS))
