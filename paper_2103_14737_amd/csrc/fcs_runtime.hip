@@ -1271,9 +1271,12 @@ int prepare(fcs_ctx* c, const fcs_sim_options* o, const Tuning& tu, const Shape&
 // LDS bytes of the geometry records the hit kernels stage
 size_t geo_lds_bytes(const Params& P) { return (size_t)(3 * P.n_layers + 2 * P.n_layers * P.n_regions) * 16; }
 
-// Enqueue the launch sequence of one batch on c->stream.  All kernels read
-// the device Params block, so a sequence can be captured once and replayed.
-// part: 0 = everything, 1 = up to the work queue, 2 = the hit kernel,
+// Enqueue the launch sequence of one batch on c->stream (the window pass
+// may fork onto win_stream and join back within the same part).  All
+// kernels read the device Params block, so a sequence can be captured once
+// and replayed.  part: 0 = everything, 1 = the setup pass (with the task
+// scans unless they run beside the window pass), 2 = the hit step: window
+// pass and hit kernel (with the scans beside the window pass when it forks),
 // 3 = compaction and reset.
 enum Part { kAll = 0, kPre = 1, kHits = 2, kPost = 3 };
 // where the cell energies go: the private accumulator (compacted, then
@@ -1375,7 +1378,8 @@ int counters_error(fcs_ctx* c, const Counters& k)
 }
 
 // GPU time of a profiled synchronous launch sequence in its three parts:
-// setup and scans, the hit step (window pass and hit kernel), compaction
+// setup (and scans), the hit step (window pass and hit kernel, with the
+// scans when the window pass runs beside them), compaction
 struct PhaseMs {
     double setup = 0.0, hits = 0.0, compact = 0.0;
 };
